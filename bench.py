@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput of the half-range lattice Boltzmann Couette step on one MI355X.
+
+A step is one full SSP-RK3 step (three stages: WENO-5 advection with diffuse walls, Shakhov
+collision, stage update, FP64 moments) of every instance of the workload.  The default workload is
+the ragged batch of 512 Couette instances drawn with seed 0 (delta = 10^U(-2,2), u_w ~ U(0.01,0.5),
+omega ~ U(0.5,1), Nx in {64..1024}, Qx in {4,8,16,32}, Qy in {4,8,12}, tanh stretching A = 0.9),
+with FP32 populations (stochastic rounding) and FP64 moments, advanced by shared launches.
+
+Prints one JSON line.  --gpus above 1 is refused: this solver runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+WORKLOADS = {
+    "couette_batch512_ragged_fp32": dict(kind="batch", precision=1, rounding=1),
+    "couette_batch512_ragged_fp64": dict(kind="batch", precision=0, rounding=0),
+    "couette_nx512_q16x8_fp64": dict(kind="single", name="couette_nx512_q16x8", precision=0, rounding=0),
+    "couette_nx512_q16x8_fp32": dict(kind="single", name="couette_nx512_q16x8", precision=1, rounding=1),
+    "couette_nx2048_q80x20_fp32": dict(kind="single", name="couette_nx2048_q80x20", precision=1, rounding=1),
+    "couette_nx2048_q80x20_fp64": dict(kind="single", name="couette_nx2048_q80x20", precision=0, rounding=0),
+}
+
+
+def _instances(spec):
+    from hrlb_inputs import batch_draws, case
+
+    if spec["kind"] == "batch":
+        return batch_draws(512, seed=0)
+    d = case(spec["name"])
+    d["seed"] = 12345
+    return [d]
+
+
+def _build(spec, insts):
+    from paper_1810_07803_amd import hrlb
+
+    quads, cases = {}, []
+    for d in insts:
+        key = (d["Qx"], d["Qy"])
+        if key not in quads:
+            quads[key] = hrlb.Quadrature(d["Qx"], d["Qy"])
+        p = hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
+                             Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
+                             precision=spec["precision"], rounding=spec["rounding"], seed=d.get("seed", 0))
+        cases.append(hrlb.Case(quads[key], p))
+    return quads, cases, hrlb.Batch(cases)
+
+
+def _cpu_baseline(insts, budget_s: float):
+    """The oracle as it stands, on a bounded sample of the same workload (host cores, OpenMP)."""
+    from oracle.oracle import OracleProblem, num_threads
+
+    sample = insts[: min(len(insts), 6)]
+    probs = []
+    for d in sample:
+        probs.append(OracleProblem(d["Qx"], d["Qy"], d["ncell"], stretch_A=d["stretch_A"], delta=d["delta"],
+                                   uw=d["uw"], omega=d["omega"]))
+    # one calibration step each, then as many steps as fit in the budget
+    t0 = time.perf_counter()
+    states = []
+    for p in probs:
+        phi, chi = p.init_state()
+        p.step(phi, chi, 1)
+        states.append((phi, chi))
+    t_cal = time.perf_counter() - t0
+    steps = max(1, int(budget_s / max(t_cal, 1e-3)))
+    t0 = time.perf_counter()
+    units = 0
+    for p, (phi, chi) in zip(probs, states):
+        p.step(phi, chi, steps)
+        units += p.nv * p.ncell * steps
+    dt = time.perf_counter() - t0
+    return {"value": units / dt, "unit": "cell·velocity updates/s", "cores": num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, first {len(sample)} instances of the workload, {steps} steps each "
+                      f"({units} cell·velocity updates in {dt:.1f} s)"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="couette_batch512_ragged_fp32", choices=sorted(WORKLOADS))
+    ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not supported "
+              "(independent instances would shard by instance, see the design notes)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    spec = WORKLOADS[args.workload]
+    insts = _instances(spec)
+    print(f"# building {len(insts)} instance(s) of {args.workload}", file=sys.stderr, flush=True)
+    quads, cases, batch = _build(spec, insts)
+    units = sum(c.nv * c.ncell for c in cases)
+    stream = torch.cuda.current_stream()
+
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    print(f"# warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    batch.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = units / (ms_per_step * 1e-3)
+
+    stage_ms, cell_ms = batch.profile(args.profile_steps)
+    es = 4 if spec["precision"] == 1 else 8
+    # algorithmic bytes per stage launch: read f_in and write f_out (both dists) in every stage,
+    # plus f^n in stages 2 and 3: (2 + 3 + 3)/3 passes of 2 dists per unit on average
+    bytes_per_unit = es * 2 * (2 + 3 + 3) / 3.0
+    achieved = units * bytes_per_unit / (stage_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "stage_kernel<%s>" % ("float" if es == 4 else "double"),
+                "kernel_ms": round(stage_ms, 4), "cell_kernel_ms": round(cell_ms, 4),
+                "bytes_per_unit_per_launch": bytes_per_unit, "units_per_launch": units}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cpu = _cpu_baseline(insts, args.cpu_seconds)
+
+    out = {
+        "metric": "cell·velocity updates/s",
+        "value": value,
+        "unit": "cell·velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if es == 4 else "f64",
+        "moments_dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "instances": len(cases), "units_per_step": units,
+                   "parallelism": "single GPU, instances batched per launch"},
+        "wall_s_timed": wall,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,160 @@
+/*
+ * hrlb.h -- C ABI of the MI355X half-range lattice Boltzmann solver for planar Couette flow
+ * (Ambrus, Sharipov, Sofonea, arXiv:1810.07803).
+ *
+ * The library advances the reduced Shakhov equations (Sec. II, equation boltz_red) for the two
+ * reduced distributions phi and chi on a mixed velocity set HHLB(Nx;Qx) x HLB(Ny;Qy)
+ * (Sec. III): half-range Gauss-Hermite on the wall-normal axis p_x, full-range Gauss-Hermite on
+ * p_y.  Space: WENO-5 finite differences on the stretched grid of equation (stretch), extended
+ * to the full channel x in [-1/2, 1/2].  Time: third-order TVD (SSP) Runge-Kutta.  Walls: diffuse
+ * reflection, equations (diffuse) and (diffuse_nw); the left wall moves with -u_w, the right
+ * one with +u_w, both at T_w.
+ *
+ * Units: m = K_B = L = 1, average density n_ref = 1, reference momentum p0 = 1.  With these,
+ * the relaxation time of equation (tau) with mu ~ T^omega is
+ *     tau = (T/T_w)^(omega-1) / (n delta sqrt(2)) / sqrt(T_w).
+ *
+ * Velocity ordering (also used by every host array below):
+ *     v = (h*Qx + i)*Qy + j,  p_x = +z_i (h = 0) or -z_i (h = 1),  p_y = y_j ascending,
+ * where z_i are the positive half-range nodes (ascending) and y_j the full-range nodes.
+ * Host population arrays are [2][Nv][n_cells] doubles: phi first, then chi, cells contiguous.
+ *
+ * Conventions for every call:
+ *   - No exception crosses the ABI.  Every call returns an hrlb_status; negative values are
+ *     errors, HRLB_NOT_CONVERGED (positive) leaves the case valid.  hrlb_last_error() returns
+ *     a thread-local message describing the last failure on the calling thread.
+ *   - The caller owns every buffer it passes in (host arrays, the device workspace and the
+ *     stream).  The library never frees caller memory.  Objects returned through "out"
+ *     pointers are owned by the library and released by the matching hrlb_free_* call.
+ *   - A case is bound to the stream given at creation and is not thread-safe; calls on one case
+ *     must not overlap.  Different cases may be used from different threads.
+ *   - Device work is enqueued asynchronously on the case's stream unless stated otherwise.
+ */
+#ifndef HRLB_H
+#define HRLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HRLB_OK = 0,
+    HRLB_NOT_CONVERGED = 1, /* run_to_steady hit max_steps; state valid and readable     */
+    HRLB_E_INVALID = -1,    /* an argument is out of range or inconsistent             */
+    HRLB_E_NOMEM = -2,      /* workspace too small, or host allocation failed          */
+    HRLB_E_DEVICE = -3,     /* a HIP runtime call failed                               */
+    HRLB_E_DIVERGED = -4    /* NaN/Inf in the residual; the state is not meaningful      */
+} hrlb_status;
+
+enum { HRLB_FP64 = 0, HRLB_FP32_STORE_FP64_MOM = 1 };
+enum { HRLB_ROUND_NEAREST = 0, HRLB_ROUND_STOCHASTIC = 1 };
+enum { HRLB_STOP_RESIDUAL = 0, HRLB_STOP_PXY = 1 };
+
+typedef struct hrlb_quad hrlb_quad;   /* immutable velocity set; may be shared by many cases */
+typedef struct hrlb_case hrlb_case;   /* one Couette problem resident in a device workspace */
+typedef struct hrlb_batch hrlb_batch; /* several cases advanced by the same kernel launches */
+
+/* Velocity set HHLB(Nx_order;Qx) x HLB(Ny_order;Qy) (Sec. III, model naming after eq. gy).
+ * Qx: half-range order (nodes per semi-axis), 3 <= Qx <= 128; Qy: full-range order, 3..64.
+ * Nx_order, Ny_order: expansion orders of the equilibrium truncations (eq. gx and eq. gy),
+ * 2 <= Nx_order <= min(Qx-1, 16), 2 <= Ny_order <= Qy-1.  p0 must be 1 (the units above).
+ * Host-only: computes the nodes and weights in extended precision, no device work.
+ * *out receives a library-owned object; release with hrlb_free_quadrature after every case
+ * using it has been freed. */
+hrlb_status hrlb_init_quadrature(int Qx, int Nx_order, int Qy, int Ny_order, double p0, hrlb_quad **out);
+
+/* Copies the velocity set to caller host buffers: px, wx [2*Qx] (p_x values and half-range
+ * weights in h-major order), py, wy [Qy].  Any pointer may be NULL. */
+hrlb_status hrlb_quadrature_nodes(const hrlb_quad *q, double *px, double *wx, double *py, double *wy);
+
+typedef struct {
+    double delta;     /* rarefaction parameter, eq. (delta); 0 selects collisionless flow      */
+    double u_w;       /* wall speed along y (left wall -u_w, right wall +u_w), |u_w| <= 2     */
+    double T_w;       /* wall temperature (> 0); the units assume T_w = 1 but any value works  */
+    double Pr;        /* Prandtl number of the Shakhov model, > 0                             */
+    double omega;     /* viscosity index of eq. (mu): mu ~ T^omega                             */
+    int n_cells;      /* cells across the full channel: multiple of 4, 8 <= n_cells <= 65536  */
+    double stretch_A; /* grid stretching of eq. (stretch), 0 <= A < 1 (0 = uniform)           */
+    int precision;    /* HRLB_FP64 or HRLB_FP32_STORE_FP64_MOM                                 */
+    int rounding;     /* FP32 storage only: HRLB_ROUND_NEAREST or HRLB_ROUND_STOCHASTIC        */
+    double cfl;       /* used when dt <= 0: dt = min(cfl min(J deta)/max|p_x|, tau_w/2)       */
+    double dt;        /* time step; <= 0 selects the rule above                               */
+    unsigned seed;    /* key of the counter-based generator used by stochastic rounding       */
+} hrlb_case_params;
+
+/* Device workspace size (bytes) needed by a case with these parameters. */
+hrlb_status hrlb_case_workspace_bytes(const hrlb_quad *q, const hrlb_case_params *p, size_t *bytes);
+
+/* Creates a case inside the caller's device workspace (at least the size reported above,
+ * 256-byte aligned) on the caller's HIP stream (hipStream_t passed as void*, NULL = default
+ * stream).  The state starts at the rest equilibrium n = 1, u = 0, T = T_w.  The workspace
+ * must stay allocated and untouched until hrlb_free_case.  Enqueues uploads on the stream. */
+hrlb_status hrlb_init_case(const hrlb_quad *q, const hrlb_case_params *p, void *dev_workspace,
+                           size_t ws_bytes, void *hip_stream, hrlb_case **out);
+
+/* Enqueues n_steps >= 0 full SSP-RK3 steps (three stages each) on the case's stream. */
+hrlb_status hrlb_step(hrlb_case *c, long n_steps);
+
+typedef struct {
+    long steps;        /* steps taken by this call                                          */
+    double residual;   /* last residual: ||f_new - f_old||/(dt ||f_old||), J-weighted L2     */
+    double pxy_drift;  /* last |dPxy_mean/dt| / |Pxy_mean| over one check window             */
+    double sim_time;   /* total simulated time of the case                                   */
+    double wall_s;     /* wall-clock seconds spent in this call                              */
+    double mass_drift; /* (mass - initial mass)/initial mass, mass = sum_s J_s deta n_s      */
+} hrlb_steady_info;
+
+/* Runs blocks of check_every steps until the stop criterion drops below tol
+ * (HRLB_STOP_RESIDUAL: the residual above; HRLB_STOP_PXY: the relative drift rate of the
+ * J-weighted mean P_xy between checks), NaN/Inf appears (HRLB_E_DIVERGED) or max_steps is
+ * reached (HRLB_NOT_CONVERGED).  Synchronous: returns when the decision is made. */
+hrlb_status hrlb_run_to_steady(hrlb_case *c, double tol, long max_steps, int check_every, int stop_rule,
+                               hrlb_steady_info *info);
+
+/* Synchronous copy of the current macroscopic state to caller host buffers:
+ *   fields [10][n_cells]: n, u_x, u_y, T, P_xx, P_xy, P_yy, T_zz, q_x, q_y (moment definitions
+ *                         of Sec. II, accumulated in FP64 for both precisions),
+ *   x [n_cells]: cell centres,  Pi: equation (Pi) with the J-weighted channel mean of P_xy,
+ *   wall_shear [2]: y-momentum flux sum_v p_x p_y F through the left and right wall faces.
+ * Any pointer may be NULL. */
+hrlb_status hrlb_moments(hrlb_case *c, double *fields, double *x, double *Pi, double *wall_shear);
+
+/* Synchronous copies of the populations to/from host [2][Nv][n_cells] doubles (phi, chi).
+ * set_state rounds to the storage precision and recomputes the moments; it is how a caller
+ * resumes from a checkpoint or starts from a given state. */
+hrlb_status hrlb_get_state(hrlb_case *c, double *host_state);
+hrlb_status hrlb_set_state(hrlb_case *c, const double *host_state);
+
+/* Time step in use and the number of velocities / cells of the case. */
+hrlb_status hrlb_case_info(const hrlb_case *c, double *dt, int *n_vel, int *n_cells, long *steps_done);
+
+void hrlb_free_case(hrlb_case *c);
+void hrlb_free_quadrature(hrlb_quad *q);
+const char *hrlb_last_error(void);
+
+/* ---- batching: several cases, possibly of different sizes and velocity sets, advanced by the
+ * same kernel launches (one persistent launch per stage for the whole batch).  Each case keeps
+ * its own workspace and results; a case's numbers are the same alone and in any batch.  All
+ * cases must share one stream and one precision.  The batch needs its own device workspace for
+ * descriptors and the tile list. */
+hrlb_status hrlb_batch_workspace_bytes(hrlb_case *const *cases, int n_cases, size_t *bytes);
+hrlb_status hrlb_batch_create(hrlb_case *const *cases, int n_cases, void *dev_workspace, size_t ws_bytes,
+                              hrlb_batch **out);
+/* Enqueues n_steps steps for every case of the batch; if check is nonzero the last step also
+ * computes each case's residual and P_xy mean (read them with hrlb_batch_poll). */
+hrlb_status hrlb_batch_step(hrlb_batch *b, long n_steps, int check);
+/* Synchronous: residual[i], pxy_mean[i] of case i from the last checked step (NULL allowed). */
+hrlb_status hrlb_batch_poll(hrlb_batch *b, double *residual, double *pxy_mean);
+void hrlb_batch_free(hrlb_batch *b);
+
+/* Profiling: runs n_steps steps of the batch like hrlb_batch_step, with a HIP event pair recorded
+ * on the batch's stream around every kernel launch, then waits and returns the mean duration (ms)
+ * of one launch of the stage kernel and of the per-cell kernel.  Synchronous. */
+hrlb_status hrlb_batch_profile(hrlb_batch *b, long n_steps, double *stage_kernel_ms, double *cell_kernel_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HRLB_H */

@@ -1,0 +1,814 @@
+// hrlb_host.cpp -- host runtime behind include/hrlb.h: velocity sets, case set-up inside a
+// caller-owned device workspace, launch sequences of the SSP-RK3 step, steady-state loop,
+// read-back, and batches of cases advanced by shared launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hrlb.h"
+#include "hrlb_internal.h"
+#include "hrlb_quadrature.h"
+
+using namespace hrlb;
+
+extern "C" hipError_t hrlbk_stage(int fp32, const InstDesc* descs, const TileRef* tiles, int ntiles, int grid,
+                                  int stage, int flags, hipStream_t st);
+extern "C" hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int flags,
+                                 hipStream_t st);
+extern "C" hipError_t hrlbk_finalize(const InstDesc* descs, int ninst, int with_res, hipStream_t st);
+extern "C" hipError_t hrlbk_init(int fp32, const InstDesc* descs, int inst, size_t units, hipStream_t st);
+
+namespace {
+
+enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2 };
+
+thread_local std::string g_err;
+
+hrlb_status fail(hrlb_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(HRLB_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+struct hrlb_quad {
+    int qx, nxo, qy, nyo;
+    std::vector<double> zx, wx;        // [qx] positive nodes, weights
+    std::vector<double> px, wx2;       // [2qx] h-major
+    std::vector<double> zy, wy;        // [qy]
+    std::vector<double> hz;            // [(nxo+1)][qx]
+    std::vector<double> auxZ, auxW;    // [kAux]
+    std::vector<double> hZ;            // [(nxo+1)][kAux]
+    std::vector<double> he;            // [(nyo+1)][qy]
+};
+
+struct Layout {
+    size_t desc, dyn, tables, f[3], cell, fields, mom, wall, res, tiles, cells, total;
+    // table offsets in doubles relative to `tables`
+    size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
+    int ngroups, nctiles, vpt, ncellblocks;
+};
+
+struct hrlb_case {
+    hrlb_case_params p;
+    const hrlb_quad* q;
+    char* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    Layout L;
+    InstDesc desc;  // host copy of the device descriptor
+    InstDesc* d_desc;
+    TileRef* d_tiles;
+    CellRef* d_cells;
+    int ntiles;
+    int nv;
+    double dt;
+    long steps_done;
+    double mass0;
+    std::vector<double> x, jdeta;
+    double pxy_prev;
+    bool has_prev_pxy;
+};
+
+struct hrlb_batch {
+    std::vector<hrlb_case*> cases;
+    InstDesc* d_descs;
+    TileRef* d_tiles;
+    CellRef* d_cells;
+    int ntiles, ncellblocks;
+    int fp32;
+    hipStream_t stream;
+};
+
+// ------------------------------------------------------------------------------------------------
+// velocity set
+extern "C" hrlb_status hrlb_init_quadrature(int Qx, int Nx_order, int Qy, int Ny_order, double p0, hrlb_quad** out)
+{
+    if (!out) return fail(HRLB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (Qx < 3 || Qx > kMaxQx) return fail(HRLB_E_INVALID, "Qx=%d outside [3,%d]", Qx, kMaxQx);
+    if (Qy < 3 || Qy > kMaxQy) return fail(HRLB_E_INVALID, "Qy=%d outside [3,%d]", Qy, kMaxQy);
+    if (Nx_order < 2 || Nx_order > Qx - 1 || Nx_order > kMaxNx)
+        return fail(HRLB_E_INVALID, "Nx_order=%d outside [2, min(Qx-1,%d)]", Nx_order, kMaxNx);
+    if (Ny_order < 2 || Ny_order > Qy - 1) return fail(HRLB_E_INVALID, "Ny_order=%d outside [2, Qy-1]", Ny_order);
+    if (p0 != 1.0) return fail(HRLB_E_INVALID, "p0 must be 1 (nondimensional units)");
+    hrlb_quad* q = new (std::nothrow) hrlb_quad;
+    if (!q) return fail(HRLB_E_NOMEM, "host allocation failed");
+    q->qx = Qx;
+    q->nxo = Nx_order;
+    q->qy = Qy;
+    q->nyo = Ny_order;
+    const int nrec = std::max(Qx, kAux) + 1;
+    Recurrence hr = half_range_recurrence(nrec);
+    std::vector<long double> nodes, weights;
+    gauss_from_recurrence(hr, Qx, nodes, weights);
+    q->zx.resize(Qx);
+    q->wx.resize(Qx);
+    for (int i = 0; i < Qx; ++i) {
+        q->zx[i] = (double)nodes[i];
+        q->wx[i] = (double)weights[i];
+    }
+    q->px.resize(2 * Qx);
+    q->wx2.resize(2 * Qx);
+    for (int i = 0; i < Qx; ++i) {
+        q->px[i] = q->zx[i];
+        q->px[Qx + i] = -q->zx[i];
+        q->wx2[i] = q->wx2[Qx + i] = q->wx[i];
+    }
+    std::vector<long double> hv(nrec + 1);
+    q->hz.assign((size_t)(Nx_order + 1) * Qx, 0.0);
+    for (int i = 0; i < Qx; ++i) {
+        orthonormal_values(hr, Nx_order, nodes[i], hv.data());
+        for (int l = 0; l <= Nx_order; ++l) q->hz[(size_t)l * Qx + i] = (double)hv[l];
+    }
+    std::vector<long double> an, aw;
+    gauss_from_recurrence(hr, kAux, an, aw);
+    q->auxZ.resize(kAux);
+    q->auxW.resize(kAux);
+    q->hZ.assign((size_t)(Nx_order + 1) * kAux, 0.0);
+    for (int k = 0; k < kAux; ++k) {
+        q->auxZ[k] = (double)an[k];
+        q->auxW[k] = (double)aw[k];
+        orthonormal_values(hr, Nx_order, an[k], hv.data());
+        for (int l = 0; l <= Nx_order; ++l) q->hZ[(size_t)l * kAux + k] = (double)hv[l];
+    }
+    Recurrence fr = hermite_recurrence(Qy + 1);
+    std::vector<long double> yn, yw;
+    gauss_from_recurrence(fr, Qy, yn, yw);
+    q->zy.resize(Qy);
+    q->wy.resize(Qy);
+    q->he.assign((size_t)(Ny_order + 1) * Qy, 0.0);
+    for (int j = 0; j < Qy; ++j) {
+        q->zy[j] = (double)yn[j];
+        q->wy[j] = (double)yw[j];
+        long double prev = 0.0L, cur = 1.0L;
+        for (int l = 0; l <= Ny_order; ++l) {
+            q->he[(size_t)l * Qy + j] = (double)cur;
+            const long double nx = yn[j] * cur - l * prev;
+            prev = cur;
+            cur = nx;
+        }
+    }
+    *out = q;
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_quadrature_nodes(const hrlb_quad* q, double* px, double* wx, double* py, double* wy)
+{
+    if (!q) return fail(HRLB_E_INVALID, "quadrature is NULL");
+    if (px) std::copy(q->px.begin(), q->px.end(), px);
+    if (wx) std::copy(q->wx2.begin(), q->wx2.end(), wx);
+    if (py) std::copy(q->zy.begin(), q->zy.end(), py);
+    if (wy) std::copy(q->wy.begin(), q->wy.end(), wy);
+    return HRLB_OK;
+}
+
+extern "C" void hrlb_free_quadrature(hrlb_quad* q) { delete q; }
+
+extern "C" const char* hrlb_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------------------------------------
+// case set-up
+namespace {
+
+hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
+{
+    if (!q || !p) return fail(HRLB_E_INVALID, "NULL quadrature or parameters");
+    if (!(p->delta >= 0.0) || !std::isfinite(p->delta)) return fail(HRLB_E_INVALID, "delta must be >= 0");
+    if (!(p->T_w > 0.0) || !std::isfinite(p->T_w)) return fail(HRLB_E_INVALID, "T_w must be > 0");
+    if (!(p->Pr > 0.0) || !std::isfinite(p->Pr)) return fail(HRLB_E_INVALID, "Pr must be > 0");
+    if (!std::isfinite(p->u_w) || std::fabs(p->u_w) > 2.0) return fail(HRLB_E_INVALID, "|u_w| must be <= 2");
+    if (!std::isfinite(p->omega) || p->omega < 0.0 || p->omega > 2.0) return fail(HRLB_E_INVALID, "omega outside [0,2]");
+    if (p->n_cells < 8 || p->n_cells > 65536 || p->n_cells % 4 != 0)
+        return fail(HRLB_E_INVALID, "n_cells=%d must be a multiple of 4 in [8, 65536]", p->n_cells);
+    if (!(p->stretch_A >= 0.0 && p->stretch_A < 1.0)) return fail(HRLB_E_INVALID, "stretch_A outside [0,1)");
+    if (p->precision != HRLB_FP64 && p->precision != HRLB_FP32_STORE_FP64_MOM)
+        return fail(HRLB_E_INVALID, "unknown precision %d", p->precision);
+    if (p->rounding != HRLB_ROUND_NEAREST && p->rounding != HRLB_ROUND_STOCHASTIC)
+        return fail(HRLB_E_INVALID, "unknown rounding %d", p->rounding);
+    if (p->dt <= 0.0 && !(p->cfl > 0.0 && p->cfl <= 2.0)) return fail(HRLB_E_INVALID, "cfl must be in (0,2] when dt <= 0");
+    if (!std::isfinite(p->dt)) return fail(HRLB_E_INVALID, "dt not finite");
+    return HRLB_OK;
+}
+
+// velocities per row: largest divisor of qy not above 8 that still fills the 16 rows of a group
+int choose_vpt(int qx, int qy)
+{
+    const int nv = 2 * qx * qy;
+    int best = 1;
+    for (int d = 1; d <= std::min(qy, 8); ++d)
+        if (qy % d == 0 && nv / d >= kRows) best = d;
+    return best;
+}
+
+Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
+{
+    Layout L{};
+    const int nx = p->n_cells, qx = q->qx, qy = q->qy, nv = 2 * qx * qy;
+    const size_t es = p->precision == HRLB_FP64 ? 8 : 4;
+    L.vpt = choose_vpt(qx, qy);
+    const int nseg = nv / L.vpt;
+    L.ngroups = (nseg + kRows - 1) / kRows;
+    L.nctiles = (nx + kTileCells - 1) / kTileCells;
+    L.ncellblocks = (nx + kCellBlock - 1) / kCellBlock;
+    size_t off = 0;
+    L.desc = off;
+    off = align256(off + sizeof(InstDesc));
+    L.dyn = off;
+    off = align256(off + sizeof(double) * kNDyn);
+    L.tables = off;
+    size_t t = 0;
+    L.t_px = t; t += 2 * qx;
+    L.t_py = t; t += qy;
+    L.t_wx = t; t += qx;
+    L.t_wy = t; t += qy;
+    L.t_hz = t; t += (size_t)(q->nxo + 1) * qx;
+    L.t_az = t; t += kAux;
+    L.t_aw = t; t += kAux;
+    L.t_hZ = t; t += (size_t)(q->nxo + 1) * kAux;
+    L.t_he = t; t += (size_t)(q->nyo + 1) * qy;
+    L.t_ijd = t; t += nx;
+    L.t_jd = t; t += nx;
+    L.t_gwl = t; t += nv;
+    L.t_gwr = t; t += nv;
+    L.t_g0 = t; t += nv;
+    L.t_n = t;
+    off = align256(off + sizeof(double) * t);
+    for (int k = 0; k < 3; ++k) {
+        L.f[k] = off;
+        off = align256(off + es * 2 * (size_t)nv * nx);
+    }
+    L.cell = off;
+    off = align256(off + es * (size_t)(kNSc + 2 * qx + qy) * nx);
+    L.fields = off;
+    off = align256(off + sizeof(double) * kNFields * nx);
+    L.mom = off;
+    off = align256(off + sizeof(double) * (size_t)L.ngroups * kNMom * nx);
+    L.wall = off;
+    off = align256(off + sizeof(double) * L.ngroups * 4);
+    L.res = off;
+    off = align256(off + sizeof(double) * (size_t)L.nctiles * L.ngroups * 2);
+    L.tiles = off;
+    off = align256(off + sizeof(TileRef) * (size_t)L.nctiles * L.ngroups);
+    L.cells = off;
+    off = align256(off + sizeof(CellRef) * L.ncellblocks);
+    L.total = off;
+    return L;
+}
+
+void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<double>& jdeta)
+{
+    const int N = p->n_cells;
+    x.resize(N);
+    jdeta.resize(N);
+    if (p->stretch_A == 0.0) {
+        for (int s = 0; s < N; ++s) {
+            x[s] = -0.5 + (s + 0.5) / N;
+            jdeta[s] = 1.0 / N;
+        }
+    } else {
+        const double A = p->stretch_A, emax = std::atanh(A), de = 2.0 * emax / N;
+        for (int s = 0; s < N; ++s) {
+            const double eta = -emax + (s + 0.5) * de;
+            const double c = std::cosh(eta);
+            x[s] = std::tanh(eta) / (2.0 * A);
+            jdeta[s] = de / (2.0 * A * c * c);
+        }
+    }
+}
+
+int stage_grid(int ntiles) { return std::min(ntiles, 4096); }
+
+hrlb_status enqueue_steps(int fp32, const InstDesc* descs, int ninst, const TileRef* tiles, int ntiles,
+                          const CellRef* cells, int ncellblocks, long n_steps, bool check_last, hipStream_t st)
+{
+    const int grid = stage_grid(ntiles);
+    for (long s = 0; s < n_steps; ++s) {
+        const bool chk = check_last && s + 1 == n_steps;
+        for (int stage = 0; stage < 3; ++stage) {
+            const int fl = (stage == 2 && chk) ? FLAG_RESID : 0;
+            HIP_TRY(hrlbk_stage(fp32, descs, tiles, ntiles, grid, stage, fl, st));
+            HIP_TRY(hrlbk_cell(fp32, descs, cells, ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, st));
+        }
+        if (chk) HIP_TRY(hrlbk_finalize(descs, ninst, 1, st));
+    }
+    return HRLB_OK;
+}
+
+hrlb_status analyze_case(hrlb_case* c)
+{
+    const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
+    HIP_TRY(hrlbk_stage(fp32, c->d_desc, c->d_tiles, c->ntiles, stage_grid(c->ntiles), -1, 0, c->stream));
+    HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, c->stream));
+    HIP_TRY(hrlbk_finalize(c->d_desc, 1, 0, c->stream));
+    return HRLB_OK;
+}
+
+}  // namespace
+
+extern "C" hrlb_status hrlb_case_workspace_bytes(const hrlb_quad* q, const hrlb_case_params* p, size_t* bytes)
+{
+    hrlb_status st = validate(q, p);
+    if (st != HRLB_OK) return st;
+    if (!bytes) return fail(HRLB_E_INVALID, "bytes is NULL");
+    *bytes = make_layout(q, p).total;
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params* p, void* dev_workspace,
+                                      size_t ws_bytes, void* hip_stream, hrlb_case** out)
+{
+    if (!out) return fail(HRLB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hrlb_status st = validate(q, p);
+    if (st != HRLB_OK) return st;
+    if (!dev_workspace) return fail(HRLB_E_INVALID, "device workspace is NULL");
+    if (((uintptr_t)dev_workspace) & 255) return fail(HRLB_E_INVALID, "device workspace must be 256-byte aligned");
+    Layout L = make_layout(q, p);
+    if (ws_bytes < L.total)
+        return fail(HRLB_E_NOMEM, "workspace of %zu bytes < %zu required", ws_bytes, L.total);
+
+    hrlb_case* c = new (std::nothrow) hrlb_case;
+    if (!c) return fail(HRLB_E_NOMEM, "host allocation failed");
+    c->p = *p;
+    c->q = q;
+    c->ws = (char*)dev_workspace;
+    c->ws_bytes = ws_bytes;
+    c->stream = (hipStream_t)hip_stream;
+    c->L = L;
+    c->steps_done = 0;
+    c->has_prev_pxy = false;
+    c->pxy_prev = 0.0;
+    const int nx = p->n_cells, qx = q->qx, qy = q->qy, nv = 2 * qx * qy;
+    c->nv = nv;
+    grid_of(p, c->x, c->jdeta);
+
+    // host tables
+    std::vector<double> tab(L.t_n, 0.0);
+    std::copy(q->px.begin(), q->px.end(), tab.begin() + L.t_px);
+    std::copy(q->zy.begin(), q->zy.end(), tab.begin() + L.t_py);
+    std::copy(q->wx.begin(), q->wx.end(), tab.begin() + L.t_wx);
+    std::copy(q->wy.begin(), q->wy.end(), tab.begin() + L.t_wy);
+    std::copy(q->hz.begin(), q->hz.end(), tab.begin() + L.t_hz);
+    std::copy(q->auxZ.begin(), q->auxZ.end(), tab.begin() + L.t_az);
+    std::copy(q->auxW.begin(), q->auxW.end(), tab.begin() + L.t_aw);
+    std::copy(q->hZ.begin(), q->hZ.end(), tab.begin() + L.t_hZ);
+    std::copy(q->he.begin(), q->he.end(), tab.begin() + L.t_he);
+    for (int s = 0; s < nx; ++s) {
+        tab[L.t_ijd + s] = 1.0 / c->jdeta[s];
+        tab[L.t_jd + s] = c->jdeta[s];
+    }
+    std::vector<double> gxw(2 * qx), gyl(qy), gyr(qy), gy0(qy);
+    eval_gx(qx, q->nxo, q->wx.data(), q->hz.data(), q->auxZ.data(), q->auxW.data(), q->hZ.data(), 0.0, p->T_w,
+            gxw.data());
+    eval_gy(qy, q->nyo, q->wy.data(), q->he.data(), -p->u_w, p->T_w, gyl.data());
+    eval_gy(qy, q->nyo, q->wy.data(), q->he.data(), +p->u_w, p->T_w, gyr.data());
+    eval_gy(qy, q->nyo, q->wy.data(), q->he.data(), 0.0, p->T_w, gy0.data());
+    double den_l = 0, den_r = 0, mom_l = 0, mom_r = 0;
+    for (int v = 0; v < nv; ++v) {
+        const int hi = v / qy, j = v % qy;
+        tab[L.t_gwl + v] = gxw[hi] * gyl[j];
+        tab[L.t_gwr + v] = gxw[hi] * gyr[j];
+        tab[L.t_g0 + v] = gxw[hi] * gy0[j];
+        const double pxv = q->px[hi], pyv = q->zy[j];
+        if (pxv > 0) {  // enters through the left wall
+            den_l += pxv * tab[L.t_gwl + v];
+            mom_l += pxv * pyv * tab[L.t_gwl + v];
+        } else {        // enters through the right wall
+            den_r += pxv * tab[L.t_gwr + v];
+            mom_r += pxv * pyv * tab[L.t_gwr + v];
+        }
+    }
+
+    // time step
+    double dt = p->dt;
+    if (dt <= 0.0) {
+        double mind = 1e300;
+        for (int s = 0; s < nx; ++s) mind = std::min(mind, c->jdeta[s]);
+        double maxp = 0.0;
+        for (double z : q->zx) maxp = std::max(maxp, z);
+        dt = p->cfl * mind / maxp;
+        if (p->delta > 0.0) {
+            const double tau_w = 1.0 / (p->delta * std::sqrt(2.0)) / std::sqrt(p->T_w);
+            dt = std::min(dt, 0.5 * tau_w);
+        }
+    }
+    c->dt = dt;
+
+    // descriptor
+    InstDesc& D = c->desc;
+    std::memset(&D, 0, sizeof D);
+    D.nx = nx;
+    D.qx = qx;
+    D.qy = qy;
+    D.nv = nv;
+    D.nxo = q->nxo;
+    D.nyo = q->nyo;
+    D.vpt = L.vpt;
+    D.segs_per_line = qy / L.vpt;
+    D.nseg = nv / L.vpt;
+    D.ngroups = L.ngroups;
+    D.nctiles = L.nctiles;
+    D.precision = p->precision;
+    D.rounding = p->precision == HRLB_FP32_STORE_FP64_MOM ? p->rounding : 0;
+    D.collisionless = p->delta == 0.0;
+    D.seed = p->seed;
+    D.dt = dt;
+    D.Tw = p->T_w;
+    D.Pr = p->Pr;
+    D.omega = p->omega;
+    D.tau_pref = p->delta * std::sqrt(2.0) * std::sqrt(p->T_w);
+    D.den_l = den_l;
+    D.den_r = den_r;
+    D.mom_l = mom_l;
+    D.mom_r = mom_r;
+    char* ws = c->ws;
+    for (int k = 0; k < 3; ++k) D.f[k] = ws + L.f[k];
+    D.cell = ws + L.cell;
+    D.fields = (double*)(ws + L.fields);
+    D.mom_part = (double*)(ws + L.mom);
+    D.wall_part = (double*)(ws + L.wall);
+    D.res_part = (double*)(ws + L.res);
+    D.dyn = (double*)(ws + L.dyn);
+    const double* tb = (const double*)(ws + L.tables);
+    D.px = tb + L.t_px;
+    D.py = tb + L.t_py;
+    D.wx = tb + L.t_wx;
+    D.wy = tb + L.t_wy;
+    D.hz = tb + L.t_hz;
+    D.auxZ = tb + L.t_az;
+    D.auxW = tb + L.t_aw;
+    D.hZ = tb + L.t_hZ;
+    D.he = tb + L.t_he;
+    D.inv_jdeta = tb + L.t_ijd;
+    D.jdeta = tb + L.t_jd;
+    D.gw_l = tb + L.t_gwl;
+    D.gw_r = tb + L.t_gwr;
+    D.g0 = tb + L.t_g0;
+    c->d_desc = (InstDesc*)(ws + L.desc);
+    c->d_tiles = (TileRef*)(ws + L.tiles);
+    c->d_cells = (CellRef*)(ws + L.cells);
+
+    std::vector<TileRef> tiles;
+    for (int ct = 0; ct < L.nctiles; ++ct)
+        for (int g = 0; g < L.ngroups; ++g) tiles.push_back(TileRef{0, ct, g, ct * L.ngroups + g});
+    c->ntiles = (int)tiles.size();
+    std::vector<CellRef> cells;
+    for (int b = 0; b < L.ncellblocks; ++b) cells.push_back(CellRef{0, b * kCellBlock});
+    std::vector<double> dyn(kNDyn, 0.0);
+    dyn[DY_NWL] = dyn[DY_NWR] = 1.0;
+
+    hipError_t e = hipSuccess;
+    auto cp = [&](size_t off, const void* src, size_t n) {
+        if (e == hipSuccess) e = hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, c->stream);
+    };
+    cp(L.desc, &D, sizeof D);
+    cp(L.dyn, dyn.data(), sizeof(double) * kNDyn);
+    cp(L.tables, tab.data(), sizeof(double) * tab.size());
+    cp(L.tiles, tiles.data(), sizeof(TileRef) * tiles.size());
+    cp(L.cells, cells.data(), sizeof(CellRef) * cells.size());
+    if (e == hipSuccess) e = hrlbk_init(p->precision == HRLB_FP32_STORE_FP64_MOM, c->d_desc, 0, (size_t)nv * nx, c->stream);
+    if (e == hipSuccess) st = analyze_case(c);
+    // the host staging vectors above must outlive the enqueued copies: wait on every path
+    const hipError_t es = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess || es != hipSuccess || st != HRLB_OK) {
+        delete c;
+        if (st != HRLB_OK) return st;
+        return fail(HRLB_E_DEVICE, "case upload: %s", hipGetErrorString(e != hipSuccess ? e : es));
+    }
+    double mass = 0.0;
+    {
+        double dy[kNDyn];
+        e = hipMemcpy(dy, D.dyn, sizeof dy, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(HRLB_E_DEVICE, "case init read-back: %s", hipGetErrorString(e));
+        }
+        mass = dy[DY_MASS];
+    }
+    c->mass0 = mass;
+    *out = c;
+    return HRLB_OK;
+}
+
+extern "C" void hrlb_free_case(hrlb_case* c) { delete c; }
+
+extern "C" hrlb_status hrlb_case_info(const hrlb_case* c, double* dt, int* n_vel, int* n_cells, long* steps_done)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    if (dt) *dt = c->dt;
+    if (n_vel) *n_vel = c->nv;
+    if (n_cells) *n_cells = c->p.n_cells;
+    if (steps_done) *steps_done = c->steps_done;
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_step(hrlb_case* c, long n_steps)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
+    hrlb_status st = enqueue_steps(c->p.precision == HRLB_FP32_STORE_FP64_MOM, c->d_desc, 1, c->d_tiles, c->ntiles,
+                                   c->d_cells, c->L.ncellblocks, n_steps, false, c->stream);
+    if (st == HRLB_OK) c->steps_done += n_steps;
+    return st;
+}
+
+extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_steps, int check_every, int stop_rule,
+                                          hrlb_steady_info* info)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    if (check_every < 1 || max_steps < 0 || !(tol > 0.0)) return fail(HRLB_E_INVALID, "bad tol/max_steps/check_every");
+    if (stop_rule != HRLB_STOP_RESIDUAL && stop_rule != HRLB_STOP_PXY) return fail(HRLB_E_INVALID, "bad stop rule");
+    const auto t0 = std::chrono::steady_clock::now();
+    const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
+    long taken = 0;
+    double res = -1.0, drift = -1.0;
+    hrlb_status verdict = HRLB_NOT_CONVERGED;
+    double dy[kNDyn];
+    bool have_prev = false;
+    double pxy_prev = 0.0;
+    while (taken < max_steps) {
+        const long n = std::min<long>(check_every, max_steps - taken);
+        hrlb_status st = enqueue_steps(fp32, c->d_desc, 1, c->d_tiles, c->ntiles, c->d_cells, c->L.ncellblocks, n,
+                                       true, c->stream);
+        if (st != HRLB_OK) return st;
+        HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        taken += n;
+        c->steps_done += n;
+        res = std::sqrt(dy[DY_RES_NUM]) / (c->dt * std::sqrt(dy[DY_RES_DEN]));
+        const double pxy = dy[DY_PXY_MEAN];
+        if (!std::isfinite(res) || !std::isfinite(pxy) || dy[DY_FLAGS] != 0.0) {
+            verdict = HRLB_E_DIVERGED;
+            fail(HRLB_E_DIVERGED, "non-finite residual after %ld steps", c->steps_done);
+            break;
+        }
+        if (have_prev) drift = std::fabs(pxy - pxy_prev) / (n * c->dt * std::max(std::fabs(pxy), 1e-300));
+        have_prev = true;
+        pxy_prev = pxy;
+        const double crit = stop_rule == HRLB_STOP_RESIDUAL ? res : drift;
+        if (crit >= 0.0 && crit < tol) {
+            verdict = HRLB_OK;
+            break;
+        }
+    }
+    if (info) {
+        info->steps = taken;
+        info->residual = res;
+        info->pxy_drift = drift;
+        info->sim_time = c->steps_done * c->dt;
+        info->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->mass_drift = taken > 0 ? (dy[DY_MASS] - c->mass0) / c->mass0 : 0.0;
+    }
+    return verdict;
+}
+
+extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, double* Pi, double* wall_shear)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    const int nx = c->p.n_cells;
+    std::vector<double> f((size_t)kNFields * nx);
+    double dy[kNDyn];
+    HIP_TRY(hipMemcpyAsync(f.data(), c->desc.fields, sizeof(double) * f.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (fields) std::copy(f.begin(), f.end(), fields);
+    if (x) std::copy(c->x.begin(), c->x.end(), x);
+    if (Pi) {
+        double num = 0, den = 0;
+        for (int s = 0; s < nx; ++s) {
+            num += c->jdeta[s] * f[(size_t)F_PXY * nx + s];
+            den += c->jdeta[s];
+        }
+        const double pxy = num / den;
+        const double vref = std::sqrt(c->p.T_w), pref = c->p.T_w;
+        *Pi = c->p.u_w != 0.0 ? -pxy * vref / (pref * c->p.u_w * std::sqrt(2.0)) : 0.0;
+    }
+    if (wall_shear) {
+        wall_shear[0] = dy[DY_SHEAR_L];
+        wall_shear[1] = dy[DY_SHEAR_R];
+    }
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_get_state(hrlb_case* c, double* host_state)
+{
+    if (!c || !host_state) return fail(HRLB_E_INVALID, "NULL argument");
+    const size_t n = 2 * (size_t)c->nv * c->p.n_cells;
+    if (c->p.precision == HRLB_FP64) {
+        HIP_TRY(hipMemcpyAsync(host_state, c->desc.f[0], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(n);
+        HIP_TRY(hipMemcpyAsync(tmp.data(), c->desc.f[0], sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (size_t k = 0; k < n; ++k) host_state[k] = tmp[k];
+    }
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_set_state(hrlb_case* c, const double* host_state)
+{
+    if (!c || !host_state) return fail(HRLB_E_INVALID, "NULL argument");
+    const size_t n = 2 * (size_t)c->nv * c->p.n_cells;
+    for (size_t k = 0; k < n; ++k)
+        if (!std::isfinite(host_state[k])) return fail(HRLB_E_INVALID, "state holds a non-finite value at %zu", k);
+    if (c->p.precision == HRLB_FP64) {
+        HIP_TRY(hipMemcpyAsync(c->desc.f[0], host_state, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(n);
+        for (size_t k = 0; k < n; ++k) tmp[k] = (float)host_state[k];
+        HIP_TRY(hipMemcpyAsync(c->desc.f[0], tmp.data(), sizeof(float) * n, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    hrlb_status st = analyze_case(c);
+    if (st != HRLB_OK) return st;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return HRLB_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// batches
+namespace {
+struct BatchLayout {
+    size_t descs, tiles, cells, total;
+    int ntiles, ncellblocks;
+};
+
+hrlb_status batch_layout(hrlb_case* const* cases, int n, BatchLayout* B)
+{
+    if (!cases || n < 1) return fail(HRLB_E_INVALID, "empty batch");
+    int nt = 0, nc = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!cases[i]) return fail(HRLB_E_INVALID, "case %d is NULL", i);
+        if (cases[i]->p.precision != cases[0]->p.precision) return fail(HRLB_E_INVALID, "mixed precisions in a batch");
+        if (cases[i]->stream != cases[0]->stream) return fail(HRLB_E_INVALID, "cases of a batch must share a stream");
+        nt += cases[i]->ntiles;
+        nc += cases[i]->L.ncellblocks;
+    }
+    size_t off = 0;
+    B->descs = off;
+    off = align256(off + sizeof(InstDesc) * n);
+    B->tiles = off;
+    off = align256(off + sizeof(TileRef) * nt);
+    B->cells = off;
+    off = align256(off + sizeof(CellRef) * nc);
+    B->total = off;
+    B->ntiles = nt;
+    B->ncellblocks = nc;
+    return HRLB_OK;
+}
+}  // namespace
+
+extern "C" hrlb_status hrlb_batch_workspace_bytes(hrlb_case* const* cases, int n_cases, size_t* bytes)
+{
+    BatchLayout B;
+    hrlb_status st = batch_layout(cases, n_cases, &B);
+    if (st != HRLB_OK) return st;
+    if (!bytes) return fail(HRLB_E_INVALID, "bytes is NULL");
+    *bytes = B.total;
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, void* dev_workspace, size_t ws_bytes,
+                                         hrlb_batch** out)
+{
+    if (!out) return fail(HRLB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    BatchLayout B;
+    hrlb_status st = batch_layout(cases, n_cases, &B);
+    if (st != HRLB_OK) return st;
+    if (!dev_workspace || ((uintptr_t)dev_workspace & 255)) return fail(HRLB_E_INVALID, "workspace NULL or misaligned");
+    if (ws_bytes < B.total) return fail(HRLB_E_NOMEM, "batch workspace of %zu bytes < %zu", ws_bytes, B.total);
+    hrlb_batch* b = new (std::nothrow) hrlb_batch;
+    if (!b) return fail(HRLB_E_NOMEM, "host allocation failed");
+    b->cases.assign(cases, cases + n_cases);
+    char* ws = (char*)dev_workspace;
+    b->d_descs = (InstDesc*)(ws + B.descs);
+    b->d_tiles = (TileRef*)(ws + B.tiles);
+    b->d_cells = (CellRef*)(ws + B.cells);
+    b->ntiles = B.ntiles;
+    b->ncellblocks = B.ncellblocks;
+    b->fp32 = cases[0]->p.precision == HRLB_FP32_STORE_FP64_MOM;
+    b->stream = cases[0]->stream;
+    std::vector<InstDesc> descs(n_cases);
+    std::vector<TileRef> tiles;
+    std::vector<CellRef> cells;
+    // tiles ordered cell tile-major within an instance so that blocks sharing cells run together
+    for (int i = 0; i < n_cases; ++i) {
+        const hrlb_case* c = cases[i];
+        descs[i] = c->desc;
+        for (int ct = 0; ct < c->L.nctiles; ++ct)
+            for (int g = 0; g < c->L.ngroups; ++g) tiles.push_back(TileRef{i, ct, g, ct * c->L.ngroups + g});
+        for (int k = 0; k < c->L.ncellblocks; ++k) cells.push_back(CellRef{i, k * kCellBlock});
+    }
+    hipError_t e = hipMemcpyAsync(b->d_descs, descs.data(), sizeof(InstDesc) * n_cases, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_cells, cells.data(), sizeof(CellRef) * cells.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(HRLB_E_DEVICE, "batch upload: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_batch_step(hrlb_batch* b, long n_steps, int check)
+{
+    if (!b) return fail(HRLB_E_INVALID, "batch is NULL");
+    if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
+    hrlb_status st = enqueue_steps(b->fp32, b->d_descs, (int)b->cases.size(), b->d_tiles, b->ntiles, b->d_cells,
+                                   b->ncellblocks, n_steps, check != 0, b->stream);
+    if (st == HRLB_OK)
+        for (hrlb_case* c : b->cases) c->steps_done += n_steps;
+    return st;
+}
+
+extern "C" hrlb_status hrlb_batch_poll(hrlb_batch* b, double* residual, double* pxy_mean)
+{
+    if (!b) return fail(HRLB_E_INVALID, "batch is NULL");
+    const int n = (int)b->cases.size();
+    std::vector<double> dy((size_t)kNDyn * n);
+    for (int i = 0; i < n; ++i)
+        HIP_TRY(hipMemcpyAsync(dy.data() + (size_t)i * kNDyn, b->cases[i]->desc.dyn, sizeof(double) * kNDyn,
+                               hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (int i = 0; i < n; ++i) {
+        const double* d = dy.data() + (size_t)i * kNDyn;
+        if (residual) residual[i] = std::sqrt(d[DY_RES_NUM]) / (b->cases[i]->dt * std::sqrt(d[DY_RES_DEN]));
+        if (pxy_mean) pxy_mean[i] = d[DY_PXY_MEAN];
+    }
+    return HRLB_OK;
+}
+
+extern "C" void hrlb_batch_free(hrlb_batch* b) { delete b; }
+
+extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* stage_kernel_ms, double* cell_kernel_ms)
+{
+    if (!b || n_steps < 1) return fail(HRLB_E_INVALID, "NULL batch or n_steps < 1");
+    const long nl = n_steps * 3;
+    std::vector<hipEvent_t> ev(4 * nl, nullptr);
+    hrlb_status st = HRLB_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            st = fail(HRLB_E_DEVICE, "hipEventCreate failed");
+            break;
+        }
+    const int grid = stage_grid(b->ntiles);
+    for (long k = 0; k < nl && st == HRLB_OK; ++k) {
+        const int stage = (int)(k % 3);
+        hipError_t e = hipEventRecord(ev[4 * k], b->stream);
+        if (e == hipSuccess) e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, grid, stage, 0, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 1], b->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 2], b->stream);
+        if (e == hipSuccess)
+            e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, b->stream);
+        if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 3], b->stream);
+        if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profiled launch: %s", hipGetErrorString(e));
+    }
+    double ts = 0, tc = 0;
+    if (st == HRLB_OK) {
+        hipError_t e = hipStreamSynchronize(b->stream);
+        for (long k = 0; k < nl && e == hipSuccess; ++k) {
+            float a = 0, c = 0;
+            e = hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[4 * k + 2], ev[4 * k + 3]);
+            ts += a;
+            tc += c;
+        }
+        if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profile events: %s", hipGetErrorString(e));
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != HRLB_OK) return st;
+    for (hrlb_case* c : b->cases) c->steps_done += n_steps;
+    if (stage_kernel_ms) *stage_kernel_ms = ts / nl;
+    if (cell_kernel_ms) *cell_kernel_ms = tc / nl;
+    return HRLB_OK;
+}

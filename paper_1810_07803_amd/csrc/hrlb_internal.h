@@ -1,0 +1,147 @@
+// hrlb_internal.h -- data layout shared by the host runtime and the gfx950 kernels of the
+// half-range lattice Boltzmann Couette solver.  Not part of the public ABI (see include/hrlb.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hrlb {
+
+// ---- stage kernel tiling ------------------------------------------------------------------
+// A block of kThreads threads covers kTileCells consecutive cells (kStrip per thread, kTPR
+// threads per velocity row) and kRows velocity rows.  A row walks `vpt` velocities sharing the
+// same p_x (consecutive j), so the x-advection upwind direction is uniform along a row.
+constexpr int kThreads = 256;
+constexpr int kStrip = 4;
+constexpr int kTPR = 16;
+constexpr int kRows = kThreads / kTPR;        // 16
+constexpr int kTileCells = kStrip * kTPR;     // 64
+constexpr int kMomPerPass = 4;                // moments reduced per LDS pass
+constexpr int kCellBlock = 64;                // threads per block of the per-cell kernel
+
+// auxiliary half-range Gauss rule used to project the Maxwellian on the half-range Hermite
+// basis (well-conditioned replacement of the monomial-moment form of eq. gx)
+constexpr int kAux = 48;
+
+constexpr int kMaxQx = 128, kMaxNx = 16, kMaxQy = 64;
+constexpr int kNMom = 11;  // raw moment accumulators per cell
+
+// per-cell scalars stored in the storage precision, slot-major [slot][nx]
+enum : int { SC_UX = 0, SC_UY, SC_T, SC_INVTAU, SC_AS, SC_AS5T, SC_QX, SC_QY, SC_IJD, kNSc };
+// FP64 output fields [field][nx]
+enum : int { F_N = 0, F_UX, F_UY, F_T, F_PXX, F_PXY, F_PYY, F_TZZ, F_QX, F_QY, kNFields };
+// mutable per-instance FP64 scalars
+enum : int {
+    DY_NWL = 0,   // wall density of the left wall for the current state
+    DY_NWR,       // right wall
+    DY_SHEAR_L,   // y-momentum flux through the left wall face
+    DY_SHEAR_R,
+    DY_STEP,      // completed steps (double, exact below 2^53)
+    DY_RES_NUM,   // last residual numerator  sum J (f_new - f_old)^2
+    DY_RES_DEN,   // last residual denominator sum J f_old^2
+    DY_PXY_MEAN,  // J-weighted channel mean of P_xy at the last check
+    DY_MASS,      // sum_s J_s deta n_s at the last check
+    DY_FLAGS,     // nonzero if a non-finite value was met
+    kNDyn = 16
+};
+
+struct InstDesc {
+    int nx;        // cells
+    int qx, qy;    // quadrature orders
+    int nv;        // 2 qx qy
+    int nxo, nyo;  // expansion orders N_x, N_y
+    int vpt;       // velocities per row (divides qy)
+    int segs_per_line;  // qy / vpt
+    int nseg;      // 2 qx qy / vpt
+    int ngroups;   // ceil(nseg / kRows)
+    int nctiles;   // ceil(nx / kTileCells)
+    int precision; // 0 fp64, 1 fp32 storage
+    int rounding;  // 0 nearest, 1 stochastic (fp32 only)
+    int collisionless;
+    uint32_t seed;
+    int pad0;
+    double dt, Tw, Pr, omega;
+    double tau_pref;     // delta sqrt(2) sqrt(T_w): 1/tau = tau_pref n (T/T_w)^(1-omega)
+    double den_l, den_r; // sum over entering directions of p_x g_x(0,T_w) g_y(-/+u_w,T_w)
+    double mom_l, mom_r; // same sums weighted by p_y (incoming momentum flux per unit n_w)
+    // device pointers (all inside the case workspace)
+    void* f[3];          // state buffers, each [2][nv][nx] in the storage precision
+    void* cell;          // [kNSc + 2 qx + qy][nx] storage precision
+    double* fields;      // [kNFields][nx]
+    double* mom_part;    // [ngroups][kNMom][nx]
+    double* wall_part;   // [ngroups][4]: left flux, right flux, left p_y flux, right p_y flux
+    double* res_part;    // [nctiles * ngroups][2]
+    double* dyn;         // [kNDyn]
+    const double* px;    // [2 qx]
+    const double* py;    // [qy]
+    const double* wx;    // [qx]
+    const double* wy;    // [qy]
+    const double* hz;    // [(nxo+1)][qx]   orthonormal half-range polynomials at the nodes
+    const double* auxZ;  // [kAux]
+    const double* auxW;  // [kAux]
+    const double* hZ;    // [(nxo+1)][kAux] the same polynomials at the auxiliary nodes
+    const double* he;    // [(nyo+1)][qy]   probabilists' Hermite polynomials at the y nodes
+    const double* inv_jdeta; // [nx]
+    const double* jdeta;     // [nx]
+    const double* gw_l;  // [nv] g_x(0,T_w) g_y(-u_w,T_w)
+    const double* gw_r;  // [nv] g_x(0,T_w) g_y(+u_w,T_w)
+    const double* g0;    // [nv] initial populations (rest equilibrium, n = 1)
+};
+
+struct TileRef {   // one block-sized unit of the stage kernel
+    int inst;
+    int ctile;     // cell tile index within the instance
+    int group;     // velocity group index within the instance
+    int tile_id;   // ctile * ngroups + group (residual partial slot)
+};
+
+struct CellRef {   // one block of the per-cell kernel
+    int inst;
+    int cell0;
+};
+
+// ---- equilibrium truncations (host and device) ------------------------------------------
+// g_{x,i}(u,T), i < 2 qx, following eq. gx as a projection: g_{x,i} = w_i sum_l h_l(z_i) I_l with
+// I_l = int_0^inf g(p; sigma_i u, T) h_l(p) dp evaluated with the auxiliary half-range rule,
+// where g/omega = exp(p^2/2 - (p-u)^2/(2T))/sqrt(T).
+__host__ __device__ inline void eval_gx(int qx, int nxo, const double* wx, const double* hz,
+                                        const double* auxZ, const double* auxW, const double* hZ,
+                                        double u, double T, double* out)
+{
+    const double inv2T = 0.5 / T;
+    const double rsT = 1.0 / sqrt(T);
+    for (int h = 0; h < 2; ++h) {
+        const double us = h == 0 ? u : -u;
+        double I[kMaxNx + 1];
+        for (int l = 0; l <= nxo; ++l) I[l] = 0.0;
+        for (int k = 0; k < kAux; ++k) {
+            const double Z = auxZ[k];
+            const double e = (Z * Z * (T - 1.0) + 2.0 * Z * us - us * us) * inv2T;
+            const double wk = auxW[k] * exp(e) * rsT;
+            for (int l = 0; l <= nxo; ++l) I[l] += wk * hZ[l * kAux + k];
+        }
+        for (int i = 0; i < qx; ++i) {
+            double s = 0.0;
+            for (int l = 0; l <= nxo; ++l) s += I[l] * hz[l * qx + i];
+            out[h * qx + i] = wx[i] * s;
+        }
+    }
+}
+
+// g_{y,j}(u,T), eq. gy: w_j sum_l He_l(y_j) c_l with c_l the coefficient of t^l in
+// exp(u t + (T-1) t^2/2), i.e. l c_l = u c_{l-1} + (T-1) c_{l-2}.
+__host__ __device__ inline void eval_gy(int qy, int nyo, const double* wy, const double* he, double u,
+                                        double T, double* out, int stride = 1)
+{
+    double c[kMaxQy];
+    c[0] = 1.0;
+    if (nyo >= 1) c[1] = u;
+    for (int l = 2; l <= nyo; ++l) c[l] = (u * c[l - 1] + (T - 1.0) * c[l - 2]) / l;
+    for (int j = 0; j < qy; ++j) {
+        double s = 0.0;
+        for (int l = 0; l <= nyo; ++l) s += c[l] * he[l * qy + j];
+        out[j * stride] = wy[j] * s;
+    }
+}
+
+}  // namespace hrlb

@@ -1,0 +1,258 @@
+"""Thin Python binding of libhrlb (include/hrlb.h) through ctypes.
+
+Argument marshalling only: every step of the solver runs in the HIP kernels of libhrlb.so.
+PyTorch supplies the device workspace (a uint8 tensor) and the HIP stream.  If the library is
+missing, loading fails loudly; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhrlb.so")
+
+HRLB_OK, HRLB_NOT_CONVERGED = 0, 1
+HRLB_E_INVALID, HRLB_E_NOMEM, HRLB_E_DEVICE, HRLB_E_DIVERGED = -1, -2, -3, -4
+HRLB_FP64, HRLB_FP32_STORE_FP64_MOM = 0, 1
+HRLB_ROUND_NEAREST, HRLB_ROUND_STOCHASTIC = 0, 1
+HRLB_STOP_RESIDUAL, HRLB_STOP_PXY = 0, 1
+
+FIELD_NAMES = ("n", "u_x", "u_y", "T", "P_xx", "P_xy", "P_yy", "T_zz", "q_x", "q_y")
+
+EXPORTED = (
+    "hrlb_init_quadrature", "hrlb_quadrature_nodes", "hrlb_case_workspace_bytes", "hrlb_init_case",
+    "hrlb_step", "hrlb_run_to_steady", "hrlb_moments", "hrlb_get_state", "hrlb_set_state",
+    "hrlb_case_info", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
+    "hrlb_batch_workspace_bytes", "hrlb_batch_create", "hrlb_batch_step", "hrlb_batch_poll",
+    "hrlb_batch_free", "hrlb_batch_profile",
+)
+
+
+class HrlbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hrlb status {status}: {msg}")
+        self.status = status
+
+
+class CaseParams(C.Structure):
+    _fields_ = [
+        ("delta", C.c_double), ("u_w", C.c_double), ("T_w", C.c_double), ("Pr", C.c_double),
+        ("omega", C.c_double), ("n_cells", C.c_int), ("stretch_A", C.c_double),
+        ("precision", C.c_int), ("rounding", C.c_int), ("cfl", C.c_double), ("dt", C.c_double),
+        ("seed", C.c_uint),
+    ]
+
+
+class SteadyInfo(C.Structure):
+    _fields_ = [("steps", C.c_long), ("residual", C.c_double), ("pxy_drift", C.c_double),
+                ("sim_time", C.c_double), ("wall_s", C.c_double), ("mass_drift", C.c_double)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load() -> C.CDLL:
+    """Load libhrlb.so (built by paper_1810_07803_amd/build.py); raise if it is absent."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1810_07803_amd.build")
+            lib = C.CDLL(LIB_PATH)
+            vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
+            sig = {
+                "hrlb_init_quadrature": [C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(vp)],
+                "hrlb_quadrature_nodes": [vp, dp, dp, dp, dp],
+                "hrlb_case_workspace_bytes": [vp, C.POINTER(CaseParams), C.POINTER(C.c_size_t)],
+                "hrlb_init_case": [vp, C.POINTER(CaseParams), vp, C.c_size_t, vp, C.POINTER(vp)],
+                "hrlb_step": [vp, C.c_long],
+                "hrlb_run_to_steady": [vp, C.c_double, C.c_long, C.c_int, C.c_int, C.POINTER(SteadyInfo)],
+                "hrlb_moments": [vp, dp, dp, dp, dp],
+                "hrlb_get_state": [vp, dp],
+                "hrlb_set_state": [vp, dp],
+                "hrlb_case_info": [vp, dp, ip, ip, C.POINTER(C.c_long)],
+                "hrlb_batch_workspace_bytes": [C.POINTER(vp), C.c_int, C.POINTER(C.c_size_t)],
+                "hrlb_batch_create": [C.POINTER(vp), C.c_int, vp, C.c_size_t, C.POINTER(vp)],
+                "hrlb_batch_step": [vp, C.c_long, C.c_int],
+                "hrlb_batch_poll": [vp, dp, dp],
+                "hrlb_batch_profile": [vp, C.c_long, dp, dp],
+            }
+            for name, args in sig.items():
+                fn = getattr(lib, name)
+                fn.argtypes = args
+                fn.restype = C.c_int
+            for name in ("hrlb_free_case", "hrlb_free_quadrature", "hrlb_batch_free"):
+                getattr(lib, name).argtypes = [vp]
+                getattr(lib, name).restype = None
+            lib.hrlb_last_error.argtypes = []
+            lib.hrlb_last_error.restype = C.c_char_p
+            _lib = lib
+    return _lib
+
+
+def _check(status: int, allow=(HRLB_OK,)) -> int:
+    if status not in allow:
+        raise HrlbError(status, load().hrlb_last_error().decode(errors="replace"))
+    return status
+
+
+def _dptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ---- velocity set ------------------------------------------------------------------------------
+class Quadrature:
+    """HHLB(Nx;Qx) x HLB(Ny;Qy) velocity set (hrlb_init_quadrature)."""
+
+    def __init__(self, Qx: int, Qy: int, Nx: int | None = None, Ny: int | None = None, p0: float = 1.0):
+        self.Qx, self.Qy = Qx, Qy
+        self.Nx = min(Qx - 1, 10) if Nx is None else Nx
+        self.Ny = Qy - 1 if Ny is None else Ny
+        h = C.c_void_p()
+        _check(load().hrlb_init_quadrature(Qx, self.Nx, Qy, self.Ny, p0, C.byref(h)))
+        self.handle = h
+
+    def nodes(self):
+        px, wx = np.zeros(2 * self.Qx), np.zeros(2 * self.Qx)
+        py, wy = np.zeros(self.Qy), np.zeros(self.Qy)
+        _check(load().hrlb_quadrature_nodes(self.handle, _dptr(px), _dptr(wx), _dptr(py), _dptr(wy)))
+        return px, wx, py, wy
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hrlb_free_quadrature(self.handle)
+            self.handle = None
+
+
+def init_quadrature(Qx, Nx, Qy, Ny, p0=1.0) -> Quadrature:
+    return Quadrature(Qx, Qy, Nx, Ny, p0)
+
+
+def make_params(*, delta, uw, ncell, stretch_A=0.0, Tw=1.0, Pr=2.0 / 3.0, omega=0.7, precision=HRLB_FP64,
+                rounding=HRLB_ROUND_NEAREST, cfl=0.5, dt=0.0, seed=0) -> CaseParams:
+    return CaseParams(delta, uw, Tw, Pr, omega, ncell, stretch_A, precision, rounding, cfl, dt, seed & 0xFFFFFFFF)
+
+
+def workspace_bytes(quad: Quadrature, params: CaseParams) -> int:
+    n = C.c_size_t()
+    _check(load().hrlb_case_workspace_bytes(quad.handle, C.byref(params), C.byref(n)))
+    return n.value
+
+
+# ---- one case ----------------------------------------------------------------------------------
+class Case:
+    """One Couette problem resident in a torch-allocated device workspace (hrlb_init_case)."""
+
+    def __init__(self, quad: Quadrature, params: CaseParams, device="cuda:0", stream=None, workspace=None):
+        import torch
+
+        self.quad, self.params = quad, params
+        nbytes = workspace_bytes(quad, params)
+        if workspace is None:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self._ws_tensor = workspace
+        base = workspace.data_ptr()
+        off = (-base) % 256
+        if workspace.numel() - off < nbytes:
+            raise HrlbError(HRLB_E_NOMEM, "workspace tensor too small")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        _check(load().hrlb_init_case(quad.handle, C.byref(params), C.c_void_p(base + off), nbytes,
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+        dt, nv, nc, sd = C.c_double(), C.c_int(), C.c_int(), C.c_long()
+        _check(load().hrlb_case_info(h, C.byref(dt), C.byref(nv), C.byref(nc), C.byref(sd)))
+        self.dt, self.nv, self.ncell = dt.value, nv.value, nc.value
+        self.workspace_bytes = nbytes
+
+    def step(self, n_steps: int):
+        _check(load().hrlb_step(self.handle, n_steps))
+
+    def run_to_steady(self, tol: float, max_steps: int, check_every: int = 100, stop_rule: int = HRLB_STOP_RESIDUAL):
+        info = SteadyInfo()
+        st = _check(load().hrlb_run_to_steady(self.handle, tol, max_steps, check_every, stop_rule, C.byref(info)),
+                    allow=(HRLB_OK, HRLB_NOT_CONVERGED))
+        return st, info
+
+    def moments(self):
+        f = np.zeros((10, self.ncell))
+        x = np.zeros(self.ncell)
+        pi = C.c_double()
+        sh = np.zeros(2)
+        _check(load().hrlb_moments(self.handle, _dptr(f), _dptr(x), C.byref(pi), _dptr(sh)))
+        return f, x, pi.value, sh
+
+    def get_state(self) -> np.ndarray:
+        s = np.zeros((2, self.nv, self.ncell))
+        _check(load().hrlb_get_state(self.handle, _dptr(s)))
+        return s
+
+    def set_state(self, state: np.ndarray):
+        s = np.ascontiguousarray(state, dtype=np.float64)
+        assert s.shape == (2, self.nv, self.ncell)
+        _check(load().hrlb_set_state(self.handle, _dptr(s)))
+
+    def steps_done(self) -> int:
+        sd = C.c_long()
+        _check(load().hrlb_case_info(self.handle, None, None, None, C.byref(sd)))
+        return sd.value
+
+    def free(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hrlb_free_case(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.free()
+
+
+def init_case(quad, params, device="cuda:0", stream=None) -> Case:
+    return Case(quad, params, device, stream)
+
+
+# ---- batches -----------------------------------------------------------------------------------
+class Batch:
+    """Several cases advanced by shared launches (hrlb_batch_create)."""
+
+    def __init__(self, cases, device="cuda:0"):
+        import torch
+
+        self.cases = list(cases)
+        arr = (C.c_void_p * len(self.cases))(*[c.handle.value for c in self.cases])
+        n = C.c_size_t()
+        _check(load().hrlb_batch_workspace_bytes(arr, len(self.cases), C.byref(n)))
+        self._ws = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        h = C.c_void_p()
+        _check(load().hrlb_batch_create(arr, len(self.cases), C.c_void_p(base + off), n.value, C.byref(h)))
+        self.handle = h
+
+    def step(self, n_steps: int, check: bool = False):
+        _check(load().hrlb_batch_step(self.handle, n_steps, int(check)))
+
+    def poll(self):
+        r = np.zeros(len(self.cases))
+        p = np.zeros(len(self.cases))
+        _check(load().hrlb_batch_poll(self.handle, _dptr(r), _dptr(p)))
+        return r, p
+
+    def profile(self, n_steps: int):
+        """Mean duration (ms) of one stage-kernel launch and one per-cell-kernel launch."""
+        a, b = C.c_double(), C.c_double()
+        _check(load().hrlb_batch_profile(self.handle, n_steps, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def free(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hrlb_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.free()

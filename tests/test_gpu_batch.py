@@ -1,0 +1,95 @@
+"""Batched ragged launches: each case's result is bitwise the same alone and in any batch, and the
+full-size ragged batch agrees with the oracle on sampled instances."""
+import numpy as np
+import pytest
+
+from hrlb_inputs import batch_draws
+from tests.gpu_helpers import field_errs, make_pair, rel_state_err, say
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(4, 4, 64, 1.0, 0.05), (8, 12, 128, 0.2, 0.3), (16, 8, 100, 5.0, 0.45), (4, 8, 36, 0.02, 0.1)]
+
+
+def _cases(precision, rounding):
+    out = []
+    for k, (Qx, Qy, nx, delta, uw) in enumerate(SHAPES):
+        c, _ = make_pair(Qx, Qy, nx, delta=delta, uw=uw, stretch_A=0.9, precision=precision, rounding=rounding,
+                         seed=100 + k)
+        out.append(c)
+    return out
+
+
+@pytest.mark.parametrize("precision,rounding", [(0, 0), (1, 1)])
+def test_batch_equals_alone_bitwise(precision, rounding):
+    from paper_1810_07803_amd import hrlb
+
+    say(f"[batch] alone vs mix, precision={precision} rounding={rounding}, shapes={SHAPES}")
+    alone = _cases(precision, rounding)
+    for c in alone:
+        c.step(25)
+    mixed = _cases(precision, rounding)
+    b = hrlb.Batch(mixed)
+    b.step(25)
+    for a, m in zip(alone, mixed):
+        np.testing.assert_array_equal(a.get_state(), m.get_state())
+        fa, _, pa, _ = a.moments()
+        fm, _, pm, _ = m.moments()
+        np.testing.assert_array_equal(fa, fm)
+    # a different mix (reversed order, one case left out) still gives the same numbers
+    again = _cases(precision, rounding)
+    b2 = hrlb.Batch(list(reversed(again[1:])))
+    b2.step(25)
+    for a, m in zip(alone[1:], again[1:]):
+        np.testing.assert_array_equal(a.get_state(), m.get_state())
+
+
+def test_batch_poll_reports_residual_and_pxy():
+    from paper_1810_07803_amd import hrlb
+
+    say("[batch] poll")
+    cs = _cases(0, 0)
+    b = hrlb.Batch(cs)
+    b.step(20, check=True)
+    res, pxy = b.poll()
+    for c, r, p in zip(cs, res, pxy):
+        f, x, pi, _ = c.moments()
+        assert np.isfinite(r) and r > 0
+        jd = np.diff(np.concatenate([[-0.5], 0.5 * (x[1:] + x[:-1]), [0.5]]))  # only a sanity scale
+        assert abs(p - np.average(f[5], weights=jd)) < 0.2 * (abs(p) + 1e-6)
+
+
+@pytest.mark.parametrize("precision,rounding,tol", [(1, 1, 1e-5), (0, 0, 1e-12)])
+def test_full_ragged_batch_sampled_against_oracle(precision, rounding, tol):
+    """The 512-instance ragged workload (seed 0), launched as one batch; three sampled instances are
+    re-run alone by the oracle from the same state and compared element by element."""
+    from paper_1810_07803_amd import hrlb
+
+    draws = batch_draws(512, seed=0)
+    say(f"[batch] full ragged batch of {len(draws)} instances, precision={precision}")
+    cases = []
+    for d in draws:
+        q = hrlb.Quadrature(d["Qx"], d["Qy"])
+        p = hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
+                             omega=d["omega"], precision=precision, rounding=rounding, seed=d["seed"])
+        c = hrlb.Case(q, p)
+        c._quad_ref = q
+        cases.append(c)
+    b = hrlb.Batch(cases)
+    steps = 3
+    b.step(steps)
+    sizes = [d["ncell"] * 2 * d["Qx"] * d["Qy"] for d in draws]
+    order = np.argsort(sizes)
+    sample = [int(order[0]), int(order[len(order) // 2]), int(order[-40])]
+    for k in sample:
+        d = draws[k]
+        say(f"   sample {k}: {d}")
+        _, orc = make_pair(d["Qx"], d["Qy"], d["ncell"], delta=d["delta"], uw=d["uw"], stretch_A=d["stretch_A"],
+                           omega=d["omega"], dt=cases[k].dt)
+        phi, chi = orc.init_state()
+        orc.step(phi, chi, steps)
+        st = cases[k].get_state()
+        e = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
+        ef = field_errs(cases[k].moments()[0], orc.moments(phi, chi))
+        say(f"   state err {e:.3e} field err max {ef.max():.3e}")
+        assert e < tol and np.all(ef < tol)

@@ -1,0 +1,70 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol of include/hrlb.h, and its
+host-side velocity sets (extended-precision discretized Stieltjes) agree with the oracle's
+arbitrary-precision tables.  No device work is started here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import quadrature as quad
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "hrlb.h")).read()
+    return sorted(set(re.findall(r"\b(hrlb_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1810_07803_amd import hrlb
+
+    lib = hrlb.load()
+    declared = _declared_symbols()
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(hrlb.EXPORTED)
+
+
+@pytest.mark.parametrize("Qx,Qy", [(3, 3), (4, 4), (7, 7), (16, 8), (32, 12), (80, 20), (128, 64)])
+def test_host_quadrature_matches_oracle_tables(Qx, Qy):
+    from paper_1810_07803_amd import hrlb
+
+    q = hrlb.Quadrature(Qx, Qy)
+    px, wx, py, wy = q.nodes()
+    hr, fr = quad.half_range_rule(Qx), quad.full_range_rule(Qy)
+    np.testing.assert_allclose(px[:Qx], hr.nodes_f64(), rtol=4e-16)
+    np.testing.assert_allclose(px[Qx:], -hr.nodes_f64(), rtol=4e-16)
+    np.testing.assert_allclose(wx[:Qx], hr.weights_f64(), rtol=2e-15)
+    np.testing.assert_allclose(py, fr.nodes_f64(), rtol=0, atol=4e-15)
+    np.testing.assert_allclose(wy, fr.weights_f64(), rtol=2e-15)
+
+
+def test_invalid_arguments_are_rejected_with_a_message():
+    from paper_1810_07803_amd import hrlb
+
+    with pytest.raises(hrlb.HrlbError) as ei:
+        hrlb.Quadrature(2, 4)
+    assert ei.value.status == hrlb.HRLB_E_INVALID
+    q = hrlb.Quadrature(4, 4)
+    for bad in (dict(ncell=30), dict(ncell=4), dict(delta=-1.0), dict(stretch_A=1.0), dict(Tw=0.0)):
+        kw = dict(delta=1.0, uw=0.1, ncell=32)
+        kw.update(bad)
+        with pytest.raises(hrlb.HrlbError) as ei:
+            hrlb.workspace_bytes(q, hrlb.make_params(**kw))
+        assert ei.value.status == hrlb.HRLB_E_INVALID
+        assert len(hrlb.load().hrlb_last_error()) > 0
+
+
+def test_workspace_size_scales_with_the_state():
+    from paper_1810_07803_amd import hrlb
+
+    q = hrlb.Quadrature(16, 8)
+    a = hrlb.workspace_bytes(q, hrlb.make_params(delta=0.1, uw=0.2, ncell=512))
+    b = hrlb.workspace_bytes(q, hrlb.make_params(delta=0.1, uw=0.2, ncell=512, precision=1))
+    units = 512 * 2 * 16 * 8
+    assert a > 3 * 2 * units * 8 and b > 3 * 2 * units * 4
+    assert a - b >= 3 * 2 * units * 4
