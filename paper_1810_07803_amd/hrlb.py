@@ -63,6 +63,10 @@ def load() -> C.CDLL:
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_1810_07803_amd.build")
+            # torch ships its own HIP runtime (same soname); loading it first makes libhrlb bind to
+            # that runtime, so torch's device pointers and streams are valid inside the library
+            import torch  # noqa: F401
+
             lib = C.CDLL(LIB_PATH)
             vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)
             sig = {

@@ -31,9 +31,15 @@ def rel_state_err(a: np.ndarray, b: np.ndarray) -> float:
 
 
 def field_errs(f_gpu: np.ndarray, f_orc: np.ndarray):
-    """Per-field max error relative to the field's own max magnitude (floor 1e-3 of the density scale)."""
+    """Per-field max error relative to the larger of the field's own max magnitude and its natural
+    scale (n_ref, sqrt(T_w), T_w, n_ref T_w, n_ref T_w^(3/2): all 1 in the solver's units)."""
     out = []
     for k in range(10):
-        scale = max(np.max(np.abs(f_orc[k])), 1e-3)
+        scale = max(np.max(np.abs(f_orc[k])), 1.0)
         out.append(float(np.max(np.abs(f_gpu[k] - f_orc[k])) / scale))
     return np.array(out)
+
+
+def pxy_err(f_gpu: np.ndarray, f_orc: np.ndarray) -> float:
+    """Shear stress error relative to its own magnitude (the headline quantity)."""
+    return float(np.max(np.abs(f_gpu[5] - f_orc[5])) / np.max(np.abs(f_orc[5])))

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from hrlb_inputs import batch_draws
-from tests.gpu_helpers import field_errs, make_pair, rel_state_err, say
+from tests.gpu_helpers import field_errs, make_pair, pxy_err, rel_state_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -90,6 +90,8 @@ def test_full_ragged_batch_sampled_against_oracle(precision, rounding, tol):
         orc.step(phi, chi, steps)
         st = cases[k].get_state()
         e = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
-        ef = field_errs(cases[k].moments()[0], orc.moments(phi, chi))
-        say(f"   state err {e:.3e} field err max {ef.max():.3e}")
-        assert e < tol and np.all(ef < tol)
+        fg, fo = cases[k].moments()[0], orc.moments(phi, chi)
+        ef = field_errs(fg, fo)
+        ep = pxy_err(fg, fo)
+        say(f"   state err {e:.3e} field err max {ef.max():.3e} P_xy rel {ep:.3e}")
+        assert e < tol and np.all(ef < tol) and ep < tol

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from hrlb_inputs import perturb
-from tests.gpu_helpers import field_errs, make_pair, rel_state_err, say
+from tests.gpu_helpers import field_errs, make_pair, pxy_err, rel_state_err, say
 
 pytestmark = pytest.mark.gpu
 
@@ -37,8 +37,9 @@ def _run_pair(name, Qx, Qy, ncell, steps, *, precision=0, rounding=0, amp=0.05, 
     f_orc = orc.moments(phi, chi)
     e_state = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
     e_fields = field_errs(f_gpu, f_orc)
-    say(f"   state err {e_state:.3e}  field errs {np.array2string(e_fields, precision=2)}")
-    return case, orc, phi, chi, e_state, e_fields
+    e_pxy = pxy_err(f_gpu, f_orc) if np.max(np.abs(f_orc[5])) > 0 else 0.0
+    say(f"   state err {e_state:.3e}  field errs {np.array2string(e_fields, precision=2)}  P_xy rel {e_pxy:.2e}")
+    return case, orc, phi, chi, e_state, np.append(e_fields, e_pxy)
 
 
 @pytest.mark.parametrize("name,Qx,Qy,ncell,steps,kw", [
