@@ -97,6 +97,8 @@ def main(argv=None):
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -131,6 +133,14 @@ def main(argv=None):
     value = units / (ms_per_step * 1e-3)
 
     stage_ms, cell_ms = batch.profile(args.profile_steps)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     es = 4 if spec["precision"] == 1 else 8
     # algorithmic bytes per stage launch: read f_in and write f_out (both dists) in every stage,
     # plus f^n in stages 2 and 3: (2 + 3 + 3)/3 passes of 2 dists per unit on average

@@ -21,7 +21,7 @@ using namespace hrlb;
 extern "C" hipError_t hrlbk_stage(int fp32, const InstDesc* descs, const TileRef* tiles, int ntiles, int grid,
                                   int stage, int flags, hipStream_t st);
 extern "C" hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int flags,
-                                 hipStream_t st);
+                                 size_t shmem, hipStream_t st);
 extern "C" hipError_t hrlbk_finalize(const InstDesc* descs, int ninst, int with_res, hipStream_t st);
 extern "C" hipError_t hrlbk_init(int fp32, const InstDesc* descs, int inst, size_t units, hipStream_t st);
 
@@ -84,12 +84,14 @@ struct hrlb_case {
     CellRef* d_cells;
     int ntiles;
     int nv;
+    size_t shmem;  // dynamic LDS of the per-cell kernel
     double dt;
     long steps_done;
     double mass0;
     std::vector<double> x, jdeta;
     double pxy_prev;
     bool has_prev_pxy;
+    bool needs_analyze;  // moments/tables of the stored state not computed yet
 };
 
 struct hrlb_batch {
@@ -99,6 +101,7 @@ struct hrlb_batch {
     CellRef* d_cells;
     int ntiles, ncellblocks;
     int fp32;
+    size_t shmem;
     hipStream_t stream;
 };
 
@@ -302,7 +305,8 @@ void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<doub
 int stage_grid(int ntiles) { return std::min(ntiles, 4096); }
 
 hrlb_status enqueue_steps(int fp32, const InstDesc* descs, int ninst, const TileRef* tiles, int ntiles,
-                          const CellRef* cells, int ncellblocks, long n_steps, bool check_last, hipStream_t st)
+                          const CellRef* cells, int ncellblocks, size_t shmem, long n_steps, bool check_last,
+                          hipStream_t st)
 {
     const int grid = stage_grid(ntiles);
     for (long s = 0; s < n_steps; ++s) {
@@ -310,7 +314,7 @@ hrlb_status enqueue_steps(int fp32, const InstDesc* descs, int ninst, const Tile
         for (int stage = 0; stage < 3; ++stage) {
             const int fl = (stage == 2 && chk) ? FLAG_RESID : 0;
             HIP_TRY(hrlbk_stage(fp32, descs, tiles, ntiles, grid, stage, fl, st));
-            HIP_TRY(hrlbk_cell(fp32, descs, cells, ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, st));
+            HIP_TRY(hrlbk_cell(fp32, descs, cells, ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, shmem, st));
         }
         if (chk) HIP_TRY(hrlbk_finalize(descs, ninst, 1, st));
     }
@@ -321,10 +325,13 @@ hrlb_status analyze_case(hrlb_case* c)
 {
     const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
     HIP_TRY(hrlbk_stage(fp32, c->d_desc, c->d_tiles, c->ntiles, stage_grid(c->ntiles), -1, 0, c->stream));
-    HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, c->stream));
+    HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, c->shmem, c->stream));
     HIP_TRY(hrlbk_finalize(c->d_desc, 1, 0, c->stream));
+    c->needs_analyze = false;
     return HRLB_OK;
 }
+
+hrlb_status ensure_analyzed(hrlb_case* c) { return c->needs_analyze ? analyze_case(c) : HRLB_OK; }
 
 }  // namespace
 
@@ -435,6 +442,8 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.rounding = p->precision == HRLB_FP32_STORE_FP64_MOM ? p->rounding : 0;
     D.collisionless = p->delta == 0.0;
     D.seed = p->seed;
+    D.ktab_n = (int)(L.t_he + (size_t)(q->nyo + 1) * qy - L.t_wx);
+    c->shmem = sizeof(double) * (size_t)D.ktab_n;
     D.dt = dt;
     D.Tw = p->T_w;
     D.Pr = p->Pr;
@@ -444,6 +453,8 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.den_r = den_r;
     D.mom_l = mom_l;
     D.mom_r = mom_r;
+    D.jsum = 0.0;
+    for (int s = 0; s < nx; ++s) D.jsum += c->jdeta[s];
     char* ws = c->ws;
     for (int k = 0; k < 3; ++k) D.f[k] = ws + L.f[k];
     D.cell = ws + L.cell;
@@ -490,25 +501,18 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     cp(L.tiles, tiles.data(), sizeof(TileRef) * tiles.size());
     cp(L.cells, cells.data(), sizeof(CellRef) * cells.size());
     if (e == hipSuccess) e = hrlbk_init(p->precision == HRLB_FP32_STORE_FP64_MOM, c->d_desc, 0, (size_t)nv * nx, c->stream);
-    if (e == hipSuccess) st = analyze_case(c);
     // the host staging vectors above must outlive the enqueued copies: wait on every path
     const hipError_t es = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess || es != hipSuccess || st != HRLB_OK) {
+    if (e != hipSuccess || es != hipSuccess) {
         delete c;
-        if (st != HRLB_OK) return st;
         return fail(HRLB_E_DEVICE, "case upload: %s", hipGetErrorString(e != hipSuccess ? e : es));
     }
-    double mass = 0.0;
-    {
-        double dy[kNDyn];
-        e = hipMemcpy(dy, D.dyn, sizeof dy, hipMemcpyDeviceToHost);
-        if (e != hipSuccess) {
-            delete c;
-            return fail(HRLB_E_DEVICE, "case init read-back: %s", hipGetErrorString(e));
-        }
-        mass = dy[DY_MASS];
-    }
-    c->mass0 = mass;
+    // moments and equilibrium tables of the initial state are computed lazily (one analysis pass per
+    // case, or one for a whole batch); the initial mass follows from the uniform rest state
+    c->needs_analyze = true;
+    double n0 = 0.0;
+    for (int v = 0; v < nv; ++v) n0 += tab[L.t_g0 + v];
+    c->mass0 = n0 * D.jsum;
     *out = c;
     return HRLB_OK;
 }
@@ -529,8 +533,10 @@ extern "C" hrlb_status hrlb_step(hrlb_case* c, long n_steps)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
     if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
+    hrlb_status st0 = ensure_analyzed(c);
+    if (st0 != HRLB_OK) return st0;
     hrlb_status st = enqueue_steps(c->p.precision == HRLB_FP32_STORE_FP64_MOM, c->d_desc, 1, c->d_tiles, c->ntiles,
-                                   c->d_cells, c->L.ncellblocks, n_steps, false, c->stream);
+                                   c->d_cells, c->L.ncellblocks, c->shmem, n_steps, false, c->stream);
     if (st == HRLB_OK) c->steps_done += n_steps;
     return st;
 }
@@ -543,6 +549,10 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
     if (stop_rule != HRLB_STOP_RESIDUAL && stop_rule != HRLB_STOP_PXY) return fail(HRLB_E_INVALID, "bad stop rule");
     const auto t0 = std::chrono::steady_clock::now();
     const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
+    {
+        hrlb_status sa = ensure_analyzed(c);
+        if (sa != HRLB_OK) return sa;
+    }
     long taken = 0;
     double res = -1.0, drift = -1.0;
     hrlb_status verdict = HRLB_NOT_CONVERGED;
@@ -551,8 +561,8 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
     double pxy_prev = 0.0;
     while (taken < max_steps) {
         const long n = std::min<long>(check_every, max_steps - taken);
-        hrlb_status st = enqueue_steps(fp32, c->d_desc, 1, c->d_tiles, c->ntiles, c->d_cells, c->L.ncellblocks, n,
-                                       true, c->stream);
+        hrlb_status st = enqueue_steps(fp32, c->d_desc, 1, c->d_tiles, c->ntiles, c->d_cells, c->L.ncellblocks,
+                                       c->shmem, n, true, c->stream);
         if (st != HRLB_OK) return st;
         HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
@@ -588,6 +598,10 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
 extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, double* Pi, double* wall_shear)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    {
+        hrlb_status sa = ensure_analyzed(c);
+        if (sa != HRLB_OK) return sa;
+    }
     const int nx = c->p.n_cells;
     std::vector<double> f((size_t)kNFields * nx);
     double dy[kNDyn];
@@ -646,7 +660,10 @@ extern "C" hrlb_status hrlb_set_state(hrlb_case* c, const double* host_state)
     }
     hrlb_status st = analyze_case(c);
     if (st != HRLB_OK) return st;
+    double dy[kNDyn];
+    HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    c->mass0 = dy[DY_MASS];  // mass drift is reported relative to the uploaded state
     return HRLB_OK;
 }
 
@@ -714,6 +731,8 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
     b->ncellblocks = B.ncellblocks;
     b->fp32 = cases[0]->p.precision == HRLB_FP32_STORE_FP64_MOM;
     b->stream = cases[0]->stream;
+    b->shmem = 0;
+    for (int i = 0; i < n_cases; ++i) b->shmem = std::max(b->shmem, cases[i]->shmem);
     std::vector<InstDesc> descs(n_cases);
     std::vector<TileRef> tiles;
     std::vector<CellRef> cells;
@@ -730,11 +749,21 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
         e = hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_cells, cells.data(), sizeof(CellRef) * cells.size(), hipMemcpyHostToDevice, b->stream);
+    // one analysis pass over the whole batch brings every case's moments up to date (it reproduces
+    // bit for bit what a case already analysed holds)
+    bool any = false;
+    for (int i = 0; i < n_cases; ++i) any = any || cases[i]->needs_analyze;
+    if (e == hipSuccess && any) {
+        e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, stage_grid(b->ntiles), -1, 0, b->stream);
+        if (e == hipSuccess) e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, 0, b->shmem, b->stream);
+        if (e == hipSuccess) e = hrlbk_finalize(b->d_descs, n_cases, 0, b->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         delete b;
         return fail(HRLB_E_DEVICE, "batch upload: %s", hipGetErrorString(e));
     }
+    for (int i = 0; i < n_cases; ++i) cases[i]->needs_analyze = false;
     *out = b;
     return HRLB_OK;
 }
@@ -744,7 +773,7 @@ extern "C" hrlb_status hrlb_batch_step(hrlb_batch* b, long n_steps, int check)
     if (!b) return fail(HRLB_E_INVALID, "batch is NULL");
     if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
     hrlb_status st = enqueue_steps(b->fp32, b->d_descs, (int)b->cases.size(), b->d_tiles, b->ntiles, b->d_cells,
-                                   b->ncellblocks, n_steps, check != 0, b->stream);
+                                   b->ncellblocks, b->shmem, n_steps, check != 0, b->stream);
     if (st == HRLB_OK)
         for (hrlb_case* c : b->cases) c->steps_done += n_steps;
     return st;
@@ -788,7 +817,8 @@ extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* s
         if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 1], b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 2], b->stream);
         if (e == hipSuccess)
-            e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, b->stream);
+            e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, b->shmem,
+                           b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 3], b->stream);
         if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profiled launch: %s", hipGetErrorString(e));
     }

@@ -59,11 +59,12 @@ struct InstDesc {
     int rounding;  // 0 nearest, 1 stochastic (fp32 only)
     int collisionless;
     uint32_t seed;
-    int pad0;
+    int ktab_n;    // doubles from wx to the end of he (contiguous quadrature tables)
     double dt, Tw, Pr, omega;
     double tau_pref;     // delta sqrt(2) sqrt(T_w): 1/tau = tau_pref n (T/T_w)^(1-omega)
     double den_l, den_r; // sum over entering directions of p_x g_x(0,T_w) g_y(-/+u_w,T_w)
     double mom_l, mom_r; // same sums weighted by p_y (incoming momentum flux per unit n_w)
+    double jsum;         // sum_s J_s deta (channel width in x)
     // device pointers (all inside the case workspace)
     void* f[3];          // state buffers, each [2][nv][nx] in the storage precision
     void* cell;          // [kNSc + 2 qx + qy][nx] storage precision

@@ -106,8 +106,8 @@ __device__ __forceinline__ T ext_m1(T y0, T y1, T y2) { return T(3) * y0 - T(3) 
 template <typename T>
 __device__ __forceinline__ T ext_m2(T y0, T y1, T y2) { return T(6) * y0 - T(8) * y1 + T(3) * y2; }  // t = -2
 
-// stage < 0: analysis pass (no update; partials of the current state f[0])
-template <typename T>
+// ANALYZE: no update; partials of the current state f[0] (used after set-up or a state upload)
+template <typename T, bool ANALYZE>
 __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restrict__ descs,
                                                          const TileRef* __restrict__ tiles, int ntiles,
                                                          int stage, int flags)
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 
     const int tid = threadIdx.x;
     const int row = tid / kTPR, strip = tid % kTPR;
-    const bool analyze = stage < 0;
+    constexpr bool analyze = ANALYZE;
     const int in_idx = analyze ? 0 : (stage == 0 ? 0 : stage == 1 ? 1 : 2);
     const int out_idx = analyze ? 0 : (stage == 0 ? 1 : stage == 1 ? 2 : 0);
     const double ca = stage == 1 ? 0.75 : stage == 2 ? (1.0 / 3.0) : 0.0;
@@ -405,14 +405,29 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 }
 
 // ---- per-cell kernel --------------------------------------------------------------------------
+constexpr int kCyReg = 32;  // expansion orders N_y below this keep their coefficients in registers
+
 template <typename T>
 __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __restrict__ descs,
                                                           const CellRef* __restrict__ cells, int flags)
 {
+    extern __shared__ double ktab[];
     const CellRef cr = cells[blockIdx.x];
     const InstDesc& D = descs[cr.inst];
     const int nx = D.nx;
     const int s = cr.cell0 + threadIdx.x;
+
+    // the instance's quadrature tables are contiguous from wx to the end of he: stage them in LDS
+    const double* gbase = D.wx;
+    for (int k = threadIdx.x; k < D.ktab_n; k += blockDim.x) ktab[k] = gbase[k];
+    __syncthreads();
+    const double* s_wx = ktab;
+    const double* s_wy = ktab + (D.wy - gbase);
+    const double* s_hz = ktab + (D.hz - gbase);
+    const double* s_az = ktab + (D.auxZ - gbase);
+    const double* s_aw = ktab + (D.auxW - gbase);
+    const double* s_hZ = ktab + (D.hZ - gbase);
+    const double* s_he = ktab + (D.he - gbase);
 
     if (cr.cell0 == 0 && threadIdx.x == 0) {
         // eq. (diffuse_nw) with the discrete leaving fluxes of the current state
@@ -433,8 +448,10 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
     if (s >= nx) return;
 
     double R[kNMom];
+#pragma unroll
     for (int m = 0; m < kNMom; ++m) R[m] = 0.0;
     for (int g = 0; g < D.ngroups; ++g)
+#pragma unroll
         for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + s];
 
     // moments of Sec. II from the raw sums (shift to the peculiar velocity xi = p - u)
@@ -479,42 +496,69 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
     cell[SC_QY * nx + s] = (T)qy;
     cell[SC_IJD * nx + s] = (T)D.inv_jdeta[s];
 
-    // equilibrium truncations at this cell; n folded into g_x
+    // g_x (eq. gx) as the projection of g/omega on h_0..h_N computed with the auxiliary rule;
+    // the exponent for the two half-lines differs only in the sign of the term linear in u
     const int qxn = D.qx, nxo = D.nxo;
     const double inv2T = 0.5 / Tm;
     const double rsT = 1.0 / sqrt(Tm);
-    for (int h = 0; h < 2; ++h) {
-        const double us = h == 0 ? ux : -ux;
-        double I[kMaxNx + 1];
+    double Ip[kMaxNx + 1], Im[kMaxNx + 1];
 #pragma unroll
-        for (int l = 0; l <= kMaxNx; ++l) I[l] = 0.0;
-        for (int k = 0; k < kAux; ++k) {
-            const double Z = D.auxZ[k];
-            const double e = (Z * Z * (Tm - 1.0) + 2.0 * Z * us - us * us) * inv2T;
-            const double wk = D.auxW[k] * exp(e) * rsT;
+    for (int l = 0; l <= kMaxNx; ++l) Ip[l] = Im[l] = 0.0;
+    for (int k = 0; k < kAux; ++k) {
+        const double Z = s_az[k];
+        const double a = (Z * Z * (Tm - 1.0) - ux * ux) * inv2T;
+        const double bb = Z * ux * (2.0 * inv2T);
+        const double wk = s_aw[k] * rsT;
+        const double ep = wk * exp(a + bb), em = wk * exp(a - bb);
 #pragma unroll
-            for (int l = 0; l <= kMaxNx; ++l)
-                if (l <= nxo) I[l] += wk * D.hZ[l * kAux + k];
-        }
-        for (int i = 0; i < qxn; ++i) {
-            double acc = 0.0;
-#pragma unroll
-            for (int l = 0; l <= kMaxNx; ++l)
-                if (l <= nxo) acc += I[l] * D.hz[l * qxn + i];
-            cell[(kNSc + h * qxn + i) * nx + s] = (T)(n * D.wx[i] * acc);
-        }
+        for (int l = 0; l <= kMaxNx; ++l)
+            if (l <= nxo) {
+                const double hz = s_hZ[l * kAux + k];
+                Ip[l] += ep * hz;
+                Im[l] += em * hz;
+            }
     }
-    {
-        const int qy = D.qy, nyo = D.nyo;
-        // c_l = coefficient of t^l in exp(u t + (T-1) t^2/2): l c_l = u c_{l-1} + (T-1) c_{l-2}
-        double cl[kMaxQy];
+    for (int i = 0; i < qxn; ++i) {
+        double ap = 0.0, am = 0.0;
+#pragma unroll
+        for (int l = 0; l <= kMaxNx; ++l)
+            if (l <= nxo) {
+                const double hz = s_hz[l * qxn + i];
+                ap += Ip[l] * hz;
+                am += Im[l] * hz;
+            }
+        const double nw = n * s_wx[i];
+        cell[(kNSc + i) * nx + s] = (T)(nw * ap);
+        cell[(kNSc + qxn + i) * nx + s] = (T)(nw * am);
+    }
+
+    // g_y (eq. gy): c_l = coefficient of t^l in exp(u t + (T-1) t^2/2), l c_l = u c_{l-1} + (T-1) c_{l-2}
+    const int nqy = D.qy, nyo = D.nyo;
+    const double tm1 = Tm - 1.0;
+    if (nyo < kCyReg) {
+        double cl[kCyReg];
         cl[0] = 1.0;
-        if (nyo >= 1) cl[1] = uy;
-        for (int l = 2; l <= nyo; ++l) cl[l] = (uy * cl[l - 1] + (Tm - 1.0) * cl[l - 2]) / l;
-        for (int j = 0; j < qy; ++j) {
+        cl[1] = uy;
+#pragma unroll
+        for (int l = 2; l < kCyReg; ++l) cl[l] = (uy * cl[l - 1] + tm1 * cl[l - 2]) * (1.0 / l);
+        for (int j = 0; j < nqy; ++j) {
             double acc = 0.0;
-            for (int l = 0; l <= nyo; ++l) acc += cl[l] * D.he[l * qy + j];
-            cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(D.wy[j] * acc);
+#pragma unroll
+            for (int l = 0; l < kCyReg; ++l)
+                if (l <= nyo) acc += cl[l] * s_he[l * nqy + j];
+            cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
+        }
+    } else {
+        for (int j = 0; j < nqy; ++j) {
+            double c2 = 1.0, c1 = uy;
+            double acc = s_he[j] + uy * s_he[nqy + j];
+            for (int l = 2; l <= nyo; ++l) {
+                const double c = (uy * c1 + tm1 * c2) / l;
+                acc += c * s_he[l * nqy + j];
+                c2 = c1;
+                c1 = c;
+            }
+            cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
         }
     }
 }
@@ -548,8 +592,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restric
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double jsum = 0.0;
-        for (int s = 0; s < nx; ++s) jsum += D.jdeta[s];
+        const double jsum = D.jsum;
         if (with_res) {
             D.dyn[DY_RES_NUM] = red[0][0];
             D.dyn[DY_RES_DEN] = red[0][1];
@@ -585,21 +628,29 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_stage(int fp32
                                   int stage, int flags, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
-    if (fp32)
-        hipLaunchKernelGGL(stage_kernel<float>, dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, stage, flags);
-    else
-        hipLaunchKernelGGL(stage_kernel<double>, dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, stage, flags);
+    if (stage < 0) {
+        if (fp32)
+            hipLaunchKernelGGL((stage_kernel<float, true>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, 0, 0);
+        else
+            hipLaunchKernelGGL((stage_kernel<double, true>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, 0, 0);
+    } else if (fp32) {
+        hipLaunchKernelGGL((stage_kernel<float, false>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, stage,
+                           flags);
+    } else {
+        hipLaunchKernelGGL((stage_kernel<double, false>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, stage,
+                           flags);
+    }
     return hipGetLastError();
 }
 
 extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int flags,
-                                 hipStream_t st)
+                                 size_t shmem, hipStream_t st)
 {
     if (ncells <= 0) return hipSuccess;
     if (fp32)
-        hipLaunchKernelGGL(cell_kernel<float>, dim3(ncells), dim3(kCellBlock), 0, st, descs, cells, flags);
+        hipLaunchKernelGGL(cell_kernel<float>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, flags);
     else
-        hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellBlock), 0, st, descs, cells, flags);
+        hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, flags);
     return hipGetLastError();
 }
 
