@@ -19,9 +19,9 @@
 using namespace hrlb;
 
 extern "C" hipError_t hrlbk_stage(int fp32, const InstDesc* descs, const TileRef* tiles, int ntiles, int grid,
-                                  int stage, int flags, hipStream_t st);
-extern "C" hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int flags,
-                                 size_t shmem, hipStream_t st);
+                                  int stage, int flags, int qy_max, hipStream_t st);
+extern "C" hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int buf,
+                                 int flags, size_t shmem, hipStream_t st);
 extern "C" hipError_t hrlbk_finalize(const InstDesc* descs, int ninst, int with_res, hipStream_t st);
 extern "C" hipError_t hrlbk_init(int fp32, const InstDesc* descs, int inst, size_t units, hipStream_t st);
 
@@ -65,7 +65,7 @@ struct hrlb_quad {
 };
 
 struct Layout {
-    size_t desc, dyn, tables, f[3], cell, fields, mom, wall, res, tiles, cells, total;
+    size_t desc, dyn, tables, f[3], cell, fields, mom, res, tiles, cells, total;
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
     int ngroups, nctiles, vpt, ncellblocks;
@@ -102,6 +102,7 @@ struct hrlb_batch {
     int ntiles, ncellblocks;
     int fp32;
     size_t shmem;
+    int qy_max;
     hipStream_t stream;
 };
 
@@ -204,9 +205,15 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
     if (!(p->Pr > 0.0) || !std::isfinite(p->Pr)) return fail(HRLB_E_INVALID, "Pr must be > 0");
     if (!std::isfinite(p->u_w) || std::fabs(p->u_w) > 2.0) return fail(HRLB_E_INVALID, "|u_w| must be <= 2");
     if (!std::isfinite(p->omega) || p->omega < 0.0 || p->omega > 2.0) return fail(HRLB_E_INVALID, "omega outside [0,2]");
-    if (p->n_cells < 8 || p->n_cells > 65536 || p->n_cells % 4 != 0)
-        return fail(HRLB_E_INVALID, "n_cells=%d must be a multiple of 4 in [8, 65536]", p->n_cells);
+    if (p->n_cells < 8 || p->n_cells > 65536 || p->n_cells % kStrip != 0)
+        return fail(HRLB_E_INVALID, "n_cells=%d must be a multiple of %d in [8, 65536]", p->n_cells, kStrip);
     if (!(p->stretch_A >= 0.0 && p->stretch_A < 1.0)) return fail(HRLB_E_INVALID, "stretch_A outside [0,1)");
+    {
+        const double es = p->precision == HRLB_FP64 ? 8.0 : 4.0;
+        const double state = 2.0 * 2.0 * q->qx * q->qy * (double)p->n_cells * es;
+        if (state >= 2147483648.0)
+            return fail(HRLB_E_INVALID, "one state buffer (%.3g bytes) must stay below 2 GiB", state);
+    }
     if (p->precision != HRLB_FP64 && p->precision != HRLB_FP32_STORE_FP64_MOM)
         return fail(HRLB_E_INVALID, "unknown precision %d", p->precision);
     if (p->rounding != HRLB_ROUND_NEAREST && p->rounding != HRLB_ROUND_STOCHASTIC)
@@ -221,7 +228,7 @@ int choose_vpt(int qx, int qy)
 {
     const int nv = 2 * qx * qy;
     int best = 1;
-    for (int d = 1; d <= std::min(qy, 8); ++d)
+    for (int d = 1; d <= std::min(std::min(qy, 8), kMaxVpt); ++d)
         if (qy % d == 0 && nv / d >= kRows) best = d;
     return best;
 }
@@ -269,8 +276,6 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     off = align256(off + sizeof(double) * kNFields * nx);
     L.mom = off;
     off = align256(off + sizeof(double) * (size_t)L.ngroups * kNMom * nx);
-    L.wall = off;
-    off = align256(off + sizeof(double) * L.ngroups * 4);
     L.res = off;
     off = align256(off + sizeof(double) * (size_t)L.nctiles * L.ngroups * 2);
     L.tiles = off;
@@ -305,16 +310,17 @@ void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<doub
 int stage_grid(int ntiles) { return std::min(ntiles, 4096); }
 
 hrlb_status enqueue_steps(int fp32, const InstDesc* descs, int ninst, const TileRef* tiles, int ntiles,
-                          const CellRef* cells, int ncellblocks, size_t shmem, long n_steps, bool check_last,
-                          hipStream_t st)
+                          const CellRef* cells, int ncellblocks, size_t shmem, int qy_max, long n_steps,
+                          bool check_last, hipStream_t st)
 {
     const int grid = stage_grid(ntiles);
     for (long s = 0; s < n_steps; ++s) {
         const bool chk = check_last && s + 1 == n_steps;
         for (int stage = 0; stage < 3; ++stage) {
             const int fl = (stage == 2 && chk) ? FLAG_RESID : 0;
-            HIP_TRY(hrlbk_stage(fp32, descs, tiles, ntiles, grid, stage, fl, st));
-            HIP_TRY(hrlbk_cell(fp32, descs, cells, ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, shmem, st));
+            HIP_TRY(hrlbk_stage(fp32, descs, tiles, ntiles, grid, stage, fl, qy_max, st));
+            HIP_TRY(hrlbk_cell(fp32, descs, cells, ncellblocks, stage == 0 ? 1 : stage == 1 ? 2 : 0,
+                               stage == 2 ? FLAG_STEP_DONE : 0, shmem, st));
         }
         if (chk) HIP_TRY(hrlbk_finalize(descs, ninst, 1, st));
     }
@@ -324,8 +330,8 @@ hrlb_status enqueue_steps(int fp32, const InstDesc* descs, int ninst, const Tile
 hrlb_status analyze_case(hrlb_case* c)
 {
     const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
-    HIP_TRY(hrlbk_stage(fp32, c->d_desc, c->d_tiles, c->ntiles, stage_grid(c->ntiles), -1, 0, c->stream));
-    HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, c->shmem, c->stream));
+    HIP_TRY(hrlbk_stage(fp32, c->d_desc, c->d_tiles, c->ntiles, stage_grid(c->ntiles), -1, 0, c->q->qy, c->stream));
+    HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, 0, c->shmem, c->stream));
     HIP_TRY(hrlbk_finalize(c->d_desc, 1, 0, c->stream));
     c->needs_analyze = false;
     return HRLB_OK;
@@ -460,7 +466,6 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.cell = ws + L.cell;
     D.fields = (double*)(ws + L.fields);
     D.mom_part = (double*)(ws + L.mom);
-    D.wall_part = (double*)(ws + L.wall);
     D.res_part = (double*)(ws + L.res);
     D.dyn = (double*)(ws + L.dyn);
     const double* tb = (const double*)(ws + L.tables);
@@ -536,7 +541,7 @@ extern "C" hrlb_status hrlb_step(hrlb_case* c, long n_steps)
     hrlb_status st0 = ensure_analyzed(c);
     if (st0 != HRLB_OK) return st0;
     hrlb_status st = enqueue_steps(c->p.precision == HRLB_FP32_STORE_FP64_MOM, c->d_desc, 1, c->d_tiles, c->ntiles,
-                                   c->d_cells, c->L.ncellblocks, c->shmem, n_steps, false, c->stream);
+                                   c->d_cells, c->L.ncellblocks, c->shmem, c->q->qy, n_steps, false, c->stream);
     if (st == HRLB_OK) c->steps_done += n_steps;
     return st;
 }
@@ -562,7 +567,7 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
     while (taken < max_steps) {
         const long n = std::min<long>(check_every, max_steps - taken);
         hrlb_status st = enqueue_steps(fp32, c->d_desc, 1, c->d_tiles, c->ntiles, c->d_cells, c->L.ncellblocks,
-                                       c->shmem, n, true, c->stream);
+                                       c->shmem, c->q->qy, n, true, c->stream);
         if (st != HRLB_OK) return st;
         HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
@@ -732,7 +737,11 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
     b->fp32 = cases[0]->p.precision == HRLB_FP32_STORE_FP64_MOM;
     b->stream = cases[0]->stream;
     b->shmem = 0;
-    for (int i = 0; i < n_cases; ++i) b->shmem = std::max(b->shmem, cases[i]->shmem);
+    b->qy_max = 0;
+    for (int i = 0; i < n_cases; ++i) {
+        b->shmem = std::max(b->shmem, cases[i]->shmem);
+        b->qy_max = std::max(b->qy_max, cases[i]->q->qy);
+    }
     std::vector<InstDesc> descs(n_cases);
     std::vector<TileRef> tiles;
     std::vector<CellRef> cells;
@@ -754,8 +763,8 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
     bool any = false;
     for (int i = 0; i < n_cases; ++i) any = any || cases[i]->needs_analyze;
     if (e == hipSuccess && any) {
-        e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, stage_grid(b->ntiles), -1, 0, b->stream);
-        if (e == hipSuccess) e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, 0, b->shmem, b->stream);
+        e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, stage_grid(b->ntiles), -1, 0, b->qy_max, b->stream);
+        if (e == hipSuccess) e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, 0, 0, b->shmem, b->stream);
         if (e == hipSuccess) e = hrlbk_finalize(b->d_descs, n_cases, 0, b->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -773,7 +782,7 @@ extern "C" hrlb_status hrlb_batch_step(hrlb_batch* b, long n_steps, int check)
     if (!b) return fail(HRLB_E_INVALID, "batch is NULL");
     if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
     hrlb_status st = enqueue_steps(b->fp32, b->d_descs, (int)b->cases.size(), b->d_tiles, b->ntiles, b->d_cells,
-                                   b->ncellblocks, b->shmem, n_steps, check != 0, b->stream);
+                                   b->ncellblocks, b->shmem, b->qy_max, n_steps, check != 0, b->stream);
     if (st == HRLB_OK)
         for (hrlb_case* c : b->cases) c->steps_done += n_steps;
     return st;
@@ -813,12 +822,13 @@ extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* s
     for (long k = 0; k < nl && st == HRLB_OK; ++k) {
         const int stage = (int)(k % 3);
         hipError_t e = hipEventRecord(ev[4 * k], b->stream);
-        if (e == hipSuccess) e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, grid, stage, 0, b->stream);
+        if (e == hipSuccess)
+            e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, grid, stage, 0, b->qy_max, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 1], b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 2], b->stream);
         if (e == hipSuccess)
-            e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, stage == 2 ? FLAG_STEP_DONE : 0, b->shmem,
-                           b->stream);
+            e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, stage == 0 ? 1 : stage == 1 ? 2 : 0,
+                           stage == 2 ? FLAG_STEP_DONE : 0, b->shmem, b->stream);
         if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 3], b->stream);
         if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profiled launch: %s", hipGetErrorString(e));
     }

@@ -10,12 +10,14 @@ namespace hrlb {
 // ---- stage kernel tiling ------------------------------------------------------------------
 // A block of kThreads threads covers kTileCells consecutive cells (kStrip per thread, kTPR
 // threads per velocity row) and kRows velocity rows.  A row walks `vpt` velocities sharing the
-// same p_x (consecutive j), so the x-advection upwind direction is uniform along a row.
+// same p_x (consecutive j), so the x-advection upwind direction is uniform along a row.  The
+// walls need 3 cells per side and 16-byte loads need n_cells to be a multiple of kStrip = 4.
 constexpr int kThreads = 256;
 constexpr int kStrip = 4;
 constexpr int kTPR = 16;
 constexpr int kRows = kThreads / kTPR;        // 16
 constexpr int kTileCells = kStrip * kTPR;     // 64
+constexpr int kMaxVpt = kTPR;                 // velocities per row are bounded by the lanes of a row
 constexpr int kMomPerPass = 4;                // moments reduced per LDS pass
 constexpr int kCellBlock = 64;                // threads per block of the per-cell kernel
 
@@ -70,7 +72,6 @@ struct InstDesc {
     void* cell;          // [kNSc + 2 qx + qy][nx] storage precision
     double* fields;      // [kNFields][nx]
     double* mom_part;    // [ngroups][kNMom][nx]
-    double* wall_part;   // [ngroups][4]: left flux, right flux, left p_y flux, right p_y flux
     double* res_part;    // [nctiles * ngroups][2]
     double* dyn;         // [kNDyn]
     const double* px;    // [2 qx]

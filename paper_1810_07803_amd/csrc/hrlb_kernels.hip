@@ -4,64 +4,131 @@
 //   stage_kernel  one pass over (cell, velocity) units: WENO-5 face values of the stage input
 //                 (diffuse-wall ghosts at the channel ends), reduced Shakhov collision, the SSP-RK3
 //                 stage combine, the store of the stage output, and FP64 partial sums of that
-//                 output's moments, wall out-fluxes and (optionally) residual, reduced per tile in
-//                 LDS in a fixed order.
+//                 output's moments (and optionally residual), reduced per tile in LDS in a fixed
+//                 order.
 //   cell_kernel   per cell: sums the partials over velocity groups, forms the moments of Sec. II,
 //                 the relaxation time of eq. (tau), the Shakhov prefactor and the truncated
 //                 equilibria of eqs. (gx), (gy) that the next stage's collision uses; per instance:
-//                 the wall densities of eq. (diffuse_nw).
-// Layout: populations [dist][v][cell] with cells contiguous; a thread owns 4 consecutive cells
-// of one velocity, a block 64 cells x 16 velocity rows.
+//                 the leaving wall fluxes and the wall densities of eq. (diffuse_nw).
+// Layout: populations [dist][v][cell] with cells contiguous.  A thread owns 4 consecutive cells of
+// one velocity and reconstructs their left faces; the right face comes from the next lane (the
+// neighbour's left face) or, at a tile edge, from a per-tile pre-pass, so every face is
+// reconstructed once per tile row.  A block covers 64 cells x 16 velocity rows; the tile's cell
+// tables (moments, equilibria) are staged in LDS.
 #include "hrlb_internal.h"
+
 
 namespace hrlb {
 
 enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2 };
 
-// ---- vector loads / stores of 4 consecutive cells ------------------------------------------
-__device__ __forceinline__ void ld4(const float* p, float (&o)[4])
-{
-    const float4 v = *reinterpret_cast<const float4*>(p);
-    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
-}
-__device__ __forceinline__ void ld4(const double* p, double (&o)[4])
-{
-    const double2 a = *reinterpret_cast<const double2*>(p);
-    const double2 b = *reinterpret_cast<const double2*>(p + 2);
-    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
-}
-__device__ __forceinline__ void st4(float* p, const float (&o)[4])
-{
-    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
-}
-__device__ __forceinline__ void st4(double* p, const double (&o)[4])
-{
-    *reinterpret_cast<double2*>(p) = make_double2(o[0], o[1]);
-    *reinterpret_cast<double2*>(p + 2) = make_double2(o[2], o[3]);
-}
+// Loads and stores through the global address space (the pointers live in descriptors, so the
+// compiler would otherwise emit flat instructions).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define HRLB_GLOBAL __attribute__((address_space(1)))
+#else
+#define HRLB_GLOBAL
+#endif
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ float fast_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ __forceinline__ double fast_div(double a, double b) { return a / b; }
-
-// WENO-5 (Jiang & Shu) face value; a..e ordered along the upwind direction, c the upwind cell.
-// The three nonlinear weights share one denominator: alpha_k (eps+b0)^2 (eps+b1)^2 (eps+b2)^2.
+// ---- loads / stores of 2 consecutive cells -----------------------------------------------------
+__device__ __forceinline__ void ld2(const float* p, float& a, float& b)
+{
+    const f2v v = *(const HRLB_GLOBAL f2v*)p;
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void ld2(const double* p, double& a, double& b)
+{
+    const d2v v = *(const HRLB_GLOBAL d2v*)p;
+    a = v.x;
+    b = v.y;
+}
+__device__ __forceinline__ void st2(float* p, float a, float b)
+{
+    f2v v;
+    v.x = a;
+    v.y = b;
+    *(HRLB_GLOBAL f2v*)p = v;
+}
+__device__ __forceinline__ void st2(double* p, double a, double b)
+{
+    d2v v;
+    v.x = a;
+    v.y = b;
+    *(HRLB_GLOBAL d2v*)p = v;
+}
 template <typename T>
-__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e)
+__device__ __forceinline__ T gld(const T* p) { return *(const HRLB_GLOBAL T*)p; }
+
+__device__ __forceinline__ float rcp6(float den) { return __builtin_amdgcn_rcpf(6.0f * den); }
+__device__ __forceinline__ double rcp6(double den) { return 1.0 / (6.0 * den); }
+
+// ---- WENO-5 (Jiang & Shu) in difference form ----------------------------------------------------
+// With the cells ordered along the upwind direction (a, b, c, d, e; c the upwind cell):
+//   dm = c - b, dp = d - c, d2m = a - 2b + c, d2c = b - 2c + d, d2p = c - 2d + e,
+//   E_x = 13/12 d2x^2 + eps,
+//   beta0 = E_m + (d2m + 2 dm)^2/4, beta1 = E_c + (dm + dp)^2/4, beta2 = E_p + (d2p - 2 dp)^2/4,
+//   candidate values q_k = c + y_k/6 with y0 = 2 d2m + 3 dm, y1 = dm + 2 dp, y2 = 3 dp - d2p,
+//   weights 0.1, 0.6, 0.3 over (eps + beta_k)^2, normalised.
+// Contraction is off so that every call site produces the same bits from the same inputs.
+#pragma clang fp contract(off)
+template <typename T>
+__device__ __forceinline__ T weno_d(T c, T dm, T dp, T d2m, T d2p, T em, T ec, T ep)
 {
-    const T eps = T(1e-6);
-    const T q0 = (T(2) * a - T(7) * b + T(11) * c) * T(1.0 / 6.0);
-    const T q1 = (-b + T(5) * c + T(2) * d) * T(1.0 / 6.0);
-    const T q2 = (T(2) * c + T(5) * d - e) * T(1.0 / 6.0);
-    const T s0 = a - T(2) * b + c, r0 = a - T(4) * b + T(3) * c;
-    const T s1 = b - T(2) * c + d, r1 = b - d;
-    const T s2 = c - T(2) * d + e, r2 = T(3) * c - T(4) * d + e;
-    const T t0 = eps + (T(13.0 / 12.0) * s0 * s0 + T(0.25) * r0 * r0);
-    const T t1 = eps + (T(13.0 / 12.0) * s1 * s1 + T(0.25) * r1 * r1);
-    const T t2 = eps + (T(13.0 / 12.0) * s2 * s2 + T(0.25) * r2 * r2);
+    const T x0 = fma(T(2), dm, d2m);
+    const T x1 = dm + dp;
+    const T x2 = fma(T(-2), dp, d2p);
+    const T t0 = fma(T(0.25) * x0, x0, em);
+    const T t1 = fma(T(0.25) * x1, x1, ec);
+    const T t2 = fma(T(0.25) * x2, x2, ep);
     const T u0 = t0 * t0, u1 = t1 * t1, u2 = t2 * t2;
-    const T a0 = T(0.1) * (u1 * u2), a1 = T(0.6) * (u0 * u2), a2 = T(0.3) * (u0 * u1);
-    return fast_div(a0 * q0 + a1 * q1 + a2 * q2, a0 + a1 + a2);
+    const T a0 = u1 * u2, a1 = T(6) * (u0 * u2), a2 = T(3) * (u0 * u1);
+    const T y0 = fma(T(2), d2m, T(3) * dm);
+    const T y1 = fma(T(2), dp, dm);
+    const T y2 = fma(T(3), dp, -d2p);
+    const T num = fma(a2, y2, fma(a1, y1, a0 * y0));
+    const T den = (a0 + a1) + a2;
+    return fma(num, rcp6(den), c);
 }
+
+template <typename T>
+__device__ __forceinline__ T e_of(T d2) { return fma(T(13.0 / 12.0) * d2, d2, T(1e-6)); }
+
+// face value from five cells in upwind order (used where no shared differences are at hand)
+template <typename T>
+__device__ __forceinline__ T weno5_cells(T a, T b, T c, T d, T e)
+{
+    const T dma = b - a, dm = c - b, dp = d - c, dpp = e - d;
+    const T d2m = dm - dma, d2c = dp - dm, d2p = dpp - dp;
+    return weno_d(c, dm, dp, d2m, d2p, e_of(d2m), e_of(d2c), e_of(d2p));
+}
+
+// Quadratic extrapolation (in cell index) through the three cells next to a wall (nodes at 0, 1, 2),
+// used for ghosts of directions leaving the domain.
+template <typename T>
+__device__ __forceinline__ T ext_p3(T y0, T y1, T y2) { return (y0 - T(3) * y1) + T(3) * y2; }         // t = 3
+template <typename T>
+__device__ __forceinline__ T ext_p4(T y0, T y1, T y2) { return (T(3) * y0 - T(8) * y1) + T(6) * y2; }  // t = 4
+template <typename T>
+__device__ __forceinline__ T ext_m1(T y0, T y1, T y2) { return (T(3) * y0 - T(3) * y1) + y2; }         // t = -1
+template <typename T>
+__device__ __forceinline__ T ext_m2(T y0, T y1, T y2) { return (T(6) * y0 - T(8) * y1) + T(3) * y2; }  // t = -2
+
+// leaving face value at the left wall (p_x < 0) from cells 0, 1, 2 with extrapolated ghosts -1, -2
+template <typename T>
+__device__ __forceinline__ T wall_face_left(T f0, T f1, T f2)
+{
+    return weno5_cells(f2, f1, f0, ext_m1(f0, f1, f2), ext_m2(f0, f1, f2));
+}
+// leaving face value at the right wall (p_x > 0) from cells nx-3, nx-2, nx-1 with ghosts nx, nx+1
+template <typename T>
+__device__ __forceinline__ T wall_face_right(T fa, T fb, T fc)
+{
+    return weno5_cells(fa, fb, fc, ext_p3(fa, fb, fc), ext_p4(fa, fb, fc));
+}
+#pragma clang fp contract(on)
 
 // counter-based 32-bit hash (integer avalanche "lowbias32", C. Wellons, 2018)
 __device__ __forceinline__ uint32_t hash32(uint32_t x)
@@ -95,16 +162,109 @@ __device__ __forceinline__ float store_round<float>(double x, int stochastic, ui
     return stochastic ? round_stochastic(x, r16) : (float)x;
 }
 
-// Quadratic extrapolation (in cell index) of the three cells next to a wall, used for the
-// ghosts of directions leaving the domain: nodes y0, y1, y2 at 0, 1, 2.
+// ---- buffer resources: 32-bit byte offsets from a base held in scalar registers ---------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef int i4v __attribute__((ext_vector_type(4)));
+constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer access on gfx9-family targets
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kBufDword3);
+}
+// four consecutive values at a byte offset (16-byte aligned for float, two 16-byte loads for double)
+__device__ __forceinline__ void bld4(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[4])
+{
+    const f4v v = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+}
+__device__ __forceinline__ void bld4(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&o)[4])
+{
+    const d2v a = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    const d2v b = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off + 16, 0, 0));
+    o[0] = a.x;
+    o[1] = a.y;
+    o[2] = b.x;
+    o[3] = b.y;
+}
+__device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&o)[4])
+{
+    f4v v;
+    v.x = o[0];
+    v.y = o[1];
+    v.z = o[2];
+    v.w = o[3];
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, uint32_t off, const double (&o)[4])
+{
+    d2v a, b;
+    a.x = o[0];
+    a.y = o[1];
+    b.x = o[2];
+    b.y = o[3];
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, a), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, b), r, (int)off + 16, 0, 0);
+}
 template <typename T>
-__device__ __forceinline__ T ext_p3(T y0, T y1, T y2) { return y0 - T(3) * y1 + T(3) * y2; }   // t = 3
+__device__ __forceinline__ T bld1(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bld1<float>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bld1<double>(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+
+// The window of a thread owning cells s0..s0+3 is w[m] = cell s0 - 4 + m, m = 0..11; its faces
+// f = 0..3 lie between cells s0+f-1 and s0+f (face 4, its right face, is the next lane's face 0).
+// Differences: dl[m] = w[m+1] - w[m], d2[m] = dl[m] - dl[m-1].
 template <typename T>
-__device__ __forceinline__ T ext_p4(T y0, T y1, T y2) { return T(3) * y0 - T(8) * y1 + T(6) * y2; }  // t = 4
-template <typename T>
-__device__ __forceinline__ T ext_m1(T y0, T y1, T y2) { return T(3) * y0 - T(3) * y1 + y2; }   // t = -1
-template <typename T>
-__device__ __forceinline__ T ext_m2(T y0, T y1, T y2) { return T(6) * y0 - T(8) * y1 + T(3) * y2; }  // t = -2
+struct Win {
+    T w[12];
+    T dl[9], d2[9], e[9];
+    // p_x > 0: faces 0..3 have upwind cell C = f + 3 and need dl[1..7], d2[2..7]
+    __device__ __forceinline__ void faces_pos(T (&F)[5])
+    {
+#pragma unroll
+        for (int m = 1; m <= 7; ++m) dl[m] = w[m + 1] - w[m];
+#pragma unroll
+        for (int m = 2; m <= 7; ++m) {
+            d2[m] = dl[m] - dl[m - 1];
+            e[m] = e_of(d2[m]);
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int C = f + 3;
+            F[f] = weno_d(w[C], dl[C - 1], dl[C], d2[C - 1], d2[C + 1], e[C - 1], e[C], e[C + 1]);
+        }
+    }
+    // p_x < 0: faces 0..3 have upwind cell C = f + 4 (cells mirrored) and need dl[2..8], d2[3..8]
+    __device__ __forceinline__ void faces_neg(T (&F)[5])
+    {
+#pragma unroll
+        for (int m = 2; m <= 8; ++m) dl[m] = w[m + 1] - w[m];
+#pragma unroll
+        for (int m = 3; m <= 8; ++m) {
+            d2[m] = dl[m] - dl[m - 1];
+            e[m] = e_of(d2[m]);
+        }
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int C = f + 4;
+            F[f] = weno_d(w[C], -dl[C], -dl[C - 1], d2[C + 1], d2[C - 1], e[C + 1], e[C], e[C - 1]);
+        }
+    }
+};
+
+// Per-tile staging of the cell tables in LDS, slot-major [slot][64 cells]: the per-cell scalars,
+// then g_y for every j of the instance, then g_x of the block's 16 rows.
+__host__ __device__ constexpr int cell_lds_slots(int qy) { return kNSc + qy + kRows; }
 
 // ANALYZE: no update; partials of the current state f[0] (used after set-up or a state upload)
 template <typename T, bool ANALYZE>
@@ -112,214 +272,274 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                                                          const TileRef* __restrict__ tiles, int ntiles,
                                                          int stage, int flags)
 {
-    __shared__ double lds_mom[kMomPerPass][kRows][kTileCells];
-    __shared__ double lds_red[kThreads / 64][6];
+    // dynamic LDS: [union of (cell tables of the tile) and (moment reduction)] + boundary faces
+    extern __shared__ __align__(16) unsigned char smem[];
+    double(*lds_mom)[kRows][kTileCells] = reinterpret_cast<double(*)[kRows][kTileCells]>(smem);
+    T* lds_cell = reinterpret_cast<T*>(smem);
+    __shared__ T lds_bface[2][kRows][kTPR];
+    __shared__ double lds_red[kThreads / 64][2];
 
     const int tid = threadIdx.x;
     const int row = tid / kTPR, strip = tid % kTPR;
-    constexpr bool analyze = ANALYZE;
-    const int in_idx = analyze ? 0 : (stage == 0 ? 0 : stage == 1 ? 1 : 2);
-    const int out_idx = analyze ? 0 : (stage == 0 ? 1 : stage == 1 ? 2 : 0);
+    const int in_idx = ANALYZE ? 0 : (stage == 0 ? 0 : stage == 1 ? 1 : 2);
+    const int out_idx = ANALYZE ? 0 : (stage == 0 ? 1 : stage == 1 ? 2 : 0);
     const double ca = stage == 1 ? 0.75 : stage == 2 ? (1.0 / 3.0) : 0.0;
     const double cb = stage == 1 ? 0.25 : stage == 2 ? (2.0 / 3.0) : 1.0;
-    const bool want_res = (flags & FLAG_RESID) && stage == 2;
+    const bool want_res = !ANALYZE && (flags & FLAG_RESID) && stage == 2;
+    constexpr uint32_t es = sizeof(T);
 
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileRef tr = tiles[t];
         const InstDesc& D = descs[tr.inst];
-        const int nx = D.nx, nv = D.nv, qx = D.qx, qy = D.qy;
-        const int cell0 = tr.ctile * kTileCells + strip * kStrip;
+        const int nx = D.nx, nv = D.nv, qx = D.qx, qy = D.qy, vpt = D.vpt;
+        const int c0 = tr.ctile * kTileCells;
+        const int s0 = c0 + strip * kStrip;
         const int seg = tr.group * kRows + row;
-        const bool active = cell0 < nx && seg < D.nseg;
-        const bool first = cell0 == 0, last = cell0 + kStrip == nx;
+        const bool row_on = seg < D.nseg;
+        const bool active = row_on && s0 < nx;
+        const bool final_tile = c0 + kTileCells >= nx;
+        const int hi = row_on ? seg / D.segs_per_line : 0;
+        const int jc = seg - hi * D.segs_per_line;
+        const double pxd = row_on ? D.px[hi] : 0.0;
+        const T px = (T)pxd;
+        const int vbase = hi * qy + jc * vpt;
+        const uint32_t state_bytes = 2u * (uint32_t)nv * (uint32_t)nx * es;
+        const __amdgpu_buffer_rsrc_t rin = make_rsrc(D.f[in_idx], state_bytes);
+        const double nwl = D.dyn[DY_NWL], nwr = D.dyn[DY_NWR];
+        const double Tw = D.Tw;
+        const int nslot = cell_lds_slots(qy);
+
+        if (!ANALYZE) {
+            // stage the tile's cell tables: scalars, g_y (all j), g_x of each row's node
+            const __amdgpu_buffer_rsrc_t rcell =
+                make_rsrc(D.cell, (uint32_t)(kNSc + 2 * qx + qy) * (uint32_t)nx * es);
+            for (int ch = tid; ch < nslot * (kTileCells / 4); ch += kThreads) {
+                const int slot = ch / (kTileCells / 4), q4 = ch % (kTileCells / 4);
+                int src;
+                if (slot < kNSc)
+                    src = slot;
+                else if (slot < kNSc + qy)
+                    src = kNSc + 2 * qx + (slot - kNSc);
+                else {
+                    const int r = slot - kNSc - qy, sg = tr.group * kRows + r;
+                    src = kNSc + (sg < D.nseg ? sg / D.segs_per_line : 0);
+                }
+                T v4[4];
+                const int cell = c0 + 4 * q4;
+                bld4(rcell, ((uint32_t)src * nx + (uint32_t)(cell < nx ? cell : 0)) * es, v4);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) lds_cell[slot * kTileCells + 4 * q4 + c] = v4[c];
+            }
+            // the face on this tile's right edge for each (row, velocity): thread (row, strip) takes
+            // velocity k = strip of its row; the edge face F < nx - 3, so no ghost is involved
+            if (!final_tile && row_on && strip < vpt) {
+                const int v = vbase + strip;
+                const int F = c0 + kTileCells;
+#pragma unroll
+                for (int dist = 0; dist < 2; ++dist) {
+                    const uint32_t rowoff = ((uint32_t)dist * nv + v) * (uint32_t)nx;
+                    T a[6];
+#pragma unroll
+                    for (int m = 0; m < 6; ++m) a[m] = bld1<T>(rin, (rowoff + F - 3 + m) * es);
+                    lds_bface[dist][row][strip] =
+                        px > T(0) ? weno5_cells(a[0], a[1], a[2], a[3], a[4]) : weno5_cells(a[5], a[4], a[3], a[2], a[1]);
+                }
+            }
+            __syncthreads();
+        }
 
         double acc[6][kStrip];
 #pragma unroll
         for (int a = 0; a < 6; ++a)
 #pragma unroll
             for (int c = 0; c < kStrip; ++c) acc[a][c] = 0.0;
-        double wflux_l = 0, wflux_r = 0, wmom_l = 0, wmom_r = 0, rnum = 0, rden = 0;
-        double pxd = 0.0;
+        double rnum = 0, rden = 0;
 
-        if (active) {
-            const int hi = seg / D.segs_per_line;
-            const int jc = seg - hi * D.segs_per_line;
-            pxd = D.px[hi];
-            const T px = (T)pxd;
-            const T* __restrict__ cell = (const T*)D.cell;
-            const T* __restrict__ fin = (const T*)D.f[in_idx];
-            const T* __restrict__ fnn = (const T*)D.f[0];
-            T* __restrict__ fout = (T*)D.f[out_idx];
-            T ux[4], uy[4], Tt[4], itau[4], AS[4], A5[4], qxv[4], qyv[4], ijd[4], Gx[4];
-            if (!analyze) {
-                ld4(cell + SC_UX * nx + cell0, ux);
-                ld4(cell + SC_UY * nx + cell0, uy);
-                ld4(cell + SC_T * nx + cell0, Tt);
-                ld4(cell + SC_INVTAU * nx + cell0, itau);
-                ld4(cell + SC_AS * nx + cell0, AS);
-                ld4(cell + SC_AS5T * nx + cell0, A5);
-                ld4(cell + SC_QX * nx + cell0, qxv);
-                ld4(cell + SC_QY * nx + cell0, qyv);
-                ld4(cell + SC_IJD * nx + cell0, ijd);
-                ld4(cell + (kNSc + hi) * nx + cell0, Gx);
-            }
-            double jw[4] = {0, 0, 0, 0};
-            if (want_res) {
-                for (int c = 0; c < 4; ++c) jw[c] = D.jdeta[cell0 + c];
-            }
-            const double nwl = D.dyn[DY_NWL], nwr = D.dyn[DY_NWR];
-            const double Tw = D.Tw;
+        if (row_on) {
+            const __amdgpu_buffer_rsrc_t rfn = make_rsrc(D.f[0], state_bytes);
+            const __amdgpu_buffer_rsrc_t rout = make_rsrc(D.f[out_idx], state_bytes);
+            const int sc = active ? s0 : 0;  // idle lanes read cells 0..3
+            const bool first = s0 == 0, last = s0 + kStrip == nx;
+            const uint32_t oL = (uint32_t)(active && !first ? s0 - 4 : sc) * es;
+            const uint32_t oC = (uint32_t)sc * es;
+            const uint32_t oR = (uint32_t)(active && !last ? s0 + 4 : sc) * es;
+            const uint32_t rowstep = (uint32_t)nx * es;
+            const uint32_t chi_off = (uint32_t)nv * rowstep;
+            uint32_t rowoff = (uint32_t)vbase * rowstep;
+            double jw[kStrip] = {0, 0, 0, 0};
+            if (want_res && active)
+#pragma unroll
+                for (int c = 0; c < kStrip; ++c) jw[c] = D.jdeta[s0 + c];
             const double dt = D.dt;
             uint32_t rkey = 0;
-            if (D.rounding) {
+            if (!ANALYZE && D.rounding) {
                 const uint32_t stepc = (uint32_t)D.dyn[DY_STEP];
                 rkey = hash32(D.seed ^ hash32(stepc * 3u + (uint32_t)stage + 0x9e3779b9u));
             }
-            const int vbase = hi * qy + jc * D.vpt;
-            for (int k = 0; k < D.vpt; ++k) {
+            const int lc = strip * kStrip;  // first cell of this thread inside the tile (LDS column)
+            for (int k = 0; k < vpt; ++k, rowoff += rowstep) {
                 const int v = vbase + k;
                 const int j = v - hi * qy;
                 const double pyd = D.py[j];
                 const T py = (T)pyd;
-                T wp[12], wc[12];
+                Win<T> P, X;
                 {
-                    const T* rp = fin + (size_t)v * nx;
-                    const T* rc = fin + ((size_t)nv + v) * nx;
                     T tmp[4];
-                    ld4(rp + (first ? cell0 : cell0 - 4), tmp);
-                    for (int c = 0; c < 4; ++c) wp[c] = tmp[c];
-                    ld4(rp + cell0, tmp);
-                    for (int c = 0; c < 4; ++c) wp[4 + c] = tmp[c];
-                    ld4(rp + (last ? cell0 : cell0 + 4), tmp);
-                    for (int c = 0; c < 4; ++c) wp[8 + c] = tmp[c];
-                    ld4(rc + (first ? cell0 : cell0 - 4), tmp);
-                    for (int c = 0; c < 4; ++c) wc[c] = tmp[c];
-                    ld4(rc + cell0, tmp);
-                    for (int c = 0; c < 4; ++c) wc[4 + c] = tmp[c];
-                    ld4(rc + (last ? cell0 : cell0 + 4), tmp);
-                    for (int c = 0; c < 4; ++c) wc[8 + c] = tmp[c];
+                    bld4(rin, rowoff + oL, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) P.w[c] = tmp[c];
+                    bld4(rin, rowoff + oC, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) P.w[4 + c] = tmp[c];
+                    bld4(rin, rowoff + oR, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) P.w[8 + c] = tmp[c];
+                    bld4(rin, chi_off + rowoff + oL, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) X.w[c] = tmp[c];
+                    bld4(rin, chi_off + rowoff + oC, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) X.w[4 + c] = tmp[c];
+                    bld4(rin, chi_off + rowoff + oR, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) X.w[8 + c] = tmp[c];
                 }
-                T op[4], oc[4];
-                double ope[4], oce[4];  // FP64 value before rounding to the storage type
-                if (analyze) {
-                    for (int c = 0; c < 4; ++c) {
-                        op[c] = wp[4 + c];
-                        oc[c] = wc[4 + c];
+                T op[kStrip], oc[kStrip];
+                if (ANALYZE) {
+#pragma unroll
+                    for (int c = 0; c < kStrip; ++c) {
+                        op[c] = P.w[4 + c];
+                        oc[c] = X.w[4 + c];
                     }
                 } else {
-                    T fnp[4], fnc[4];
+                    T fnp[4] = {T(0), T(0), T(0), T(0)}, fnc[4] = {T(0), T(0), T(0), T(0)};
                     if (stage > 0) {
-                        ld4(fnn + (size_t)v * nx + cell0, fnp);
-                        ld4(fnn + ((size_t)nv + v) * nx + cell0, fnc);
+                        bld4(rfn, rowoff + oC, fnp);
+                        bld4(rfn, chi_off + rowoff + oC, fnc);
                     }
                     const T phiwl = (T)(nwl * D.gw_l[v]), phiwr = (T)(nwr * D.gw_r[v]);
                     const T chiwl = (T)(Tw * nwl * D.gw_l[v]), chiwr = (T)(Tw * nwr * D.gw_r[v]);
+                    // ghosts: entering directions take the wall populations, leaving ones the
+                    // quadratic extrapolation of the three cells next to the wall
                     T Fp[5], Fc[5];
                     if (px > T(0)) {
                         if (first) {
-                            wp[1] = wp[2] = wp[3] = phiwl;
-                            wc[1] = wc[2] = wc[3] = chiwl;
+                            P.w[1] = P.w[2] = P.w[3] = phiwl;
+                            X.w[1] = X.w[2] = X.w[3] = chiwl;
                         }
                         if (last) {
-                            wp[8] = ext_p3(wp[5], wp[6], wp[7]);
-                            wp[9] = ext_p4(wp[5], wp[6], wp[7]);
-                            wc[8] = ext_p3(wc[5], wc[6], wc[7]);
-                            wc[9] = ext_p4(wc[5], wc[6], wc[7]);
+                            P.w[8] = ext_p3(P.w[5], P.w[6], P.w[7]);
+                            P.w[9] = ext_p4(P.w[5], P.w[6], P.w[7]);
+                            X.w[8] = ext_p3(X.w[5], X.w[6], X.w[7]);
+                            X.w[9] = ext_p4(X.w[5], X.w[6], X.w[7]);
                         }
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) {
-                            Fp[f] = weno5(wp[f + 1], wp[f + 2], wp[f + 3], wp[f + 4], wp[f + 5]);
-                            Fc[f] = weno5(wc[f + 1], wc[f + 2], wc[f + 3], wc[f + 4], wc[f + 5]);
-                        }
+                        P.faces_pos(Fp);
+                        X.faces_pos(Fc);
                         if (first) {
                             Fp[0] = phiwl;
                             Fc[0] = chiwl;
                         }
                     } else {
                         if (first) {
-                            wp[3] = ext_m1(wp[4], wp[5], wp[6]);
-                            wp[2] = ext_m2(wp[4], wp[5], wp[6]);
-                            wc[3] = ext_m1(wc[4], wc[5], wc[6]);
-                            wc[2] = ext_m2(wc[4], wc[5], wc[6]);
+                            P.w[3] = ext_m1(P.w[4], P.w[5], P.w[6]);
+                            P.w[2] = ext_m2(P.w[4], P.w[5], P.w[6]);
+                            X.w[3] = ext_m1(X.w[4], X.w[5], X.w[6]);
+                            X.w[2] = ext_m2(X.w[4], X.w[5], X.w[6]);
                         }
                         if (last) {
-                            wp[8] = wp[9] = wp[10] = phiwr;
-                            wc[8] = wc[9] = wc[10] = chiwr;
+                            P.w[8] = P.w[9] = P.w[10] = phiwr;
+                            X.w[8] = X.w[9] = X.w[10] = chiwr;
                         }
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) {
-                            Fp[f] = weno5(wp[f + 6], wp[f + 5], wp[f + 4], wp[f + 3], wp[f + 2]);
-                            Fc[f] = weno5(wc[f + 6], wc[f + 5], wc[f + 4], wc[f + 3], wc[f + 2]);
+                        P.faces_neg(Fp);
+                        X.faces_neg(Fc);
+                        if (first) {
+                            Fp[0] = wall_face_left(P.w[4], P.w[5], P.w[6]);
+                            Fc[0] = wall_face_left(X.w[4], X.w[5], X.w[6]);
                         }
-                        if (last) {
+                    }
+                    // right face: the next lane's left face, the pre-pass value at a tile edge, or
+                    // the wall face at the end of the channel
+                    Fp[4] = __shfl_down(Fp[0], 1, kTPR);
+                    Fc[4] = __shfl_down(Fc[0], 1, kTPR);
+                    if (strip == kTPR - 1 && !final_tile) {
+                        Fp[4] = lds_bface[0][row][k];
+                        Fc[4] = lds_bface[1][row][k];
+                    }
+                    if (last) {
+                        if (px > T(0)) {
+                            Fp[4] = wall_face_right(P.w[5], P.w[6], P.w[7]);
+                            Fc[4] = wall_face_right(X.w[5], X.w[6], X.w[7]);
+                        } else {
                             Fp[4] = phiwr;
                             Fc[4] = chiwr;
                         }
                     }
-                    T Gy[4];
-                    ld4(cell + (kNSc + 2 * qx + j) * nx + cell0, Gy);
-                    uint32_t rbits[4] = {0, 0, 0, 0};
+                    uint32_t rbits[kStrip] = {0, 0, 0, 0};
                     if (D.rounding) {
-                        const uint32_t base = rkey ^ ((uint32_t)v * 0x85ebca6bu) ^ ((uint32_t)cell0 * 0xc2b2ae35u);
-                        for (int q = 0; q < 4; ++q) rbits[q] = hash32(base + (uint32_t)q);
-                    }
+                        const uint32_t base = rkey ^ ((uint32_t)v * 0x85ebca6bu) ^ ((uint32_t)s0 * 0xc2b2ae35u);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        const T p = wp[4 + c], x = wc[4 + c];
+                        for (int c = 0; c < kStrip; ++c) rbits[c] = hash32(base + (uint32_t)c);
+                    }
+                    int lcol = lc;
+                    // an opaque column index keeps the compiler from hoisting the per-cell terms out of
+                    // the velocity loop into registers (they stay in LDS; occupancy 3 instead of 2)
+                    __asm__ volatile("" : "+v"(lcol));
+                    const T* Lc = lds_cell + lcol;
+#pragma unroll
+                    for (int c = 0; c < kStrip; ++c) {
+                        const T p = P.w[4 + c], x = X.w[4 + c];
+                        const T ux = Lc[SC_UX * kTileCells + c], uy = Lc[SC_UY * kTileCells + c];
+                        const T Tt = Lc[SC_T * kTileCells + c], itau = Lc[SC_INVTAU * kTileCells + c];
+                        const T AS = Lc[SC_AS * kTileCells + c], A5 = Lc[SC_AS5T * kTileCells + c];
+                        const T qxv = Lc[SC_QX * kTileCells + c], qyv = Lc[SC_QY * kTileCells + c];
+                        const T ijd = Lc[SC_IJD * kTileCells + c];
+                        const T gy = Lc[(kNSc + j) * kTileCells + c];
+                        const T gx = Lc[(kNSc + qy + row) * kTileCells + c];
                         // reduced Shakhov collision, Sec. II
-                        const T xx = px - ux[c], xy = py - uy[c];
+                        const T xx = px - ux, xy = py - uy;
                         const T x2 = xx * xx + xy * xy;
-                        const T qxi = qxv[c] * xx + qyv[c] * xy;
-                        const T sp = qxi * (A5[c] * x2 - T(0.8) * AS[c]);
-                        const T sc = qxi * (A5[c] * x2 - T(0.4) * AS[c]);
-                        const T feq = Gx[c] * Gy[c];
+                        const T qxi = qxv * xx + qyv * xy;
+                        const T sp = qxi * (A5 * x2 - T(0.8) * AS);
+                        const T sch = qxi * (A5 * x2 - T(0.4) * AS);
+                        const T feq = gx * gy;
                         const T tp = feq + feq * sp;
-                        const T tc = Tt[c] * (feq + feq * sc);
-                        const T Lp = -px * (Fp[c + 1] - Fp[c]) * ijd[c] + (tp - p) * itau[c];
-                        const T Lc = -px * (Fc[c + 1] - Fc[c]) * ijd[c] + (tc - x) * itau[c];
-                        const double fnpd = stage > 0 ? (double)fnp[c] : 0.0;
-                        const double fncd = stage > 0 ? (double)fnc[c] : 0.0;
+                        const T tc = Tt * (feq + feq * sch);
+                        const T Lp = -px * (Fp[c + 1] - Fp[c]) * ijd + (tp - p) * itau;
+                        const T Lx = -px * (Fc[c + 1] - Fc[c]) * ijd + (tc - x) * itau;
                         // SSP-RK3 stage: out = a f^n + b (f_in + dt L(f_in)), combined in FP64
-                        ope[c] = ca * fnpd + cb * ((double)p + dt * (double)Lp);
-                        oce[c] = ca * fncd + cb * ((double)x + dt * (double)Lc);
-                        op[c] = store_round<T>(ope[c], D.rounding, rbits[c]);
-                        oc[c] = store_round<T>(oce[c], D.rounding, rbits[c] >> 16);
+                        const double fnpd = (double)fnp[c], fncd = (double)fnc[c];
+                        const double ope = ca * fnpd + cb * ((double)p + dt * (double)Lp);
+                        const double oce = ca * fncd + cb * ((double)x + dt * (double)Lx);
+                        op[c] = store_round<T>(ope, D.rounding, rbits[c]);
+                        oc[c] = store_round<T>(oce, D.rounding, rbits[c] >> 16);
                         if (want_res) {
-                            const double dp = ope[c] - fnpd, dc = oce[c] - fncd;
+                            const double dp = ope - fnpd, dc = oce - fncd;
                             rnum += jw[c] * (dp * dp + dc * dc);
                             rden += jw[c] * (fnpd * fnpd + fncd * fncd);
                         }
                     }
-                    st4(fout + (size_t)v * nx + cell0, op);
-                    st4(fout + ((size_t)nv + v) * nx + cell0, oc);
+                    if (active) {
+                        bst4(rout, rowoff + oC, op);
+                        bst4(rout, chi_off + rowoff + oC, oc);
+                    }
                 }
-                // moments of the output (FP64): sums over this row's j of phi p_y^a and chi p_y^b
-                const double py2 = pyd * pyd, py3 = py2 * pyd;
+                if (active) {
+                    // moments of the output (FP64): sums over this row's j of phi p_y^a and chi p_y^b
+                    const double py2 = pyd * pyd, py3 = py2 * pyd;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const double o = (double)op[c], x = (double)oc[c];
-                    acc[0][c] += o;
-                    acc[1][c] += pyd * o;
-                    acc[2][c] += py2 * o;
-                    acc[3][c] += py3 * o;
-                    acc[4][c] += x;
-                    acc[5][c] += pyd * x;
-                }
-                // leaving face value of the output at a wall (eq. diffuse_nw for the next stage)
-                if (last && pxd > 0) {
-                    const T o1 = op[1], o2 = op[2], o3 = op[3];
-                    const T F = weno5(o1, o2, o3, ext_p3(o1, o2, o3), ext_p4(o1, o2, o3));
-                    wflux_r += pxd * (double)F;
-                    wmom_r += pxd * pyd * (double)F;
-                }
-                if (first && pxd < 0) {
-                    const T o0 = op[0], o1 = op[1], o2 = op[2];
-                    const T F = weno5(o2, o1, o0, ext_m1(o0, o1, o2), ext_m2(o0, o1, o2));
-                    wflux_l += pxd * (double)F;
-                    wmom_l += pxd * pyd * (double)F;
+                    for (int c = 0; c < kStrip; ++c) {
+                        const double o = (double)op[c], x = (double)oc[c];
+                        acc[0][c] += o;
+                        acc[1][c] += pyd * o;
+                        acc[2][c] += py2 * o;
+                        acc[3][c] += py3 * o;
+                        acc[4][c] += x;
+                        acc[5][c] += pyd * x;
+                    }
                 }
             }
         }
+        if (!ANALYZE) __syncthreads();  // the LDS region switches from cell tables to moment sums
 
         // ---- moments: combine the row sums with the powers of p_x, reduce rows in LDS ----------
         double m11[kNMom][kStrip];
@@ -356,7 +576,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
             {
                 const int mm = tid / kTileCells, cc = tid % kTileCells;
                 const int m = pass * kMomPerPass + mm;
-                const int cellx = tr.ctile * kTileCells + cc;
+                const int cellx = c0 + cc;
                 if (m < kNMom && cellx < nx) {
                     double s = 0.0;
 #pragma unroll
@@ -367,36 +587,22 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
             __syncthreads();
         }
 
-        // ---- wall out-fluxes and residual: block sums in a fixed order -------------------------
-        const bool has_l = tr.ctile == 0, has_r = tr.ctile == D.nctiles - 1;
-        if (has_l || has_r || want_res) {
-            double vals[6] = {wflux_l, wflux_r, wmom_l, wmom_r, rnum, rden};
+        // ---- residual partials: block sums in a fixed order ------------------------------------
+        if (want_res) {
+            double vals[2] = {rnum, rden};
             const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
+            for (int q = 0; q < 2; ++q) {
                 double s = vals[q];
                 for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
                 if (lane == 0) lds_red[wave][q] = s;
             }
             __syncthreads();
             if (tid == 0) {
-                double tot[6];
-                for (int q = 0; q < 6; ++q) {
+                for (int q = 0; q < 2; ++q) {
                     double s = 0.0;
                     for (int w = 0; w < kThreads / 64; ++w) s += lds_red[w][q];
-                    tot[q] = s;
-                }
-                if (has_l) {
-                    D.wall_part[tr.group * 4 + 0] = tot[0];
-                    D.wall_part[tr.group * 4 + 2] = tot[2];
-                }
-                if (has_r) {
-                    D.wall_part[tr.group * 4 + 1] = tot[1];
-                    D.wall_part[tr.group * 4 + 3] = tot[3];
-                }
-                if (want_res) {
-                    D.res_part[tr.tile_id * 2 + 0] = tot[4];
-                    D.res_part[tr.tile_id * 2 + 1] = tot[5];
+                    D.res_part[tr.tile_id * 2 + q] = s;
                 }
             }
             __syncthreads();
@@ -407,9 +613,44 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 // ---- per-cell kernel --------------------------------------------------------------------------
 constexpr int kCyReg = 32;  // expansion orders N_y below this keep their coefficients in registers
 
+// leaving fluxes through one wall (eq. diffuse_nw): block-wide sums over the leaving directions of
+// p_x F and p_x p_y F, F the wall face value of the current state; fixed-order reduction
+template <typename T>
+__device__ void wall_sums(const InstDesc& D, const T* f, bool right, double& flux, double& mom)
+{
+    __shared__ double red[kCellBlock / 64][2];
+    const int nx = D.nx, qx = D.qx, qy = D.qy, half = qx * qy;
+    double a = 0.0, b = 0.0;
+    for (int u = threadIdx.x; u < half; u += blockDim.x) {
+        const int v = right ? u : half + u;  // right wall: p_x > 0 leave; left wall: p_x < 0 leave
+        const T* r = f + (size_t)v * nx;
+        const T F = right ? wall_face_right(r[nx - 3], r[nx - 2], r[nx - 1]) : wall_face_left(r[0], r[1], r[2]);
+        const double pxv = D.px[v / qy], pyv = D.py[v % qy];
+        a += pxv * (double)F;
+        b += pxv * pyv * (double)F;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wave][0] = a;
+        red[wave][1] = b;
+    }
+    __syncthreads();
+    flux = 0.0;
+    mom = 0.0;
+    for (int w = 0; w < kCellBlock / 64; ++w) {
+        flux += red[w][0];
+        mom += red[w][1];
+    }
+    __syncthreads();  // red may be reused by a second call in the same block
+}
+
 template <typename T>
 __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __restrict__ descs,
-                                                          const CellRef* __restrict__ cells, int flags)
+                                                          const CellRef* __restrict__ cells, int buf, int flags)
 {
     extern __shared__ double ktab[];
     const CellRef cr = cells[blockIdx.x];
@@ -429,21 +670,26 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
     const double* s_hZ = ktab + (D.hZ - gbase);
     const double* s_he = ktab + (D.he - gbase);
 
-    if (cr.cell0 == 0 && threadIdx.x == 0) {
-        // eq. (diffuse_nw) with the discrete leaving fluxes of the current state
-        double fl = 0, fr = 0, ml = 0, mr = 0;
-        for (int g = 0; g < D.ngroups; ++g) {
-            fl += D.wall_part[g * 4 + 0];
-            fr += D.wall_part[g * 4 + 1];
-            ml += D.wall_part[g * 4 + 2];
-            mr += D.wall_part[g * 4 + 3];
+    // walls: the block holding cell 0 does the left wall, the one holding cell nx-1 the right wall
+    const T* fcur = (const T*)D.f[buf];
+    if (cr.cell0 == 0) {
+        double fl, ml;
+        wall_sums<T>(D, fcur, false, fl, ml);
+        if (threadIdx.x == 0) {
+            const double nwl = -fl / D.den_l;
+            D.dyn[DY_NWL] = nwl;
+            D.dyn[DY_SHEAR_L] = ml + nwl * D.mom_l;
+            if (flags & FLAG_STEP_DONE) D.dyn[DY_STEP] += 1.0;
         }
-        const double nwl = -fl / D.den_l, nwr = -fr / D.den_r;
-        D.dyn[DY_NWL] = nwl;
-        D.dyn[DY_NWR] = nwr;
-        D.dyn[DY_SHEAR_L] = ml + nwl * D.mom_l;
-        D.dyn[DY_SHEAR_R] = mr + nwr * D.mom_r;
-        if (flags & FLAG_STEP_DONE) D.dyn[DY_STEP] += 1.0;
+    }
+    if (cr.cell0 + kCellBlock >= nx) {
+        double fr, mr;
+        wall_sums<T>(D, fcur, true, fr, mr);
+        if (threadIdx.x == 0) {
+            const double nwr = -fr / D.den_r;
+            D.dyn[DY_NWR] = nwr;
+            D.dyn[DY_SHEAR_R] = mr + nwr * D.mom_r;
+        }
     }
     if (s >= nx) return;
 
@@ -624,33 +870,43 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
 // ---- host-callable launchers (C linkage inside the library) --------------------------------------
 using namespace hrlb;
 
+// dynamic LDS of the stage kernel for a batch whose largest full-range order is qy_max
+extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_stage_lds(int fp32, int qy_max)
+{
+    const size_t es = fp32 ? sizeof(float) : sizeof(double);
+    const size_t cells = (size_t)cell_lds_slots(qy_max) * kTileCells * es;
+    const size_t moms = sizeof(double) * kMomPerPass * kRows * kTileCells;
+    return cells > moms ? cells : moms;
+}
+
 extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_stage(int fp32, const InstDesc* descs, const TileRef* tiles, int ntiles, int grid,
-                                  int stage, int flags, hipStream_t st)
+                                  int stage, int flags, int qy_max, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
+    const size_t lds = hrlbk_stage_lds(fp32, qy_max);
     if (stage < 0) {
         if (fp32)
-            hipLaunchKernelGGL((stage_kernel<float, true>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, 0, 0);
+            hipLaunchKernelGGL((stage_kernel<float, true>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0, 0);
         else
-            hipLaunchKernelGGL((stage_kernel<double, true>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, 0, 0);
+            hipLaunchKernelGGL((stage_kernel<double, true>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0, 0);
     } else if (fp32) {
-        hipLaunchKernelGGL((stage_kernel<float, false>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, stage,
+        hipLaunchKernelGGL((stage_kernel<float, false>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage,
                            flags);
     } else {
-        hipLaunchKernelGGL((stage_kernel<double, false>), dim3(grid), dim3(kThreads), 0, st, descs, tiles, ntiles, stage,
+        hipLaunchKernelGGL((stage_kernel<double, false>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage,
                            flags);
     }
     return hipGetLastError();
 }
 
-extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int flags,
-                                 size_t shmem, hipStream_t st)
+extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int buf,
+                                 int flags, size_t shmem, hipStream_t st)
 {
     if (ncells <= 0) return hipSuccess;
     if (fp32)
-        hipLaunchKernelGGL(cell_kernel<float>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, flags);
+        hipLaunchKernelGGL(cell_kernel<float>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, buf, flags);
     else
-        hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, flags);
+        hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, buf, flags);
     return hipGetLastError();
 }
 

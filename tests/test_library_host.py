@@ -50,7 +50,7 @@ def test_invalid_arguments_are_rejected_with_a_message():
         hrlb.Quadrature(2, 4)
     assert ei.value.status == hrlb.HRLB_E_INVALID
     q = hrlb.Quadrature(4, 4)
-    for bad in (dict(ncell=30), dict(ncell=4), dict(delta=-1.0), dict(stretch_A=1.0), dict(Tw=0.0)):
+    for bad in (dict(ncell=31), dict(ncell=6), dict(delta=-1.0), dict(stretch_A=1.0), dict(Tw=0.0)):
         kw = dict(delta=1.0, uw=0.1, ncell=32)
         kw.update(bad)
         with pytest.raises(hrlb.HrlbError) as ei:
