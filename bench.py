@@ -44,19 +44,23 @@ def _instances(spec):
     return [d]
 
 
-def _build(spec, insts):
+def _build(spec, insts, tune: bool):
+    """Cases of the workload; a single instance gets its stage-kernel tiling from the autotuner."""
     from paper_1810_07803_amd import hrlb
 
-    quads, cases = {}, []
+    quads, cases, tuned = {}, [], None
     for d in insts:
         key = (d["Qx"], d["Qy"])
         if key not in quads:
             quads[key] = hrlb.Quadrature(d["Qx"], d["Qy"])
-        p = hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
-                             Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
-                             precision=spec["precision"], rounding=spec["rounding"], seed=d.get("seed", 0))
-        cases.append(hrlb.Case(quads[key], p))
-    return quads, cases, hrlb.Batch(cases)
+        kw = dict(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
+                  Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
+                  precision=spec["precision"], rounding=spec["rounding"], seed=d.get("seed", 0))
+        if tune and len(insts) == 1:
+            tuned = hrlb.tune_plan(quads[key], hrlb.make_params(**kw), n_steps=10)
+            kw["tile_vpt"], kw["cell_lanes"] = tuned[0], tuned[1]
+        cases.append(hrlb.Case(quads[key], hrlb.make_params(**kw)))
+    return quads, cases, hrlb.Batch(cases), tuned
 
 
 def _cpu_baseline(insts, budget_s: float):
@@ -97,6 +101,9 @@ def main(argv=None):
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the tiling autotuner for single instances")
+    ap.add_argument("--graph-steps", type=int, default=0,
+                    help="steps per captured HIP graph (0 launches every kernel directly)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
@@ -114,8 +121,9 @@ def main(argv=None):
     spec = WORKLOADS[args.workload]
     insts = _instances(spec)
     print(f"# building {len(insts)} instance(s) of {args.workload}", file=sys.stderr, flush=True)
-    quads, cases, batch = _build(spec, insts)
+    quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune)
     units = sum(c.nv * c.ncell for c in cases)
+    batch.set_graph_steps(args.graph_steps)
     stream = torch.cuda.current_stream()
 
     batch.step(args.warmup)
@@ -172,6 +180,7 @@ def main(argv=None):
         "moments_dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "instances": len(cases), "units_per_step": units,
+                   "graph_steps": args.graph_steps, "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
                    "parallelism": "single GPU, instances batched per launch"},
         "wall_s_timed": wall,
         "roofline": roofline,

@@ -82,6 +82,12 @@ typedef struct {
     double cfl;       /* used when dt <= 0: dt = min(cfl min(J deta)/max|p_x|, tau_w/2)       */
     double dt;        /* time step; <= 0 selects the rule above                               */
     unsigned seed;    /* key of the counter-based generator used by stochastic rounding       */
+    int tile_vpt;     /* velocities per thread row of the stage kernel: a divisor of Qy up to  */
+                      /* 16; 0 = automatic (largest divisor <= 8 that fills a tile's 16 rows). */
+                      /* The choice fixes the summation order of the moments, so a case gives  */
+                      /* bitwise the same numbers alone and in any batch for a given tile_vpt. */
+    int cell_lanes;   /* lanes per cell of the per-cell kernel: 1, 2, 4, 8 or 16; 0 = automatic */
+                      /* (about 2 Qx / 8).  Also part of the plan that fixes summation order.   */
 } hrlb_case_params;
 
 /* Device workspace size (bytes) needed by a case with these parameters. */
@@ -105,6 +111,16 @@ typedef struct {
     double wall_s;     /* wall-clock seconds spent in this call                              */
     double mass_drift; /* (mass - initial mass)/initial mass, mass = sum_s J_s deta n_s      */
 } hrlb_steady_info;
+
+/* Autotuner of the kernel plan of one case: a coordinate search, first over tile_vpt (divisors
+ * of Qy up to 16) with the given cell_lanes, then over cell_lanes (1, 2, 4, 8, 16) with the best
+ * tile_vpt.  Each candidate is created in the caller's workspace (size from
+ * hrlb_tune_workspace_bytes) and timed over n_steps steps with HIP events after one warm-up step.
+ * Returns the fastest plan and its ms/step; the workspace contents are scratch afterwards.
+ * Synchronous. */
+hrlb_status hrlb_tune_workspace_bytes(const hrlb_quad *q, const hrlb_case_params *p, size_t *bytes);
+hrlb_status hrlb_tune_plan(const hrlb_quad *q, const hrlb_case_params *p, void *dev_workspace, size_t ws_bytes,
+                           void *hip_stream, int n_steps, int *best_vpt, int *best_lanes, double *best_ms_per_step);
 
 /* Runs blocks of check_every steps until the stop criterion drops below tol
  * (HRLB_STOP_RESIDUAL: the residual above; HRLB_STOP_PXY: the relative drift rate of the
@@ -148,6 +164,13 @@ hrlb_status hrlb_batch_step(hrlb_batch *b, long n_steps, int check);
 /* Synchronous: residual[i], pxy_mean[i] of case i from the last checked step (NULL allowed). */
 hrlb_status hrlb_batch_poll(hrlb_batch *b, double *residual, double *pxy_mean);
 void hrlb_batch_free(hrlb_batch *b);
+
+/* Step blocks of this many steps are captured once as a HIP graph (on a library-private stream)
+ * and replayed on the case's or batch's stream; 0 or 1 launches every kernel directly (default:
+ * direct launches measured faster than graph replay on MI355X with ROCm 7).
+ * The graph holds the launch arguments of the case/batch, so it stays valid until it is freed. */
+hrlb_status hrlb_case_set_graph_steps(hrlb_case *c, int steps_per_graph);
+hrlb_status hrlb_batch_set_graph_steps(hrlb_batch *b, int steps_per_graph);
 
 /* Profiling: runs n_steps steps of the batch like hrlb_batch_step, with a HIP event pair recorded
  * on the batch's stream around every kernel launch, then waits and returns the mean duration (ms)

@@ -50,6 +50,31 @@ hrlb_status fail(hrlb_status st, const char* fmt, ...)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// launch parameters of a case or a batch, with its cached step-block graphs
+struct Launcher {
+    int fp32 = 0;
+    const InstDesc* descs = nullptr;
+    int ninst = 0;
+    const TileRef* tiles = nullptr;
+    int ntiles = 0;
+    const CellRef* cells = nullptr;
+    int ncellblocks = 0;
+    size_t shmem = 0;
+    int qy_max = 0;
+    hipStream_t stream = nullptr;
+    int graph_steps = 0;  // steps per captured graph; < 2 launches directly (faster on this stack)
+    int graph_len = 0;
+    hipGraphExec_t graph_plain = nullptr, graph_check = nullptr;
+    void drop_graphs()
+    {
+        if (graph_plain) (void)hipGraphExecDestroy(graph_plain);
+        if (graph_check) (void)hipGraphExecDestroy(graph_check);
+        graph_plain = graph_check = nullptr;
+        graph_len = 0;
+    }
+    ~Launcher() { drop_graphs(); }
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------------
@@ -68,7 +93,7 @@ struct Layout {
     size_t desc, dyn, tables, f[3], cell, fields, mom, res, tiles, cells, total;
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
-    int ngroups, nctiles, vpt, ncellblocks;
+    int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
 };
 
 struct hrlb_case {
@@ -92,6 +117,7 @@ struct hrlb_case {
     double pxy_prev;
     bool has_prev_pxy;
     bool needs_analyze;  // moments/tables of the stored state not computed yet
+    Launcher run;
 };
 
 struct hrlb_batch {
@@ -104,6 +130,7 @@ struct hrlb_batch {
     size_t shmem;
     int qy_max;
     hipStream_t stream;
+    Launcher run;
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -220,12 +247,18 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
         return fail(HRLB_E_INVALID, "unknown rounding %d", p->rounding);
     if (p->dt <= 0.0 && !(p->cfl > 0.0 && p->cfl <= 2.0)) return fail(HRLB_E_INVALID, "cfl must be in (0,2] when dt <= 0");
     if (!std::isfinite(p->dt)) return fail(HRLB_E_INVALID, "dt not finite");
+    if (p->tile_vpt < 0 || p->tile_vpt > kMaxVpt || (p->tile_vpt > 0 && q->qy % p->tile_vpt != 0))
+        return fail(HRLB_E_INVALID, "tile_vpt=%d must be 0 or a divisor of Qy=%d up to %d", p->tile_vpt, q->qy, kMaxVpt);
+    if (p->cell_lanes < 0 || p->cell_lanes > kMaxCellLanes || (p->cell_lanes & (p->cell_lanes - 1)))
+        return fail(HRLB_E_INVALID, "cell_lanes=%d must be 0 or a power of two up to %d", p->cell_lanes, kMaxCellLanes);
     return HRLB_OK;
 }
 
-// velocities per row: largest divisor of qy not above 8 that still fills the 16 rows of a group
-int choose_vpt(int qx, int qy)
+// velocities per row: the requested divisor, or the largest divisor of qy not above 8 that still
+// fills the 16 rows of a group
+int choose_vpt(int qx, int qy, int requested)
 {
+    if (requested > 0) return requested;
     const int nv = 2 * qx * qy;
     int best = 1;
     for (int d = 1; d <= std::min(std::min(qy, 8), kMaxVpt); ++d)
@@ -233,16 +266,26 @@ int choose_vpt(int qx, int qy)
     return best;
 }
 
+// lanes per cell of the per-cell kernel: about a quarter of the x nodes of one half-line
+int auto_cell_lanes(int qx)
+{
+    int l = 1;
+    while (l < kMaxCellLanes && 4 * l < qx) l *= 2;
+    return l;
+}
+
 Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
 {
     Layout L{};
     const int nx = p->n_cells, qx = q->qx, qy = q->qy, nv = 2 * qx * qy;
     const size_t es = p->precision == HRLB_FP64 ? 8 : 4;
-    L.vpt = choose_vpt(qx, qy);
+    L.vpt = choose_vpt(qx, qy, p->tile_vpt);
     const int nseg = nv / L.vpt;
     L.ngroups = (nseg + kRows - 1) / kRows;
     L.nctiles = (nx + kTileCells - 1) / kTileCells;
-    L.ncellblocks = (nx + kCellBlock - 1) / kCellBlock;
+    L.cell_lanes = p->cell_lanes > 0 ? p->cell_lanes : auto_cell_lanes(qx);
+    const int cpb = kCellThreads / L.cell_lanes;
+    L.ncellblocks = (nx + cpb - 1) / cpb;
     size_t off = 0;
     L.desc = off;
     off = align256(off + sizeof(InstDesc));
@@ -309,22 +352,66 @@ void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<doub
 
 int stage_grid(int ntiles) { return std::min(ntiles, 4096); }
 
-hrlb_status enqueue_steps(int fp32, const InstDesc* descs, int ninst, const TileRef* tiles, int ntiles,
-                          const CellRef* cells, int ncellblocks, size_t shmem, int qy_max, long n_steps,
-                          bool check_last, hipStream_t st)
+hrlb_status enqueue_eager(const Launcher& L, long n_steps, bool check_last, hipStream_t st)
 {
-    const int grid = stage_grid(ntiles);
+    const int grid = stage_grid(L.ntiles);
     for (long s = 0; s < n_steps; ++s) {
         const bool chk = check_last && s + 1 == n_steps;
         for (int stage = 0; stage < 3; ++stage) {
             const int fl = (stage == 2 && chk) ? FLAG_RESID : 0;
-            HIP_TRY(hrlbk_stage(fp32, descs, tiles, ntiles, grid, stage, fl, qy_max, st));
-            HIP_TRY(hrlbk_cell(fp32, descs, cells, ncellblocks, stage == 0 ? 1 : stage == 1 ? 2 : 0,
-                               stage == 2 ? FLAG_STEP_DONE : 0, shmem, st));
+            HIP_TRY(hrlbk_stage(L.fp32, L.descs, L.tiles, L.ntiles, grid, stage, fl, L.qy_max, st));
+            HIP_TRY(hrlbk_cell(L.fp32, L.descs, L.cells, L.ncellblocks, stage == 0 ? 1 : stage == 1 ? 2 : 0,
+                               stage == 2 ? FLAG_STEP_DONE : 0, L.shmem, st));
         }
-        if (chk) HIP_TRY(hrlbk_finalize(descs, ninst, 1, st));
+        if (chk) HIP_TRY(hrlbk_finalize(L.descs, L.ninst, 1, st));
     }
     return HRLB_OK;
+}
+
+// A block of graph_steps steps (with or without the residual check on its last step) is captured
+// once on a private stream and replayed on the caller's stream.
+hrlb_status graph_for(Launcher& L, bool check, hipGraphExec_t* out)
+{
+    hipGraphExec_t& slot = check ? L.graph_check : L.graph_plain;
+    if (slot && L.graph_len == L.graph_steps) {
+        *out = slot;
+        return HRLB_OK;
+    }
+    if (L.graph_len != L.graph_steps) L.drop_graphs();
+    hipStream_t cap = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    hrlb_status st = HRLB_OK;
+    if (e == hipSuccess) st = enqueue_eager(L, L.graph_steps, check, cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess && st == HRLB_OK) e = hipGraphInstantiate(&slot, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (st != HRLB_OK) return st;
+    if (e != hipSuccess) {
+        slot = nullptr;
+        return fail(HRLB_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+    L.graph_len = L.graph_steps;
+    *out = slot;
+    return HRLB_OK;
+}
+
+hrlb_status enqueue_steps(Launcher& L, long n_steps, bool check_last)
+{
+    const int G = L.graph_steps;
+    if (G < 2 || n_steps < G) return enqueue_eager(L, n_steps, check_last, L.stream);
+    const long blocks = n_steps / G, rest = n_steps % G;
+    for (long b = 0; b < blocks; ++b) {
+        const bool chk = check_last && rest == 0 && b + 1 == blocks;
+        hipGraphExec_t ex = nullptr;
+        hrlb_status st = graph_for(L, chk, &ex);
+        if (st != HRLB_OK) return st;
+        HIP_TRY(hipGraphLaunch(ex, L.stream));
+    }
+    return rest ? enqueue_eager(L, rest, check_last, L.stream) : HRLB_OK;
 }
 
 hrlb_status analyze_case(hrlb_case* c)
@@ -449,7 +536,9 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.collisionless = p->delta == 0.0;
     D.seed = p->seed;
     D.ktab_n = (int)(L.t_he + (size_t)(q->nyo + 1) * qy - L.t_wx);
+    D.cell_lanes = L.cell_lanes;
     c->shmem = sizeof(double) * (size_t)D.ktab_n;
+    c->run.shmem = c->shmem;
     D.dt = dt;
     D.Tw = p->T_w;
     D.Pr = p->Pr;
@@ -491,8 +580,17 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     for (int ct = 0; ct < L.nctiles; ++ct)
         for (int g = 0; g < L.ngroups; ++g) tiles.push_back(TileRef{0, ct, g, ct * L.ngroups + g});
     c->ntiles = (int)tiles.size();
+    c->run.fp32 = p->precision == HRLB_FP32_STORE_FP64_MOM;
+    c->run.descs = c->d_desc;
+    c->run.ninst = 1;
+    c->run.tiles = c->d_tiles;
+    c->run.ntiles = c->ntiles;
+    c->run.cells = c->d_cells;
+    c->run.ncellblocks = L.ncellblocks;
+    c->run.qy_max = qy;
+    c->run.stream = c->stream;
     std::vector<CellRef> cells;
-    for (int b = 0; b < L.ncellblocks; ++b) cells.push_back(CellRef{0, b * kCellBlock});
+    for (int b = 0; b < L.ncellblocks; ++b) cells.push_back(CellRef{0, b * (kCellThreads / L.cell_lanes)});
     std::vector<double> dyn(kNDyn, 0.0);
     dyn[DY_NWL] = dyn[DY_NWR] = 1.0;
 
@@ -540,10 +638,99 @@ extern "C" hrlb_status hrlb_step(hrlb_case* c, long n_steps)
     if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
     hrlb_status st0 = ensure_analyzed(c);
     if (st0 != HRLB_OK) return st0;
-    hrlb_status st = enqueue_steps(c->p.precision == HRLB_FP32_STORE_FP64_MOM, c->d_desc, 1, c->d_tiles, c->ntiles,
-                                   c->d_cells, c->L.ncellblocks, c->shmem, c->q->qy, n_steps, false, c->stream);
+    hrlb_status st = enqueue_steps(c->run, n_steps, false);
     if (st == HRLB_OK) c->steps_done += n_steps;
     return st;
+}
+
+extern "C" hrlb_status hrlb_tune_workspace_bytes(const hrlb_quad* q, const hrlb_case_params* p, size_t* bytes)
+{
+    hrlb_status st = validate(q, p);
+    if (st != HRLB_OK) return st;
+    if (!bytes) return fail(HRLB_E_INVALID, "bytes is NULL");
+    size_t mx = 0;
+    for (int d = 1; d <= std::min(q->qy, kMaxVpt); ++d) {
+        if (q->qy % d) continue;
+        for (int l = 1; l <= kMaxCellLanes; l *= 2) {
+            hrlb_case_params pp = *p;
+            pp.tile_vpt = d;
+            pp.cell_lanes = l;
+            mx = std::max(mx, make_layout(q, &pp).total);
+        }
+    }
+    *bytes = mx;
+    return HRLB_OK;
+}
+
+namespace {
+// ms per step of one plan, timed with events after a warm-up step (the case is freed again)
+hrlb_status time_plan(const hrlb_quad* q, const hrlb_case_params* pp, void* ws, size_t ws_bytes, hipStream_t s,
+                      int n_steps, hipEvent_t e0, hipEvent_t e1, double* ms_out)
+{
+    hrlb_case* c = nullptr;
+    hrlb_status st = hrlb_init_case(q, pp, ws, ws_bytes, s, &c);
+    if (st != HRLB_OK) return st;
+    st = hrlb_step(c, 1);
+    float ms = 0.0f;
+    hipError_t e = hipSuccess;
+    if (st == HRLB_OK) e = hipEventRecord(e0, s);
+    if (st == HRLB_OK && e == hipSuccess) st = hrlb_step(c, n_steps);
+    if (st == HRLB_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+    if (st == HRLB_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    if (st == HRLB_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (st == HRLB_OK && e != hipSuccess) st = fail(HRLB_E_DEVICE, "tuning events: %s", hipGetErrorString(e));
+    (void)hipStreamSynchronize(s);
+    hrlb_free_case(c);
+    *ms_out = ms / n_steps;
+    return st;
+}
+}  // namespace
+
+extern "C" hrlb_status hrlb_tune_plan(const hrlb_quad* q, const hrlb_case_params* p, void* dev_workspace,
+                                      size_t ws_bytes, void* hip_stream, int n_steps, int* best_vpt,
+                                      int* best_lanes, double* best_ms_per_step)
+{
+    size_t need = 0;
+    hrlb_status st = hrlb_tune_workspace_bytes(q, p, &need);
+    if (st != HRLB_OK) return st;
+    if (ws_bytes < need) return fail(HRLB_E_NOMEM, "tuning workspace of %zu bytes < %zu", ws_bytes, need);
+    if (n_steps < 1 || !best_vpt || !best_lanes) return fail(HRLB_E_INVALID, "n_steps < 1 or NULL output");
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hrlb_case_params pp = *p;
+    if (pp.cell_lanes == 0) pp.cell_lanes = auto_cell_lanes(q->qx);
+    double best_ms = 1e300;
+    int bv = 0, bl = pp.cell_lanes;
+    for (int d = 1; d <= std::min(q->qy, kMaxVpt) && st == HRLB_OK; ++d) {
+        if (q->qy % d) continue;
+        pp.tile_vpt = d;
+        double ms = 0;
+        st = time_plan(q, &pp, dev_workspace, ws_bytes, s, n_steps, e0, e1, &ms);
+        if (st == HRLB_OK && ms < best_ms) {
+            best_ms = ms;
+            bv = d;
+        }
+    }
+    pp.tile_vpt = bv;
+    for (int l = 1; l <= kMaxCellLanes && st == HRLB_OK; l *= 2) {
+        if (l == bl) continue;
+        pp.cell_lanes = l;
+        double ms = 0;
+        st = time_plan(q, &pp, dev_workspace, ws_bytes, s, n_steps, e0, e1, &ms);
+        if (st == HRLB_OK && ms < best_ms) {
+            best_ms = ms;
+            bl = l;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HRLB_OK) return st;
+    *best_vpt = bv;
+    *best_lanes = bl;
+    if (best_ms_per_step) *best_ms_per_step = best_ms;
+    return HRLB_OK;
 }
 
 extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_steps, int check_every, int stop_rule,
@@ -553,7 +740,6 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
     if (check_every < 1 || max_steps < 0 || !(tol > 0.0)) return fail(HRLB_E_INVALID, "bad tol/max_steps/check_every");
     if (stop_rule != HRLB_STOP_RESIDUAL && stop_rule != HRLB_STOP_PXY) return fail(HRLB_E_INVALID, "bad stop rule");
     const auto t0 = std::chrono::steady_clock::now();
-    const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
     {
         hrlb_status sa = ensure_analyzed(c);
         if (sa != HRLB_OK) return sa;
@@ -566,8 +752,7 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
     double pxy_prev = 0.0;
     while (taken < max_steps) {
         const long n = std::min<long>(check_every, max_steps - taken);
-        hrlb_status st = enqueue_steps(fp32, c->d_desc, 1, c->d_tiles, c->ntiles, c->d_cells, c->L.ncellblocks,
-                                       c->shmem, c->q->qy, n, true, c->stream);
+        hrlb_status st = enqueue_steps(c->run, n, true);
         if (st != HRLB_OK) return st;
         HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
@@ -742,6 +927,16 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
         b->shmem = std::max(b->shmem, cases[i]->shmem);
         b->qy_max = std::max(b->qy_max, cases[i]->q->qy);
     }
+    b->run.fp32 = b->fp32;
+    b->run.descs = b->d_descs;
+    b->run.ninst = n_cases;
+    b->run.tiles = b->d_tiles;
+    b->run.ntiles = b->ntiles;
+    b->run.cells = b->d_cells;
+    b->run.ncellblocks = b->ncellblocks;
+    b->run.shmem = b->shmem;
+    b->run.qy_max = b->qy_max;
+    b->run.stream = b->stream;
     std::vector<InstDesc> descs(n_cases);
     std::vector<TileRef> tiles;
     std::vector<CellRef> cells;
@@ -751,7 +946,7 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
         descs[i] = c->desc;
         for (int ct = 0; ct < c->L.nctiles; ++ct)
             for (int g = 0; g < c->L.ngroups; ++g) tiles.push_back(TileRef{i, ct, g, ct * c->L.ngroups + g});
-        for (int k = 0; k < c->L.ncellblocks; ++k) cells.push_back(CellRef{i, k * kCellBlock});
+        for (int k = 0; k < c->L.ncellblocks; ++k) cells.push_back(CellRef{i, k * (kCellThreads / c->L.cell_lanes)});
     }
     hipError_t e = hipMemcpyAsync(b->d_descs, descs.data(), sizeof(InstDesc) * n_cases, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)
@@ -781,8 +976,7 @@ extern "C" hrlb_status hrlb_batch_step(hrlb_batch* b, long n_steps, int check)
 {
     if (!b) return fail(HRLB_E_INVALID, "batch is NULL");
     if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
-    hrlb_status st = enqueue_steps(b->fp32, b->d_descs, (int)b->cases.size(), b->d_tiles, b->ntiles, b->d_cells,
-                                   b->ncellblocks, b->shmem, b->qy_max, n_steps, check != 0, b->stream);
+    hrlb_status st = enqueue_steps(b->run, n_steps, check != 0);
     if (st == HRLB_OK)
         for (hrlb_case* c : b->cases) c->steps_done += n_steps;
     return st;
@@ -806,6 +1000,22 @@ extern "C" hrlb_status hrlb_batch_poll(hrlb_batch* b, double* residual, double* 
 }
 
 extern "C" void hrlb_batch_free(hrlb_batch* b) { delete b; }
+
+extern "C" hrlb_status hrlb_case_set_graph_steps(hrlb_case* c, int steps_per_graph)
+{
+    if (!c || steps_per_graph < 0) return fail(HRLB_E_INVALID, "NULL case or negative steps");
+    c->run.drop_graphs();
+    c->run.graph_steps = steps_per_graph;
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_batch_set_graph_steps(hrlb_batch* b, int steps_per_graph)
+{
+    if (!b || steps_per_graph < 0) return fail(HRLB_E_INVALID, "NULL batch or negative steps");
+    b->run.drop_graphs();
+    b->run.graph_steps = steps_per_graph;
+    return HRLB_OK;
+}
 
 extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* stage_kernel_ms, double* cell_kernel_ms)
 {

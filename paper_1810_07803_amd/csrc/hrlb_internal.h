@@ -19,7 +19,8 @@ constexpr int kRows = kThreads / kTPR;        // 16
 constexpr int kTileCells = kStrip * kTPR;     // 64
 constexpr int kMaxVpt = kTPR;                 // velocities per row are bounded by the lanes of a row
 constexpr int kMomPerPass = 4;                // moments reduced per LDS pass
-constexpr int kCellBlock = 64;                // threads per block of the per-cell kernel
+constexpr int kCellThreads = 256;             // threads per block of the per-cell kernel
+constexpr int kMaxCellLanes = 16;             // lanes per cell of the per-cell kernel (4, 8 or 16)
 
 // auxiliary half-range Gauss rule used to project the Maxwellian on the half-range Hermite
 // basis (well-conditioned replacement of the monomial-moment form of eq. gx)
@@ -62,6 +63,8 @@ struct InstDesc {
     int collisionless;
     uint32_t seed;
     int ktab_n;    // doubles from wx to the end of he (contiguous quadrature tables)
+    int cell_lanes;  // lanes per cell in the per-cell kernel (4, 8 or 16)
+    int pad1;
     double dt, Tw, Pr, omega;
     double tau_pref;     // delta sqrt(2) sqrt(T_w): 1/tau = tau_pref n (T/T_w)^(1-omega)
     double den_l, den_r; // sum over entering directions of p_x g_x(0,T_w) g_y(-/+u_w,T_w)

@@ -611,6 +611,10 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 }
 
 // ---- per-cell kernel --------------------------------------------------------------------------
+// A block of kCellThreads threads serves kCellThreads / L cells with L = cell_lanes lanes per cell
+// (4, 8 or 16, by the size of the velocity set): the lanes of a cell split the sums of the moment
+// partials over velocity groups, the auxiliary-rule sums of g_x and the output nodes of g_x and
+// g_y, and combine their partial sums by an xor butterfly (identical bits in every lane).
 constexpr int kCyReg = 32;  // expansion orders N_y below this keep their coefficients in registers
 
 // leaving fluxes through one wall (eq. diffuse_nw): block-wide sums over the leaving directions of
@@ -618,7 +622,7 @@ constexpr int kCyReg = 32;  // expansion orders N_y below this keep their coeffi
 template <typename T>
 __device__ void wall_sums(const InstDesc& D, const T* f, bool right, double& flux, double& mom)
 {
-    __shared__ double red[kCellBlock / 64][2];
+    __shared__ double red[kCellThreads / 64][2];
     const int nx = D.nx, qx = D.qx, qy = D.qy, half = qx * qy;
     double a = 0.0, b = 0.0;
     for (int u = threadIdx.x; u < half; u += blockDim.x) {
@@ -641,22 +645,32 @@ __device__ void wall_sums(const InstDesc& D, const T* f, bool right, double& flu
     __syncthreads();
     flux = 0.0;
     mom = 0.0;
-    for (int w = 0; w < kCellBlock / 64; ++w) {
+    for (int w = 0; w < kCellThreads / 64; ++w) {
         flux += red[w][0];
         mom += red[w][1];
     }
     __syncthreads();  // red may be reused by a second call in the same block
 }
 
+__device__ __forceinline__ double lane_sum(double x, int lanes)
+{
+    for (int o = 1; o < lanes; o <<= 1) x += __shfl_xor(x, o, kMaxCellLanes);
+    return x;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __restrict__ descs,
-                                                          const CellRef* __restrict__ cells, int buf, int flags)
+__global__ __launch_bounds__(kCellThreads) void cell_kernel(const InstDesc* __restrict__ descs,
+                                                            const CellRef* __restrict__ cells, int buf, int flags)
 {
     extern __shared__ double ktab[];
     const CellRef cr = cells[blockIdx.x];
     const InstDesc& D = descs[cr.inst];
     const int nx = D.nx;
-    const int s = cr.cell0 + threadIdx.x;
+    const int LN = D.cell_lanes;
+    const int q = threadIdx.x & (LN - 1);
+    const int s = cr.cell0 + threadIdx.x / LN;
+    const bool on = s < nx;
+    const int sc = on ? s : 0;
 
     // the instance's quadrature tables are contiguous from wx to the end of he: stage them in LDS
     const double* gbase = D.wx;
@@ -682,7 +696,7 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
             if (flags & FLAG_STEP_DONE) D.dyn[DY_STEP] += 1.0;
         }
     }
-    if (cr.cell0 + kCellBlock >= nx) {
+    if (cr.cell0 + kCellThreads / LN >= nx) {
         double fr, mr;
         wall_sums<T>(D, fcur, true, fr, mr);
         if (threadIdx.x == 0) {
@@ -691,14 +705,15 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
             D.dyn[DY_SHEAR_R] = mr + nwr * D.mom_r;
         }
     }
-    if (s >= nx) return;
 
     double R[kNMom];
 #pragma unroll
     for (int m = 0; m < kNMom; ++m) R[m] = 0.0;
-    for (int g = 0; g < D.ngroups; ++g)
+    for (int g = q; g < D.ngroups; g += LN)
 #pragma unroll
-        for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + s];
+        for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + sc];
+#pragma unroll
+    for (int m = 0; m < kNMom; ++m) R[m] = lane_sum(R[m], LN);
 
     // moments of Sec. II from the raw sums (shift to the peculiar velocity xi = p - u)
     const double n = R[0];
@@ -716,41 +731,43 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
     const double qx = 0.5 * (R[6] - ux * b - 2.0 * cx + 2.0 * ux * c0 + u2 * (R[1] - ux * R[0]) + R[9] - ux * R[8]);
     const double qy = 0.5 * (R[7] - uy * b - 2.0 * cy + 2.0 * uy * c0 + u2 * (R[2] - uy * R[0]) + R[10] - uy * R[8]);
 
-    double* F = D.fields;
-    F[F_N * nx + s] = n;
-    F[F_UX * nx + s] = ux;
-    F[F_UY * nx + s] = uy;
-    F[F_T * nx + s] = Tm;
-    F[F_PXX * nx + s] = pxx;
-    F[F_PXY * nx + s] = pxy;
-    F[F_PYY * nx + s] = pyy;
-    F[F_TZZ * nx + s] = tzz;
-    F[F_QX * nx + s] = qx;
-    F[F_QY * nx + s] = qy;
-
     // eq. (tau) with mu ~ T^omega; Shakhov prefactor (1 - Pr)/(n K_B^2 T^2)
     const double invtau = D.collisionless ? 0.0 : D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
     const double As = (1.0 - D.Pr) / (n * Tm * Tm);
     T* cell = (T*)D.cell;
-    cell[SC_UX * nx + s] = (T)ux;
-    cell[SC_UY * nx + s] = (T)uy;
-    cell[SC_T * nx + s] = (T)Tm;
-    cell[SC_INVTAU * nx + s] = (T)invtau;
-    cell[SC_AS * nx + s] = (T)As;
-    cell[SC_AS5T * nx + s] = (T)(As / (5.0 * Tm));
-    cell[SC_QX * nx + s] = (T)qx;
-    cell[SC_QY * nx + s] = (T)qy;
-    cell[SC_IJD * nx + s] = (T)D.inv_jdeta[s];
+    if (on && q == 0) {
+        double* F = D.fields;
+        F[F_N * nx + s] = n;
+        F[F_UX * nx + s] = ux;
+        F[F_UY * nx + s] = uy;
+        F[F_T * nx + s] = Tm;
+        F[F_PXX * nx + s] = pxx;
+        F[F_PXY * nx + s] = pxy;
+        F[F_PYY * nx + s] = pyy;
+        F[F_TZZ * nx + s] = tzz;
+        F[F_QX * nx + s] = qx;
+        F[F_QY * nx + s] = qy;
+        cell[SC_UX * nx + s] = (T)ux;
+        cell[SC_UY * nx + s] = (T)uy;
+        cell[SC_T * nx + s] = (T)Tm;
+        cell[SC_INVTAU * nx + s] = (T)invtau;
+        cell[SC_AS * nx + s] = (T)As;
+        cell[SC_AS5T * nx + s] = (T)(As / (5.0 * Tm));
+        cell[SC_QX * nx + s] = (T)qx;
+        cell[SC_QY * nx + s] = (T)qy;
+        cell[SC_IJD * nx + s] = (T)D.inv_jdeta[s];
+    }
 
-    // g_x (eq. gx) as the projection of g/omega on h_0..h_N computed with the auxiliary rule;
-    // the exponent for the two half-lines differs only in the sign of the term linear in u
+    // g_x (eq. gx) as the projection of g/omega on h_0..h_N computed with the auxiliary rule; the
+    // exponents for the two half-lines differ only in the sign of the term linear in u.  Lane q of
+    // the cell takes auxiliary nodes k = q mod L; the lanes then sum their partial projections.
     const int qxn = D.qx, nxo = D.nxo;
     const double inv2T = 0.5 / Tm;
     const double rsT = 1.0 / sqrt(Tm);
     double Ip[kMaxNx + 1], Im[kMaxNx + 1];
 #pragma unroll
     for (int l = 0; l <= kMaxNx; ++l) Ip[l] = Im[l] = 0.0;
-    for (int k = 0; k < kAux; ++k) {
+    for (int k = q; k < kAux; k += LN) {
         const double Z = s_az[k];
         const double a = (Z * Z * (Tm - 1.0) - ux * ux) * inv2T;
         const double bb = Z * ux * (2.0 * inv2T);
@@ -764,7 +781,13 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
                 Im[l] += em * hz;
             }
     }
-    for (int i = 0; i < qxn; ++i) {
+#pragma unroll
+    for (int l = 0; l <= kMaxNx; ++l)
+        if (l <= nxo) {
+            Ip[l] = lane_sum(Ip[l], LN);
+            Im[l] = lane_sum(Im[l], LN);
+        }
+    for (int i = q; i < qxn; i += LN) {
         double ap = 0.0, am = 0.0;
 #pragma unroll
         for (int l = 0; l <= kMaxNx; ++l)
@@ -774,8 +797,10 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
                 am += Im[l] * hz;
             }
         const double nw = n * s_wx[i];
-        cell[(kNSc + i) * nx + s] = (T)(nw * ap);
-        cell[(kNSc + qxn + i) * nx + s] = (T)(nw * am);
+        if (on) {
+            cell[(kNSc + i) * nx + s] = (T)(nw * ap);
+            cell[(kNSc + qxn + i) * nx + s] = (T)(nw * am);
+        }
     }
 
     // g_y (eq. gy): c_l = coefficient of t^l in exp(u t + (T-1) t^2/2), l c_l = u c_{l-1} + (T-1) c_{l-2}
@@ -787,15 +812,15 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
         cl[1] = uy;
 #pragma unroll
         for (int l = 2; l < kCyReg; ++l) cl[l] = (uy * cl[l - 1] + tm1 * cl[l - 2]) * (1.0 / l);
-        for (int j = 0; j < nqy; ++j) {
+        for (int j = q; j < nqy; j += LN) {
             double acc = 0.0;
 #pragma unroll
             for (int l = 0; l < kCyReg; ++l)
                 if (l <= nyo) acc += cl[l] * s_he[l * nqy + j];
-            cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
+            if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
         }
     } else {
-        for (int j = 0; j < nqy; ++j) {
+        for (int j = q; j < nqy; j += LN) {
             double c2 = 1.0, c1 = uy;
             double acc = s_he[j] + uy * s_he[nqy + j];
             for (int l = 2; l <= nyo; ++l) {
@@ -804,7 +829,7 @@ __global__ __launch_bounds__(kCellBlock) void cell_kernel(const InstDesc* __rest
                 c2 = c1;
                 c1 = c;
             }
-            cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
+            if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
         }
     }
 }
@@ -904,9 +929,9 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_cell(int fp32,
 {
     if (ncells <= 0) return hipSuccess;
     if (fp32)
-        hipLaunchKernelGGL(cell_kernel<float>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, buf, flags);
+        hipLaunchKernelGGL(cell_kernel<float>, dim3(ncells), dim3(kCellThreads), shmem, st, descs, cells, buf, flags);
     else
-        hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellBlock), shmem, st, descs, cells, buf, flags);
+        hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellThreads), shmem, st, descs, cells, buf, flags);
     return hipGetLastError();
 }
 

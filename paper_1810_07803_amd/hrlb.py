@@ -28,7 +28,8 @@ EXPORTED = (
     "hrlb_step", "hrlb_run_to_steady", "hrlb_moments", "hrlb_get_state", "hrlb_set_state",
     "hrlb_case_info", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
     "hrlb_batch_workspace_bytes", "hrlb_batch_create", "hrlb_batch_step", "hrlb_batch_poll",
-    "hrlb_batch_free", "hrlb_batch_profile",
+    "hrlb_batch_free", "hrlb_batch_profile", "hrlb_case_set_graph_steps", "hrlb_batch_set_graph_steps",
+    "hrlb_tune_workspace_bytes", "hrlb_tune_plan",
 )
 
 
@@ -43,7 +44,7 @@ class CaseParams(C.Structure):
         ("delta", C.c_double), ("u_w", C.c_double), ("T_w", C.c_double), ("Pr", C.c_double),
         ("omega", C.c_double), ("n_cells", C.c_int), ("stretch_A", C.c_double),
         ("precision", C.c_int), ("rounding", C.c_int), ("cfl", C.c_double), ("dt", C.c_double),
-        ("seed", C.c_uint),
+        ("seed", C.c_uint), ("tile_vpt", C.c_int), ("cell_lanes", C.c_int),
     ]
 
 
@@ -85,6 +86,10 @@ def load() -> C.CDLL:
                 "hrlb_batch_step": [vp, C.c_long, C.c_int],
                 "hrlb_batch_poll": [vp, dp, dp],
                 "hrlb_batch_profile": [vp, C.c_long, dp, dp],
+                "hrlb_case_set_graph_steps": [vp, C.c_int],
+                "hrlb_tune_workspace_bytes": [vp, C.POINTER(CaseParams), C.POINTER(C.c_size_t)],
+                "hrlb_tune_plan": [vp, C.POINTER(CaseParams), vp, C.c_size_t, vp, C.c_int, ip, ip, dp],
+                "hrlb_batch_set_graph_steps": [vp, C.c_int],
             }
             for name, args in sig.items():
                 fn = getattr(lib, name)
@@ -139,8 +144,25 @@ def init_quadrature(Qx, Nx, Qy, Ny, p0=1.0) -> Quadrature:
 
 
 def make_params(*, delta, uw, ncell, stretch_A=0.0, Tw=1.0, Pr=2.0 / 3.0, omega=0.7, precision=HRLB_FP64,
-                rounding=HRLB_ROUND_NEAREST, cfl=0.5, dt=0.0, seed=0) -> CaseParams:
-    return CaseParams(delta, uw, Tw, Pr, omega, ncell, stretch_A, precision, rounding, cfl, dt, seed & 0xFFFFFFFF)
+                rounding=HRLB_ROUND_NEAREST, cfl=0.5, dt=0.0, seed=0, tile_vpt=0, cell_lanes=0) -> CaseParams:
+    return CaseParams(delta, uw, Tw, Pr, omega, ncell, stretch_A, precision, rounding, cfl, dt, seed & 0xFFFFFFFF,
+                      tile_vpt, cell_lanes)
+
+
+def tune_plan(quad: "Quadrature", params: CaseParams, n_steps: int = 20, device="cuda:0"):
+    """Autotune the kernel plan of one case (hrlb_tune_plan): returns (tile_vpt, cell_lanes, ms_per_step)."""
+    import torch
+
+    n = C.c_size_t()
+    _check(load().hrlb_tune_workspace_bytes(quad.handle, C.byref(params), C.byref(n)))
+    ws = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+    base = ws.data_ptr()
+    off = (-base) % 256
+    stream = torch.cuda.current_stream(device)
+    bv, bl, ms = C.c_int(), C.c_int(), C.c_double()
+    _check(load().hrlb_tune_plan(quad.handle, C.byref(params), C.c_void_p(base + off), n.value,
+                                 C.c_void_p(stream.cuda_stream), n_steps, C.byref(bv), C.byref(bl), C.byref(ms)))
+    return bv.value, bl.value, ms.value
 
 
 def workspace_bytes(quad: Quadrature, params: CaseParams) -> int:
@@ -202,6 +224,10 @@ class Case:
         assert s.shape == (2, self.nv, self.ncell)
         _check(load().hrlb_set_state(self.handle, _dptr(s)))
 
+    def set_graph_steps(self, steps: int):
+        """Steps per captured HIP graph (0 disables graphs)."""
+        _check(load().hrlb_case_set_graph_steps(self.handle, steps))
+
     def steps_done(self) -> int:
         sd = C.c_long()
         _check(load().hrlb_case_info(self.handle, None, None, None, C.byref(sd)))
@@ -246,6 +272,10 @@ class Batch:
         p = np.zeros(len(self.cases))
         _check(load().hrlb_batch_poll(self.handle, _dptr(r), _dptr(p)))
         return r, p
+
+    def set_graph_steps(self, steps: int):
+        """Steps per captured HIP graph (0 disables graphs)."""
+        _check(load().hrlb_batch_set_graph_steps(self.handle, steps))
 
     def profile(self, n_steps: int):
         """Mean duration (ms) of one stage-kernel launch and one per-cell-kernel launch."""
