@@ -154,8 +154,11 @@ def main(argv=None):
     # plus f^n in stages 2 and 3: (2 + 3 + 3)/3 passes of 2 dists per unit on average
     bytes_per_unit = es * 2 * (2 + 3 + 3) / 3.0
     achieved = units * bytes_per_unit / (stage_ms * 1e-3) / 1e9
+    from paper_1810_07803_amd import profiling
+
+    traffic = profiling.load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_stage_kernel_traffic.txt"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "stage_kernel<%s>" % ("float" if es == 4 else "double"),
                 "kernel_ms": round(stage_ms, 4), "cell_kernel_ms": round(cell_ms, 4),
                 "bytes_per_unit_per_launch": bytes_per_unit, "units_per_launch": units}

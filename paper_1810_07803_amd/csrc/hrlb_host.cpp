@@ -14,6 +14,7 @@
 
 #include "../../include/hrlb.h"
 #include "hrlb_internal.h"
+#include "hrlb_plan.h"
 #include "hrlb_quadrature.h"
 
 using namespace hrlb;
@@ -94,6 +95,7 @@ struct Layout {
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
     int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
+    int ntile_list;  // records in the case's tile list (XCD-aware order, padded)
 };
 
 struct hrlb_case {
@@ -266,6 +268,9 @@ int choose_vpt(int qx, int qy, int requested)
     return best;
 }
 
+// persistent grid: at most 4096 blocks, a multiple of 8 so that block b stays on XCD b % 8
+int stage_grid(int ntiles) { return std::max(8, std::min(ntiles, 4096) / 8 * 8); }
+
 // lanes per cell of the per-cell kernel: about a quarter of the x nodes of one half-line
 int auto_cell_lanes(int qx)
 {
@@ -322,7 +327,8 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     L.res = off;
     off = align256(off + sizeof(double) * (size_t)L.nctiles * L.ngroups * 2);
     L.tiles = off;
-    off = align256(off + sizeof(TileRef) * (size_t)L.nctiles * L.ngroups);
+    L.ntile_list = (int)case_tiles(L.nctiles, L.ngroups).size();
+    off = align256(off + sizeof(TileRef) * (size_t)L.ntile_list);
     L.cells = off;
     off = align256(off + sizeof(CellRef) * L.ncellblocks);
     L.total = off;
@@ -350,7 +356,7 @@ void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<doub
     }
 }
 
-int stage_grid(int ntiles) { return std::min(ntiles, 4096); }
+
 
 hrlb_status enqueue_eager(const Launcher& L, long n_steps, bool check_last, hipStream_t st)
 {
@@ -433,7 +439,10 @@ extern "C" hrlb_status hrlb_case_workspace_bytes(const hrlb_quad* q, const hrlb_
     hrlb_status st = validate(q, p);
     if (st != HRLB_OK) return st;
     if (!bytes) return fail(HRLB_E_INVALID, "bytes is NULL");
-    *bytes = make_layout(q, p).total;
+    const Layout L = make_layout(q, p);
+    if (!tiles_valid(case_tiles(L.nctiles, L.ngroups), (size_t)L.ntile_list, 1, &L.nctiles, &L.ngroups))
+        return fail(HRLB_E_INVALID, "internal: inconsistent tile list");
+    *bytes = L.total;
     return HRLB_OK;
 }
 
@@ -576,9 +585,11 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     c->d_tiles = (TileRef*)(ws + L.tiles);
     c->d_cells = (CellRef*)(ws + L.cells);
 
-    std::vector<TileRef> tiles;
-    for (int ct = 0; ct < L.nctiles; ++ct)
-        for (int g = 0; g < L.ngroups; ++g) tiles.push_back(TileRef{0, ct, g, ct * L.ngroups + g});
+    std::vector<TileRef> tiles = case_tiles(L.nctiles, L.ngroups);
+    if (!tiles_valid(tiles, (size_t)L.ntile_list, 1, &L.nctiles, &L.ngroups)) {
+        delete c;
+        return fail(HRLB_E_INVALID, "internal: inconsistent tile list");
+    }
     c->ntiles = (int)tiles.size();
     c->run.fp32 = p->precision == HRLB_FP32_STORE_FP64_MOM;
     c->run.descs = c->d_desc;
@@ -865,17 +876,26 @@ struct BatchLayout {
     int ntiles, ncellblocks;
 };
 
+// tile list of a batch: natural sequence over cases, then the XCD-aware order weighted by work
+std::vector<TileRef> batch_tiles(hrlb_case* const* cases, int n)
+{
+    std::vector<PlanShape> shapes(n);
+    for (int i = 0; i < n; ++i)
+        shapes[i] = PlanShape{cases[i]->L.nctiles, cases[i]->L.ngroups, cases[i]->L.vpt, cases[i]->p.n_cells};
+    return plan_batch_tiles(shapes);
+}
+
 hrlb_status batch_layout(hrlb_case* const* cases, int n, BatchLayout* B)
 {
     if (!cases || n < 1) return fail(HRLB_E_INVALID, "empty batch");
-    int nt = 0, nc = 0;
+    int nc = 0;
     for (int i = 0; i < n; ++i) {
         if (!cases[i]) return fail(HRLB_E_INVALID, "case %d is NULL", i);
         if (cases[i]->p.precision != cases[0]->p.precision) return fail(HRLB_E_INVALID, "mixed precisions in a batch");
         if (cases[i]->stream != cases[0]->stream) return fail(HRLB_E_INVALID, "cases of a batch must share a stream");
-        nt += cases[i]->ntiles;
         nc += cases[i]->L.ncellblocks;
     }
+    const int nt = (int)batch_tiles(cases, n).size();
     size_t off = 0;
     B->descs = off;
     off = align256(off + sizeof(InstDesc) * n);
@@ -938,15 +958,20 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
     b->run.qy_max = b->qy_max;
     b->run.stream = b->stream;
     std::vector<InstDesc> descs(n_cases);
-    std::vector<TileRef> tiles;
     std::vector<CellRef> cells;
-    // tiles ordered cell tile-major within an instance so that blocks sharing cells run together
+    std::vector<int> nct(n_cases), ngr(n_cases);
     for (int i = 0; i < n_cases; ++i) {
         const hrlb_case* c = cases[i];
         descs[i] = c->desc;
-        for (int ct = 0; ct < c->L.nctiles; ++ct)
-            for (int g = 0; g < c->L.ngroups; ++g) tiles.push_back(TileRef{i, ct, g, ct * c->L.ngroups + g});
+        nct[i] = c->L.nctiles;
+        ngr[i] = c->L.ngroups;
         for (int k = 0; k < c->L.ncellblocks; ++k) cells.push_back(CellRef{i, k * (kCellThreads / c->L.cell_lanes)});
+    }
+    const std::vector<TileRef> tiles = batch_tiles(cases, n_cases);
+    if ((int)tiles.size() != b->ntiles || (int)cells.size() != b->ncellblocks ||
+        !tiles_valid(tiles, (size_t)b->ntiles, n_cases, nct.data(), ngr.data())) {
+        delete b;
+        return fail(HRLB_E_INVALID, "internal: inconsistent batch tile list");
     }
     hipError_t e = hipMemcpyAsync(b->d_descs, descs.data(), sizeof(InstDesc) * n_cases, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)

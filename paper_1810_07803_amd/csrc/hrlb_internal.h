@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "hrlb_plan.h"
+
 namespace hrlb {
 
 // ---- stage kernel tiling ------------------------------------------------------------------
@@ -17,6 +19,7 @@ constexpr int kStrip = 4;
 constexpr int kTPR = 16;
 constexpr int kRows = kThreads / kTPR;        // 16
 constexpr int kTileCells = kStrip * kTPR;     // 64
+static_assert(kTileCells == kPlanTileCells, "tile width of the work lists");
 constexpr int kMaxVpt = kTPR;                 // velocities per row are bounded by the lanes of a row
 constexpr int kMomPerPass = 4;                // moments reduced per LDS pass
 constexpr int kCellThreads = 256;             // threads per block of the per-cell kernel
@@ -91,18 +94,6 @@ struct InstDesc {
     const double* gw_l;  // [nv] g_x(0,T_w) g_y(-u_w,T_w)
     const double* gw_r;  // [nv] g_x(0,T_w) g_y(+u_w,T_w)
     const double* g0;    // [nv] initial populations (rest equilibrium, n = 1)
-};
-
-struct TileRef {   // one block-sized unit of the stage kernel
-    int inst;
-    int ctile;     // cell tile index within the instance
-    int group;     // velocity group index within the instance
-    int tile_id;   // ctile * ngroups + group (residual partial slot)
-};
-
-struct CellRef {   // one block of the per-cell kernel
-    int inst;
-    int cell0;
 };
 
 // ---- equilibrium truncations (host and device) ------------------------------------------

@@ -290,6 +290,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const TileRef tr = tiles[t];
+        if (tr.inst < 0) continue;  // padding of the XCD-aware tile order (uniform per block)
         const InstDesc& D = descs[tr.inst];
         const int nx = D.nx, nv = D.nv, qx = D.qx, qy = D.qy, vpt = D.vpt;
         const int c0 = tr.ctile * kTileCells;

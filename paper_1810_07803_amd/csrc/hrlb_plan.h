@@ -1,0 +1,95 @@
+// hrlb_plan.h -- work lists of the stage kernel (host only, no HIP dependency).
+#pragma once
+
+#include <algorithm>
+#include <vector>
+
+namespace hrlb {
+
+constexpr int kPlanTileCells = 64;  // cells per tile of the stage kernel
+constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, each with its own L2
+
+struct TileRef {   // one block-sized unit of the stage kernel
+    int inst;      // -1: padding, skipped
+    int ctile;     // cell tile index within the instance
+    int group;     // velocity group index within the instance
+    int tile_id;   // ctile * ngroups + group (residual partial slot)
+};
+
+struct CellRef {   // one block of the per-cell kernel
+    int inst;
+    int cell0;
+};
+
+struct PlanShape {  // what the tile list needs to know about one instance
+    int nctiles, ngroups, vpt, ncells;
+};
+
+// XCD-aware order of a tile list.  Workgroups are dispatched to the 8 XCDs round robin, and the
+// persistent stage kernel gives block b the positions b, b + grid, ... (grid a multiple of 8), so
+// position p runs on XCD p % 8.  The natural sequence (instance, velocity group, cell tile) keeps
+// tiles that share halos and cell tables next to each other; it is cut into 8 contiguous chunks of
+// about equal work, chunk x is laid on positions x, x + 8, ..., and short chunks are padded with
+// empty tiles (inst = -1) so that every chunk stays on its own XCD's L2.
+inline std::vector<TileRef> xcd_order(const std::vector<TileRef>& seq, const std::vector<double>& cost)
+{
+    double total = 0.0;
+    for (double c : cost) total += c;
+    std::vector<std::vector<TileRef>> chunk(kXcds);
+    double acc = 0.0;
+    for (size_t t = 0; t < seq.size(); ++t) {
+        const int x = total > 0.0 ? (int)std::min<double>(kXcds - 1, acc / total * kXcds) : 0;
+        chunk[x].push_back(seq[t]);
+        acc += cost[t];
+    }
+    size_t mx = 0;
+    for (auto& c : chunk) mx = std::max(mx, c.size());
+    std::vector<TileRef> out(mx * kXcds, TileRef{-1, 0, 0, 0});
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t k = 0; k < chunk[x].size(); ++k) out[k * kXcds + x] = chunk[x][k];
+    return out;
+}
+
+// tile list of one case: natural sequence (velocity group, cell tile), XCD-aware order
+inline std::vector<TileRef> case_tiles(int nctiles, int ngroups)
+{
+    std::vector<TileRef> seq;
+    for (int g = 0; g < ngroups; ++g)
+        for (int ct = 0; ct < nctiles; ++ct) seq.push_back(TileRef{0, ct, g, ct * ngroups + g});
+    return xcd_order(seq, std::vector<double>(seq.size(), 1.0));
+}
+
+// tile list of a batch: natural sequence over instances, XCD-aware order weighted by the work of
+// each tile (velocities per row x cells)
+inline std::vector<TileRef> plan_batch_tiles(const std::vector<PlanShape>& shapes)
+{
+    std::vector<TileRef> seq;
+    std::vector<double> cost;
+    for (int i = 0; i < (int)shapes.size(); ++i) {
+        const PlanShape& s = shapes[i];
+        for (int g = 0; g < s.ngroups; ++g)
+            for (int ct = 0; ct < s.nctiles; ++ct) {
+                seq.push_back(TileRef{i, ct, g, ct * s.ngroups + g});
+                cost.push_back((double)s.vpt * std::min(kPlanTileCells, s.ncells - ct * kPlanTileCells));
+            }
+    }
+    return xcd_order(seq, cost);
+}
+
+// every record must name an instance of the list (or be padding) and a cell tile and velocity
+// group of that instance; checked on the host before any upload
+inline bool tiles_valid(const std::vector<TileRef>& tiles, size_t capacity, int ninst, const int* nctiles,
+                        const int* ngroups)
+{
+    if (tiles.size() > capacity) return false;
+    for (const TileRef& t : tiles) {
+        if (t.inst == -1) continue;
+        if (t.inst < 0 || t.inst >= ninst) return false;
+        const int nc = nctiles[t.inst], ng = ngroups[t.inst];
+        if (t.ctile < 0 || t.ctile >= nc || t.group < 0 || t.group >= ng || t.tile_id != t.ctile * ng + t.group)
+            return false;
+    }
+    return true;
+}
+
+}  // namespace hrlb

@@ -1,0 +1,112 @@
+"""Summaries of rocprofv3 output for the solver's kernels (tracing/profiling support).
+
+* ``stats``: the kernel table of a ``rocprofv3 --kernel-trace --stats --output-format csv`` run.
+* ``traffic``: HBM bytes per dispatch of one kernel from two counter runs (``--pmc FETCH_SIZE`` and
+  ``--pmc WRITE_SIZE``, values in KiB per dispatch), each scaled by what the same counter reads for
+  the largest plain device copy in the same run (``bench.py --copy-probe-mib N`` issues one of a
+  known size).  The summary records a digest of the kernel sources; ``load_traffic`` returns the
+  figures only while the sources still have that digest.
+
+Command line:
+    python -m paper_1810_07803_amd.profiling stats <kernel_stats.csv> [command...]
+    python -m paper_1810_07803_amd.profiling traffic <fetch.csv> <write.csv> <kernel-substring> <probe-MiB> [command...]
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/hrlb_kernels.hip", "csrc/hrlb_internal.h", "csrc/hrlb_plan.h", "csrc/hrlb_host.cpp")
+
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stats(path: str, command: str = "") -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    if command:
+        out.append(f"command: {command}")
+    out.append(f"kernel source digest: {source_digest()}")
+    out.append("")
+    out.append("| kernel | calls | total ms | average us | min us | max us | % |")
+    out.append("|---|---:|---:|---:|---:|---:|---:|")
+    for r in rows:
+        name = r["Name"].replace("|", "/")
+        out.append("| %s | %s | %.3f | %.2f | %.2f | %.2f | %.1f |" % (
+            name[:90], r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e3,
+            float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return "\n".join(out) + "\n"
+
+
+def _per_dispatch(path: str, counter: str):
+    rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+    return [(r["Kernel_Name"], float(r["Counter_Value"])) for r in rows]
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel: str, probe_mib: float, command: str = "") -> str:
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+    known_kib = probe_mib * 1024.0
+    # calibration: the copy dispatch that wrote the most bytes is the probe copy
+    cal_w = max(v for n, v in write if "copy" in n.lower() or "elementwise" in n.lower())
+    cal_f = max(v for n, v in fetch if "copy" in n.lower() or "elementwise" in n.lower())
+    f_scale, w_scale = known_kib / cal_f, known_kib / cal_w
+    kf = [v for n, v in fetch if kernel in n]
+    kw = [v for n, v in write if kernel in n]
+    f_kib = sum(kf) / len(kf)
+    w_kib = sum(kw) / len(kw)
+    tb = (f_kib * f_scale + w_kib * w_scale) * 1024.0
+    lines = []
+    if command:
+        lines.append(f"command: {command}")
+    lines += [
+        f"kernel: {kernel}",
+        f"kernel_source_digest: {source_digest()}",
+        f"dispatches_fetch: {len(kf)}",
+        f"dispatches_write: {len(kw)}",
+        f"fetch_kib_per_dispatch: {f_kib:.1f}",
+        f"write_kib_per_dispatch: {w_kib:.1f}",
+        f"probe_copy_mib: {probe_mib}",
+        f"probe_fetch_kib: {cal_f:.1f}",
+        f"probe_write_kib: {cal_w:.1f}",
+        f"fetch_scale: {f_scale:.4f}",
+        f"write_scale: {w_scale:.4f}",
+        f"traffic_bytes_per_dispatch: {tb:.0f}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def load_traffic(path: str):
+    """Traffic bytes per dispatch from a summary, or None if absent or the kernels have changed."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+if __name__ == "__main__":
+    mode = sys.argv[1]
+    if mode == "stats":
+        sys.stdout.write(stats(sys.argv[2], " ".join(sys.argv[3:])))
+    elif mode == "traffic":
+        sys.stdout.write(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), " ".join(sys.argv[6:])))
+    else:
+        raise SystemExit(__doc__)

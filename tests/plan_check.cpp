@@ -1,0 +1,79 @@
+// CPU check of the stage kernel's work lists (hrlb_plan.h): for many random ragged batches and
+// single cases, every natural tile appears exactly once, padding records are the only extras,
+// position p of a list belongs to the chunk of XCD p % 8 (chunks contiguous in the natural order),
+// and the validator accepts the list at its own length and rejects it one record shorter.
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "hrlb_plan.h"
+
+using namespace hrlb;
+
+static int fails = 0;
+#define CHECK(c)                                                          \
+    do {                                                                  \
+        if (!(c)) {                                                       \
+            std::fprintf(stderr, "check failed line %d: %s\n", __LINE__, #c); \
+            ++fails;                                                      \
+        }                                                                 \
+    } while (0)
+
+static void check_list(const std::vector<TileRef>& tiles, const std::vector<PlanShape>& shapes)
+{
+    std::map<std::tuple<int, int, int>, int> seen;
+    size_t natural = 0;
+    std::vector<int> nct, ngr;
+    for (const PlanShape& s : shapes) {
+        natural += (size_t)s.nctiles * s.ngroups;
+        nct.push_back(s.nctiles);
+        ngr.push_back(s.ngroups);
+    }
+    CHECK(tiles.size() % kXcds == 0);
+    CHECK(tiles.size() >= natural);
+    size_t real = 0;
+    for (const TileRef& t : tiles) {
+        if (t.inst < 0) continue;
+        ++real;
+        seen[std::make_tuple(t.inst, t.ctile, t.group)]++;
+    }
+    CHECK(real == natural);
+    for (auto& kv : seen) CHECK(kv.second == 1);
+    CHECK(tiles_valid(tiles, tiles.size(), (int)shapes.size(), nct.data(), ngr.data()));
+    if (!tiles.empty()) CHECK(!tiles_valid(tiles, tiles.size() - 1, (int)shapes.size(), nct.data(), ngr.data()));
+    // chunks: the records at positions x, x+8, ... are contiguous in the natural order
+    for (int x = 0; x < kXcds; ++x) {
+        long last = -1;
+        for (size_t p = x; p < tiles.size(); p += kXcds) {
+            const TileRef& t = tiles[p];
+            if (t.inst < 0) continue;
+            long key = 0;
+            for (int i = 0; i < t.inst; ++i) key += (long)shapes[i].nctiles * shapes[i].ngroups;
+            key += (long)t.group * shapes[t.inst].nctiles + t.ctile;
+            CHECK(key > last);
+            last = key;
+        }
+    }
+}
+
+int main()
+{
+    std::srand(12345);
+    for (int trial = 0; trial < 400; ++trial) {
+        const int n = 1 + std::rand() % 40;
+        std::vector<PlanShape> shapes;
+        for (int i = 0; i < n; ++i) {
+            const int ncells = 8 + 4 * (std::rand() % 600);
+            const int nct = (ncells + kPlanTileCells - 1) / kPlanTileCells;
+            shapes.push_back(PlanShape{nct, 1 + std::rand() % 60, 1 + std::rand() % 8, ncells});
+        }
+        check_list(plan_batch_tiles(shapes), shapes);
+        const PlanShape& s = shapes[0];
+        std::vector<PlanShape> one{s};
+        check_list(case_tiles(s.nctiles, s.ngroups), one);
+    }
+    std::printf("plan checks: %d failures\n", fails);
+    return fails ? 1 : 0;
+}
