@@ -75,7 +75,7 @@ typedef struct {
     double T_w;       /* wall temperature (> 0); the units assume T_w = 1 but any value works  */
     double Pr;        /* Prandtl number of the Shakhov model, > 0                             */
     double omega;     /* viscosity index of eq. (mu): mu ~ T^omega                             */
-    int n_cells;      /* cells across the full channel: even, 8 <= n_cells <= 65536           */
+    int n_cells;      /* cells across the full channel: a multiple of 4, 8 <= n_cells <= 65536 */
     double stretch_A; /* grid stretching of eq. (stretch), 0 <= A < 1 (0 = uniform)           */
     int precision;    /* HRLB_FP64 or HRLB_FP32_STORE_FP64_MOM                                 */
     int rounding;     /* FP32 storage only: HRLB_ROUND_NEAREST or HRLB_ROUND_STOCHASTIC        */
