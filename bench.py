@@ -31,6 +31,11 @@ WORKLOADS = {
     "couette_nx512_q16x8_fp32": dict(kind="single", name="couette_nx512_q16x8", precision=1, rounding=1),
     "couette_nx2048_q80x20_fp32": dict(kind="single", name="couette_nx2048_q80x20", precision=1, rounding=1),
     "couette_nx2048_q80x20_fp64": dict(kind="single", name="couette_nx2048_q80x20", precision=0, rounding=0),
+    # serving: 64 solves drawn like the ragged batch with Nx up to 2048 (seed 1), Poisson arrivals at
+    # 200 requests/s (seed 2), FP32 storage; each stops when its P_xy drift rate falls below 2e-6 per
+    # unit time or after 100k steps
+    "couette_serve_poisson200": dict(kind="serve", precision=1, rounding=1, requests=64, rate=200.0,
+                                     tol=2e-6, max_steps=100000, check_every=1000),
 }
 
 
@@ -92,6 +97,47 @@ def _cpu_baseline(insts, budget_s: float):
                       f"({units} cell·velocity updates in {dt:.1f} s)"}
 
 
+def _serve_main(args, spec):
+    """Serving workload: requests arrive on a Poisson trace and are served with continuous batching."""
+    from hrlb_inputs import batch_draws, poisson_arrivals
+    from paper_1810_07803_amd import hrlb, serve
+
+    reqs = batch_draws(spec["requests"], seed=1, nx_choices=(64, 128, 256, 512, 1024, 2048))
+    arrivals = poisson_arrivals(spec["requests"], spec["rate"], seed=2)
+    arrivals = arrivals - arrivals[0]
+    srv = hrlb.Server(args.arena_mib << 20, max_active=256, check_every=spec["check_every"], max_bypass=4,
+                      precision=spec["precision"])
+    # warm-up (kernel loading, velocity-set construction) on one small solve, untimed
+    srv.submit(4, 4, hrlb.make_params(delta=1.0, uw=0.1, ncell=64, precision=spec["precision"], rounding=1),
+               tol=1.0, max_steps=spec["check_every"])
+    while srv.pump().active:
+        pass
+    print(f"# serving {len(reqs)} requests", file=sys.stderr, flush=True)
+    records, tot = serve.run_trace(srv, reqs, arrivals, tol=spec["tol"], max_steps=spec["max_steps"],
+                                   wall_limit_s=args.serve_wall_s)
+    summ = serve.latency_summary(records)
+    summ["solves_per_s"] = summ["finished"] / tot["wall_s"]
+    summ["rounds"] = tot["rounds"]
+    summ["wall_s"] = tot["wall_s"]
+    out = {
+        "metric": "cell·velocity updates/s",
+        "value": tot["units"] / tot["wall_s"],
+        "unit": "cell·velocity updates/s",
+        "n_gpus": 1, "steps": tot["rounds"], "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "moments_dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "requests": len(reqs), "arrival_rate_per_s": spec["rate"],
+                   "stop": {"rule": "pxy_drift", "tol": spec["tol"], "max_steps": spec["max_steps"],
+                            "check_every": spec["check_every"]},
+                   "arena_mib": args.arena_mib, "parallelism": "single GPU, continuous batching"},
+        "serving": summ,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +152,8 @@ def main(argv=None):
                     help="steps per captured HIP graph (0 launches every kernel directly)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--arena-mib", type=int, default=4096, help="serving: device arena for resident solves")
+    ap.add_argument("--serve-wall-s", type=float, default=240.0, help="serving: wall-clock limit of the trace")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -119,6 +167,8 @@ def main(argv=None):
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
     spec = WORKLOADS[args.workload]
+    if spec["kind"] == "serve":
+        return _serve_main(args, spec)
     insts = _instances(spec)
     print(f"# building {len(insts)} instance(s) of {args.workload}", file=sys.stderr, flush=True)
     quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune)

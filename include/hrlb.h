@@ -177,6 +177,79 @@ hrlb_status hrlb_batch_set_graph_steps(hrlb_batch *b, int steps_per_graph);
  * of one launch of the stage kernel and of the per-cell kernel.  Synchronous. */
 hrlb_status hrlb_batch_profile(hrlb_batch *b, long n_steps, double *stage_kernel_ms, double *cell_kernel_ms);
 
+/* ---- serving: a request loop with continuous batching.  Couette solves (any velocity set, grid,
+ * delta, wall speed, wall temperature and viscosity index) are submitted as they arrive.  Each
+ * scheduling round (hrlb_server_pump) retires the solves that have stopped, admits waiting ones as
+ * slots and device memory allow, advances every resident solve by check_every steps with shared
+ * launches, and applies each solve's stop rule.  A solve's populations stay in device memory from
+ * admission until it stops.  Device memory comes from one caller-owned arena that the server
+ * sub-allocates (first fit, 256-byte blocks); a request is admitted only when its workspace and
+ * the batch's launch tables fit.  Admission follows arrival order; a later request may pass one
+ * that does not fit until that one has been passed max_bypass times.
+ * Every solve runs exactly the steps and checks that hrlb_run_to_steady(tol, max_steps,
+ * check_every, stop_rule) runs on the same case alone, so its results are the same bit for bit
+ * whatever else is resident.  Times are seconds on the server's monotonic clock.
+ * Not thread-safe: one thread drives a server. */
+typedef struct hrlb_server hrlb_server;
+
+typedef struct {
+    int max_active;   /* slots: solves resident and stepped together, >= 1                   */
+    int check_every;  /* steps per scheduling round (and between stop-rule checks), >= 1      */
+    int max_bypass;   /* backfill limit of the admission order, >= 0 (0 = strict FIFO)       */
+    int precision;    /* HRLB_FP64 or HRLB_FP32_STORE_FP64_MOM, the same for every request   */
+} hrlb_server_config;
+
+typedef struct {
+    int Qx, Nx_order, Qy, Ny_order; /* velocity set, as hrlb_init_quadrature (p0 = 1)             */
+    hrlb_case_params params;        /* as hrlb_init_case; params.precision = the server's        */
+    double tol;                     /* stop rule and tolerance, as hrlb_run_to_steady            */
+    int stop_rule;
+    long max_steps;                 /* a positive multiple of check_every                         */
+    double arrival_s;               /* arrival time on the server clock; < 0 means now           */
+} hrlb_solve_request;
+
+enum { HRLB_REQ_WAITING = 0, HRLB_REQ_ACTIVE = 1, HRLB_REQ_DONE = 2, HRLB_REQ_FAILED = 3 };
+
+typedef struct {
+    int state;          /* HRLB_REQ_*                                                         */
+    int status;         /* DONE: HRLB_OK (stop rule met) or HRLB_NOT_CONVERGED (max_steps);    */
+                        /* FAILED: the error (HRLB_E_DIVERGED, HRLB_E_DEVICE, ...)            */
+    long steps;         /* steps taken                                                         */
+    double residual, pxy_drift, Pi, sim_time, mass_drift;  /* as hrlb_steady_info/hrlb_moments */
+    double t_arrival, t_admit, t_done;                      /* server clock; -1 if not reached */
+    int n_cells, n_vel;
+    size_t bytes;       /* device workspace of the solve                                       */
+} hrlb_request_info;
+
+typedef struct {
+    int waiting, active, done, failed; /* counts after the round                               */
+    int admitted, retired;             /* in this round                                        */
+    long steps;                        /* steps per resident solve in this round (0 if idle)   */
+    double units;                      /* cell-velocity updates in this round                  */
+    double round_s;                    /* wall time of the round                               */
+    size_t arena_used, arena_largest_free;
+} hrlb_server_stats;
+
+/* Creates a server over the caller's device arena (256-byte aligned; it must stay allocated until
+ * hrlb_server_free) on the caller's stream.  Host-only apart from remembering the pointers. */
+hrlb_status hrlb_server_create(const hrlb_server_config *cfg, void *dev_arena, size_t arena_bytes, void *hip_stream,
+                               hrlb_server **out);
+/* Seconds since the server was created (monotonic clock). */
+double hrlb_server_clock(const hrlb_server *s);
+/* Queues a solve; *id receives its handle.  Validates everything hrlb_init_case would and
+ * rejects with HRLB_E_NOMEM a solve whose workspace can never fit the arena. */
+hrlb_status hrlb_server_submit(hrlb_server *s, const hrlb_solve_request *r, long *id);
+/* One scheduling round as described above.  Synchronous.  Returns HRLB_OK also when a solve
+ * failed (its request reports the error); a negative status means the server itself failed. */
+hrlb_status hrlb_server_pump(hrlb_server *s, hrlb_server_stats *stats);
+/* State and result of a request.  fields [10][n_cells] and x [n_cells] (as hrlb_moments) are
+ * written once the request is DONE; either may be NULL.  release != 0 forgets a DONE or FAILED
+ * request after the copy (its id becomes invalid). */
+hrlb_status hrlb_server_request(hrlb_server *s, long id, hrlb_request_info *info, double *fields, double *x,
+                                int release);
+/* Frees every resident solve, the cached velocity sets and the server.  The arena is the caller's. */
+void hrlb_server_free(hrlb_server *s);
+
 #ifdef __cplusplus
 }
 #endif

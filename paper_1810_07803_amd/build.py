@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libhrlb.so")
 ARCH = os.environ.get("HRLB_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["hrlb_kernels.hip", "hrlb_host.cpp", "hrlb_quadrature.cpp"]
+SOURCES = ["hrlb_kernels.hip", "hrlb_host.cpp", "hrlb_serve.cpp", "hrlb_quadrature.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I" + os.path.join(ROOT, "include")]
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -16,21 +16,15 @@
 #include "hrlb_internal.h"
 #include "hrlb_plan.h"
 #include "hrlb_quadrature.h"
+#include "hrlb_runtime.h"
 
 using namespace hrlb;
 
-extern "C" hipError_t hrlbk_stage(int fp32, const InstDesc* descs, const TileRef* tiles, int ntiles, int grid,
-                                  int stage, int flags, int qy_max, hipStream_t st);
-extern "C" hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int buf,
-                                 int flags, size_t shmem, hipStream_t st);
-extern "C" hipError_t hrlbk_finalize(const InstDesc* descs, int ninst, int with_res, hipStream_t st);
-extern "C" hipError_t hrlbk_init(int fp32, const InstDesc* descs, int inst, size_t units, hipStream_t st);
+namespace hrlb {
 
 namespace {
-
-enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2 };
-
 thread_local std::string g_err;
+}
 
 hrlb_status fail(hrlb_status st, const char* fmt, ...)
 {
@@ -43,97 +37,7 @@ hrlb_status fail(hrlb_status st, const char* fmt, ...)
     return st;
 }
 
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return fail(HRLB_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
-    } while (0)
-
-size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// launch parameters of a case or a batch, with its cached step-block graphs
-struct Launcher {
-    int fp32 = 0;
-    const InstDesc* descs = nullptr;
-    int ninst = 0;
-    const TileRef* tiles = nullptr;
-    int ntiles = 0;
-    const CellRef* cells = nullptr;
-    int ncellblocks = 0;
-    size_t shmem = 0;
-    int qy_max = 0;
-    hipStream_t stream = nullptr;
-    int graph_steps = 0;  // steps per captured graph; < 2 launches directly (faster on this stack)
-    int graph_len = 0;
-    hipGraphExec_t graph_plain = nullptr, graph_check = nullptr;
-    void drop_graphs()
-    {
-        if (graph_plain) (void)hipGraphExecDestroy(graph_plain);
-        if (graph_check) (void)hipGraphExecDestroy(graph_check);
-        graph_plain = graph_check = nullptr;
-        graph_len = 0;
-    }
-    ~Launcher() { drop_graphs(); }
-};
-
-}  // namespace
-
-// ------------------------------------------------------------------------------------------------
-struct hrlb_quad {
-    int qx, nxo, qy, nyo;
-    std::vector<double> zx, wx;        // [qx] positive nodes, weights
-    std::vector<double> px, wx2;       // [2qx] h-major
-    std::vector<double> zy, wy;        // [qy]
-    std::vector<double> hz;            // [(nxo+1)][qx]
-    std::vector<double> auxZ, auxW;    // [kAux]
-    std::vector<double> hZ;            // [(nxo+1)][kAux]
-    std::vector<double> he;            // [(nyo+1)][qy]
-};
-
-struct Layout {
-    size_t desc, dyn, tables, f[3], cell, fields, mom, res, tiles, cells, total;
-    // table offsets in doubles relative to `tables`
-    size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
-    int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
-    int ntile_list;  // records in the case's tile list (XCD-aware order, padded)
-};
-
-struct hrlb_case {
-    hrlb_case_params p;
-    const hrlb_quad* q;
-    char* ws;
-    size_t ws_bytes;
-    hipStream_t stream;
-    Layout L;
-    InstDesc desc;  // host copy of the device descriptor
-    InstDesc* d_desc;
-    TileRef* d_tiles;
-    CellRef* d_cells;
-    int ntiles;
-    int nv;
-    size_t shmem;  // dynamic LDS of the per-cell kernel
-    double dt;
-    long steps_done;
-    double mass0;
-    std::vector<double> x, jdeta;
-    double pxy_prev;
-    bool has_prev_pxy;
-    bool needs_analyze;  // moments/tables of the stored state not computed yet
-    Launcher run;
-};
-
-struct hrlb_batch {
-    std::vector<hrlb_case*> cases;
-    InstDesc* d_descs;
-    TileRef* d_tiles;
-    CellRef* d_cells;
-    int ntiles, ncellblocks;
-    int fp32;
-    size_t shmem;
-    int qy_max;
-    hipStream_t stream;
-    Launcher run;
-};
+}  // namespace hrlb
 
 // ------------------------------------------------------------------------------------------------
 // velocity set
@@ -405,20 +309,6 @@ hrlb_status graph_for(Launcher& L, bool check, hipGraphExec_t* out)
     return HRLB_OK;
 }
 
-hrlb_status enqueue_steps(Launcher& L, long n_steps, bool check_last)
-{
-    const int G = L.graph_steps;
-    if (G < 2 || n_steps < G) return enqueue_eager(L, n_steps, check_last, L.stream);
-    const long blocks = n_steps / G, rest = n_steps % G;
-    for (long b = 0; b < blocks; ++b) {
-        const bool chk = check_last && rest == 0 && b + 1 == blocks;
-        hipGraphExec_t ex = nullptr;
-        hrlb_status st = graph_for(L, chk, &ex);
-        if (st != HRLB_OK) return st;
-        HIP_TRY(hipGraphLaunch(ex, L.stream));
-    }
-    return rest ? enqueue_eager(L, rest, check_last, L.stream) : HRLB_OK;
-}
 
 hrlb_status analyze_case(hrlb_case* c)
 {
@@ -433,6 +323,21 @@ hrlb_status analyze_case(hrlb_case* c)
 hrlb_status ensure_analyzed(hrlb_case* c) { return c->needs_analyze ? analyze_case(c) : HRLB_OK; }
 
 }  // namespace
+
+hrlb_status hrlb::enqueue_steps(Launcher& L, long n_steps, bool check_last)
+{
+    const int G = L.graph_steps;
+    if (G < 2 || n_steps < G) return enqueue_eager(L, n_steps, check_last, L.stream);
+    const long blocks = n_steps / G, rest = n_steps % G;
+    for (long b = 0; b < blocks; ++b) {
+        const bool chk = check_last && rest == 0 && b + 1 == blocks;
+        hipGraphExec_t ex = nullptr;
+        hrlb_status st = graph_for(L, chk, &ex);
+        if (st != HRLB_OK) return st;
+        HIP_TRY(hipGraphLaunch(ex, L.stream));
+    }
+    return rest ? enqueue_eager(L, rest, check_last, L.stream) : HRLB_OK;
+}
 
 extern "C" hrlb_status hrlb_case_workspace_bytes(const hrlb_quad* q, const hrlb_case_params* p, size_t* bytes)
 {
@@ -468,8 +373,6 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     c->stream = (hipStream_t)hip_stream;
     c->L = L;
     c->steps_done = 0;
-    c->has_prev_pxy = false;
-    c->pxy_prev = 0.0;
     const int nx = p->n_cells, qx = q->qx, qy = q->qy, nv = 2 * qx * qy;
     c->nv = nv;
     grid_of(p, c->x, c->jdeta);
@@ -744,6 +647,18 @@ extern "C" hrlb_status hrlb_tune_plan(const hrlb_quad* q, const hrlb_case_params
     return HRLB_OK;
 }
 
+hrlb_status hrlb::steady_update(SteadyTrack& t, const double* dy, long n, double dt, double tol, int stop_rule)
+{
+    t.res = std::sqrt(dy[DY_RES_NUM]) / (dt * std::sqrt(dy[DY_RES_DEN]));
+    const double pxy = dy[DY_PXY_MEAN];
+    if (!std::isfinite(t.res) || !std::isfinite(pxy) || dy[DY_FLAGS] != 0.0) return HRLB_E_DIVERGED;
+    if (t.have_prev) t.drift = std::fabs(pxy - t.pxy_prev) / (n * dt * std::max(std::fabs(pxy), 1e-300));
+    t.have_prev = true;
+    t.pxy_prev = pxy;
+    const double crit = stop_rule == HRLB_STOP_RESIDUAL ? t.res : t.drift;
+    return (crit >= 0.0 && crit < tol) ? HRLB_OK : HRLB_NOT_CONVERGED;
+}
+
 extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_steps, int check_every, int stop_rule,
                                           hrlb_steady_info* info)
 {
@@ -756,11 +671,9 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         if (sa != HRLB_OK) return sa;
     }
     long taken = 0;
-    double res = -1.0, drift = -1.0;
     hrlb_status verdict = HRLB_NOT_CONVERGED;
     double dy[kNDyn];
-    bool have_prev = false;
-    double pxy_prev = 0.0;
+    SteadyTrack track;
     while (taken < max_steps) {
         const long n = std::min<long>(check_every, max_steps - taken);
         hrlb_status st = enqueue_steps(c->run, n, true);
@@ -769,22 +682,14 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         HIP_TRY(hipStreamSynchronize(c->stream));
         taken += n;
         c->steps_done += n;
-        res = std::sqrt(dy[DY_RES_NUM]) / (c->dt * std::sqrt(dy[DY_RES_DEN]));
-        const double pxy = dy[DY_PXY_MEAN];
-        if (!std::isfinite(res) || !std::isfinite(pxy) || dy[DY_FLAGS] != 0.0) {
-            verdict = HRLB_E_DIVERGED;
-            fail(HRLB_E_DIVERGED, "non-finite residual after %ld steps", c->steps_done);
-            break;
-        }
-        if (have_prev) drift = std::fabs(pxy - pxy_prev) / (n * c->dt * std::max(std::fabs(pxy), 1e-300));
-        have_prev = true;
-        pxy_prev = pxy;
-        const double crit = stop_rule == HRLB_STOP_RESIDUAL ? res : drift;
-        if (crit >= 0.0 && crit < tol) {
-            verdict = HRLB_OK;
+        const hrlb_status v = steady_update(track, dy, n, c->dt, tol, stop_rule);
+        if (v != HRLB_NOT_CONVERGED) {
+            verdict = v;
+            if (v == HRLB_E_DIVERGED) fail(HRLB_E_DIVERGED, "non-finite residual after %ld steps", c->steps_done);
             break;
         }
     }
+    const double res = track.res, drift = track.drift;
     if (info) {
         info->steps = taken;
         info->residual = res;

@@ -1,0 +1,132 @@
+// hrlb_runtime.h -- host-side objects behind the opaque handles of include/hrlb.h, shared by the
+// host runtime (hrlb_host.cpp) and the request server (hrlb_serve.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hrlb.h"
+#include "hrlb_internal.h"
+#include "hrlb_plan.h"
+
+extern "C" hipError_t hrlbk_stage(int fp32, const hrlb::InstDesc* descs, const hrlb::TileRef* tiles, int ntiles, int grid,
+                                  int stage, int flags, int qy_max, hipStream_t st);
+extern "C" hipError_t hrlbk_cell(int fp32, const hrlb::InstDesc* descs, const hrlb::CellRef* cells, int ncells, int buf,
+                                 int flags, size_t shmem, hipStream_t st);
+extern "C" hipError_t hrlbk_finalize(const hrlb::InstDesc* descs, int ninst, int with_res, hipStream_t st);
+extern "C" hipError_t hrlbk_init(int fp32, const hrlb::InstDesc* descs, int inst, size_t units, hipStream_t st);
+
+namespace hrlb {
+
+enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2 };
+
+hrlb_status fail(hrlb_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(HRLB_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// launch parameters of a case or a batch, with its cached step-block graphs
+struct Launcher {
+    int fp32 = 0;
+    const InstDesc* descs = nullptr;
+    int ninst = 0;
+    const TileRef* tiles = nullptr;
+    int ntiles = 0;
+    const CellRef* cells = nullptr;
+    int ncellblocks = 0;
+    size_t shmem = 0;
+    int qy_max = 0;
+    hipStream_t stream = nullptr;
+    int graph_steps = 0;  // steps per captured graph; < 2 launches directly (faster on this stack)
+    int graph_len = 0;
+    hipGraphExec_t graph_plain = nullptr, graph_check = nullptr;
+    void drop_graphs()
+    {
+        if (graph_plain) (void)hipGraphExecDestroy(graph_plain);
+        if (graph_check) (void)hipGraphExecDestroy(graph_check);
+        graph_plain = graph_check = nullptr;
+        graph_len = 0;
+    }
+    ~Launcher() { drop_graphs(); }
+};
+
+// residual and P_xy-drift bookkeeping of a steady-state run; the same rule serves
+// hrlb_run_to_steady and the request server, so both stop a case after the same step
+struct SteadyTrack {
+    bool have_prev = false;
+    double pxy_prev = 0.0;
+    double res = -1.0, drift = -1.0;
+};
+// dy: the case's dynamic scalars read after a block of n steps whose last step was checked.
+// Returns HRLB_OK when the stop criterion is below tol, HRLB_NOT_CONVERGED to go on, and
+// HRLB_E_DIVERGED (with the message set) on a non-finite value.
+hrlb_status steady_update(SteadyTrack& t, const double* dy, long n, double dt, double tol, int stop_rule);
+
+// byte offsets of the regions of a case workspace
+struct Layout {
+    size_t desc, dyn, tables, f[3], cell, fields, mom, res, tiles, cells, total;
+    // table offsets in doubles relative to `tables`
+    size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
+    int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
+    int ntile_list;  // records in the case's tile list (XCD-aware order, padded)
+};
+
+}  // namespace hrlb
+
+struct hrlb_quad {
+    int qx, nxo, qy, nyo;
+    std::vector<double> zx, wx;        // [qx] positive nodes, weights
+    std::vector<double> px, wx2;       // [2qx] h-major
+    std::vector<double> zy, wy;        // [qy]
+    std::vector<double> hz;            // [(nxo+1)][qx]
+    std::vector<double> auxZ, auxW;    // [kAux]
+    std::vector<double> hZ;            // [(nxo+1)][kAux]
+    std::vector<double> he;            // [(nyo+1)][qy]
+};
+
+struct hrlb_case {
+    hrlb_case_params p;
+    const hrlb_quad* q;
+    char* ws;
+    size_t ws_bytes;
+    hipStream_t stream;
+    hrlb::Layout L;
+    hrlb::InstDesc desc;  // host copy of the device descriptor
+    hrlb::InstDesc* d_desc;
+    hrlb::TileRef* d_tiles;
+    hrlb::CellRef* d_cells;
+    int ntiles;
+    int nv;
+    size_t shmem;  // dynamic LDS of the per-cell kernel
+    double dt;
+    long steps_done;
+    double mass0;
+    std::vector<double> x, jdeta;
+    bool needs_analyze;  // moments/tables of the stored state not computed yet
+    hrlb::Launcher run;
+};
+
+struct hrlb_batch {
+    std::vector<hrlb_case*> cases;
+    hrlb::InstDesc* d_descs;
+    hrlb::TileRef* d_tiles;
+    hrlb::CellRef* d_cells;
+    int ntiles, ncellblocks;
+    int fp32;
+    size_t shmem;
+    int qy_max;
+    hipStream_t stream;
+    hrlb::Launcher run;
+};
+
+namespace hrlb {
+// enqueue n steps of a case or a batch on its stream (residual check on the last step if asked)
+hrlb_status enqueue_steps(Launcher& L, long n_steps, bool check_last);
+}  // namespace hrlb

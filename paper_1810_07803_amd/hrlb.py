@@ -30,7 +30,10 @@ EXPORTED = (
     "hrlb_batch_workspace_bytes", "hrlb_batch_create", "hrlb_batch_step", "hrlb_batch_poll",
     "hrlb_batch_free", "hrlb_batch_profile", "hrlb_case_set_graph_steps", "hrlb_batch_set_graph_steps",
     "hrlb_tune_workspace_bytes", "hrlb_tune_plan",
+    "hrlb_server_create", "hrlb_server_clock", "hrlb_server_submit", "hrlb_server_pump", "hrlb_server_request",
+    "hrlb_server_free",
 )
+HRLB_REQ_WAITING, HRLB_REQ_ACTIVE, HRLB_REQ_DONE, HRLB_REQ_FAILED = 0, 1, 2, 3
 
 
 class HrlbError(RuntimeError):
@@ -51,6 +54,29 @@ class CaseParams(C.Structure):
 class SteadyInfo(C.Structure):
     _fields_ = [("steps", C.c_long), ("residual", C.c_double), ("pxy_drift", C.c_double),
                 ("sim_time", C.c_double), ("wall_s", C.c_double), ("mass_drift", C.c_double)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("max_active", C.c_int), ("check_every", C.c_int), ("max_bypass", C.c_int), ("precision", C.c_int)]
+
+
+class SolveRequest(C.Structure):
+    _fields_ = [("Qx", C.c_int), ("Nx_order", C.c_int), ("Qy", C.c_int), ("Ny_order", C.c_int),
+                ("params", CaseParams), ("tol", C.c_double), ("stop_rule", C.c_int), ("max_steps", C.c_long),
+                ("arrival_s", C.c_double)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int), ("status", C.c_int), ("steps", C.c_long), ("residual", C.c_double),
+                ("pxy_drift", C.c_double), ("Pi", C.c_double), ("sim_time", C.c_double),
+                ("mass_drift", C.c_double), ("t_arrival", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("n_cells", C.c_int), ("n_vel", C.c_int), ("bytes", C.c_size_t)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("waiting", C.c_int), ("active", C.c_int), ("done", C.c_int), ("failed", C.c_int),
+                ("admitted", C.c_int), ("retired", C.c_int), ("steps", C.c_long), ("units", C.c_double),
+                ("round_s", C.c_double), ("arena_used", C.c_size_t), ("arena_largest_free", C.c_size_t)]
 
 
 _lib = None
@@ -90,12 +116,18 @@ def load() -> C.CDLL:
                 "hrlb_tune_workspace_bytes": [vp, C.POINTER(CaseParams), C.POINTER(C.c_size_t)],
                 "hrlb_tune_plan": [vp, C.POINTER(CaseParams), vp, C.c_size_t, vp, C.c_int, ip, ip, dp],
                 "hrlb_batch_set_graph_steps": [vp, C.c_int],
+                "hrlb_server_create": [C.POINTER(ServerConfig), vp, C.c_size_t, vp, C.POINTER(vp)],
+                "hrlb_server_submit": [vp, C.POINTER(SolveRequest), C.POINTER(C.c_long)],
+                "hrlb_server_pump": [vp, C.POINTER(ServerStats)],
+                "hrlb_server_request": [vp, C.c_long, C.POINTER(RequestInfo), dp, dp, C.c_int],
             }
             for name, args in sig.items():
                 fn = getattr(lib, name)
                 fn.argtypes = args
                 fn.restype = C.c_int
-            for name in ("hrlb_free_case", "hrlb_free_quadrature", "hrlb_batch_free"):
+            lib.hrlb_server_clock.argtypes = [vp]
+            lib.hrlb_server_clock.restype = C.c_double
+            for name in ("hrlb_free_case", "hrlb_free_quadrature", "hrlb_batch_free", "hrlb_server_free"):
                 getattr(lib, name).argtypes = [vp]
                 getattr(lib, name).restype = None
             lib.hrlb_last_error.argtypes = []
@@ -286,6 +318,68 @@ class Batch:
     def free(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.hrlb_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.free()
+
+
+# ---- serving -----------------------------------------------------------------------------------
+class Server:
+    """Request loop with continuous batching over one torch-allocated device arena (hrlb_server_*)."""
+
+    def __init__(self, arena_bytes: int, *, max_active: int = 64, check_every: int = 200, max_bypass: int = 4,
+                 precision: int = HRLB_FP32_STORE_FP64_MOM, device="cuda:0", stream=None):
+        import torch
+
+        self.check_every, self.precision = check_every, precision
+        self._arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=device)
+        base = self._arena.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        cfg = ServerConfig(max_active, check_every, max_bypass, precision)
+        h = C.c_void_p()
+        _check(load().hrlb_server_create(C.byref(cfg), C.c_void_p(base + off), arena_bytes,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+        self._ncell = {}
+
+    def clock(self) -> float:
+        return load().hrlb_server_clock(self.handle)
+
+    def submit(self, Qx: int, Qy: int, params: CaseParams, *, tol: float, max_steps: int,
+               stop_rule: int = HRLB_STOP_PXY, Nx: int | None = None, Ny: int | None = None,
+               arrival_s: float = -1.0) -> int:
+        nxo = min(Qx - 1, 10) if Nx is None else Nx
+        nyo = Qy - 1 if Ny is None else Ny
+        req = SolveRequest(Qx, nxo, Qy, nyo, params, tol, stop_rule, max_steps, arrival_s)
+        rid = C.c_long()
+        _check(load().hrlb_server_submit(self.handle, C.byref(req), C.byref(rid)))
+        self._ncell[rid.value] = params.n_cells
+        return rid.value
+
+    def pump(self) -> ServerStats:
+        st = ServerStats()
+        _check(load().hrlb_server_pump(self.handle, C.byref(st)))
+        return st
+
+    def request(self, rid: int, release: bool = False):
+        """(info, fields [10][n_cells] or None, x or None) of a request."""
+        info = RequestInfo()
+        if rid not in self._ncell:  # unknown or released: the library reports the error
+            _check(load().hrlb_server_request(self.handle, rid, C.byref(info), None, None, 0))
+        n = self._ncell[rid]
+        f, x = np.zeros((10, n)), np.zeros(n)
+        _check(load().hrlb_server_request(self.handle, rid, C.byref(info), _dptr(f), _dptr(x), int(release)))
+        if release and info.state in (HRLB_REQ_DONE, HRLB_REQ_FAILED):
+            self._ncell.pop(rid, None)
+        if info.state != HRLB_REQ_DONE:
+            return info, None, None
+        return info, f, x
+
+    def free(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.hrlb_server_free(self.handle)
             self.handle = None
 
     def __del__(self):
