@@ -49,8 +49,9 @@ def _instances(spec):
     return [d]
 
 
-def _build(spec, insts, tune: bool):
-    """Cases of the workload; a single instance gets its stage-kernel tiling from the autotuner."""
+def _build(spec, insts, tune: bool, tile_vpt: int = 0, cell_lanes: int = 0):
+    """Cases of the workload; a single instance gets its stage-kernel tiling from the autotuner.
+    tile_vpt / cell_lanes > 0 impose a plan on every instance (where admissible)."""
     from paper_1810_07803_amd import hrlb
 
     quads, cases, tuned = {}, [], None
@@ -61,6 +62,10 @@ def _build(spec, insts, tune: bool):
         kw = dict(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
                   Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
                   precision=spec["precision"], rounding=spec["rounding"], seed=d.get("seed", 0))
+        if cell_lanes > 0:
+            kw["cell_lanes"] = cell_lanes
+        if tile_vpt > 0 and d["Qy"] % tile_vpt == 0:
+            kw["tile_vpt"] = tile_vpt
         if tune and len(insts) == 1:
             tuned = hrlb.tune_plan(quads[key], hrlb.make_params(**kw), n_steps=10)
             kw["tile_vpt"], kw["cell_lanes"] = tuned[0], tuned[1]
@@ -152,6 +157,10 @@ def main(argv=None):
                     help="steps per captured HIP graph (0 launches every kernel directly)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--cell-lanes", type=int, default=0, help="lanes per cell of the per-cell kernel for every "
+                    "instance (0 = each instance's automatic choice)")
+    ap.add_argument("--tile-vpt", type=int, default=0, help="velocities per stage-kernel row for every instance "
+                    "whose Qy it divides (0 = automatic)")
     ap.add_argument("--arena-mib", type=int, default=4096, help="serving: device arena for resident solves")
     ap.add_argument("--serve-wall-s", type=float, default=240.0, help="serving: wall-clock limit of the trace")
     args = ap.parse_args(argv)
@@ -171,7 +180,8 @@ def main(argv=None):
         return _serve_main(args, spec)
     insts = _instances(spec)
     print(f"# building {len(insts)} instance(s) of {args.workload}", file=sys.stderr, flush=True)
-    quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune)
+    quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune, tile_vpt=args.tile_vpt,
+                                        cell_lanes=args.cell_lanes)
     units = sum(c.nv * c.ncell for c in cases)
     batch.set_graph_steps(args.graph_steps)
     stream = torch.cuda.current_stream()
