@@ -87,7 +87,7 @@ typedef struct {
                       /* The choice fixes the summation order of the moments, so a case gives  */
                       /* bitwise the same numbers alone and in any batch for a given tile_vpt. */
     int cell_lanes;   /* lanes per cell of the per-cell kernel: 1, 2, 4, 8 or 16; 0 = automatic */
-                      /* (about 2 Qx / 8).  Also part of the plan that fixes summation order.   */
+                      /* (2).  Also part of the plan that fixes the summation order.            */
 } hrlb_case_params;
 
 /* Device workspace size (bytes) needed by a case with these parameters. */

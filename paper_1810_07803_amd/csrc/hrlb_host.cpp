@@ -178,9 +178,11 @@ int stage_grid(int ntiles) { return std::max(8, std::min(ntiles, 4096) / 8 * 8);
 // lanes per cell of the per-cell kernel: about a quarter of the x nodes of one half-line
 int auto_cell_lanes(int qx)
 {
-    int l = 1;
-    while (l < kMaxCellLanes && 4 * l < qx) l *= 2;
-    return l;
+    // two lanes per cell measured best for large ragged batches on MI355X (fewer redundant per-cell
+    // operations than wider splits, more parallelism than one lane); the autotuner picks wider
+    // splits for a lone case with few cells
+    (void)qx;
+    return 2;
 }
 
 Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
@@ -447,7 +449,9 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.rounding = p->precision == HRLB_FP32_STORE_FP64_MOM ? p->rounding : 0;
     D.collisionless = p->delta == 0.0;
     D.seed = p->seed;
-    D.ktab_n = (int)(L.t_he + (size_t)(q->nyo + 1) * qy - L.t_wx);
+    D.nxb = gx_rows(q->nxo);
+    D.nyb = gy_rows(q->nyo);
+    D.ktab_n = cell_lds(qx, qy, D.nxb, D.nyb, q->nyo).total;
     D.cell_lanes = L.cell_lanes;
     c->shmem = sizeof(double) * (size_t)D.ktab_n;
     c->run.shmem = c->shmem;

@@ -65,8 +65,10 @@ struct InstDesc {
     int rounding;  // 0 nearest, 1 stochastic (fp32 only)
     int collisionless;
     uint32_t seed;
-    int ktab_n;    // doubles from wx to the end of he (contiguous quadrature tables)
-    int cell_lanes;  // lanes per cell in the per-cell kernel (4, 8 or 16)
+    int ktab_n;    // doubles of the per-cell kernel's LDS copy of the quadrature tables (padded rows)
+    int cell_lanes;  // lanes per cell in the per-cell kernel (1, 2, 4, 8 or 16)
+    int nxb;       // rows of the padded h tables: gx_rows(nxo)
+    int nyb;       // rows of the padded He table: gy_rows(nyo), 0 = evaluated without the table padding
     int pad1;
     double dt, Tw, Pr, omega;
     double tau_pref;     // delta sqrt(2) sqrt(T_w): 1/tau = tau_pref n (T/T_w)^(1-omega)
@@ -95,6 +97,36 @@ struct InstDesc {
     const double* gw_r;  // [nv] g_x(0,T_w) g_y(+u_w,T_w)
     const double* g0;    // [nv] initial populations (rest equilibrium, n = 1)
 };
+
+// ---- padded table shapes of the per-cell kernel ---------------------------------------------
+// The per-cell kernel evaluates eqs. (gx) and (gy) with loops over the expansion order unrolled at
+// compile time for a few row counts; the tables are copied to LDS with zero rows up to that count.
+__host__ __device__ constexpr int gx_rows(int nxo)
+{
+    return nxo + 1 <= 4 ? 4 : nxo + 1 <= 8 ? 8 : nxo + 1 <= 11 ? 11 : 17;
+}
+__host__ __device__ constexpr int gy_rows(int nyo)
+{
+    return nyo + 1 <= 4 ? 4 : nyo + 1 <= 8 ? 8 : nyo + 1 <= 12 ? 12 : nyo + 1 <= 16 ? 16 : nyo + 1 <= 20 ? 20
+         : nyo + 1 <= 32 ? 32 : 0;
+}
+// LDS layout (doubles): wx[qx] wy[qy] auxZ[kAux] auxW[kAux] hZ[nxb][kAux] hz[nxb][qx] he[rows][qy]
+struct CellLds {
+    int wx, wy, az, aw, hZ, hz, he, total;
+};
+__host__ __device__ inline CellLds cell_lds(int qx, int qy, int nxb, int nyb, int nyo)
+{
+    CellLds o;
+    o.wx = 0;
+    o.wy = o.wx + qx;
+    o.az = o.wy + qy;
+    o.aw = o.az + kAux;
+    o.hZ = o.aw + kAux;
+    o.hz = o.hZ + nxb * kAux;
+    o.he = o.hz + nxb * qx;
+    o.total = o.he + (nyb > 0 ? nyb : nyo + 1) * qy;
+    return o;
+}
 
 // ---- equilibrium truncations (host and device) ------------------------------------------
 // g_{x,i}(u,T), i < 2 qx, following eq. gx as a projection: g_{x,i} = w_i sum_l h_l(z_i) I_l with

@@ -72,6 +72,8 @@ __device__ __forceinline__ double rcp6(double den) { return 1.0 / (6.0 * den); }
 //   beta0 = E_m + (d2m + 2 dm)^2/4, beta1 = E_c + (dm + dp)^2/4, beta2 = E_p + (d2p - 2 dp)^2/4,
 //   candidate values q_k = c + y_k/6 with y0 = 2 d2m + 3 dm, y1 = dm + 2 dp, y2 = 3 dp - d2p,
 //   weights 0.1, 0.6, 0.3 over (eps + beta_k)^2, normalised.
+// The code carries t_k = 4 (eps + beta_k) (em, ec, ep hold 4 E_x): the common factor cancels in
+// the normalised weights and saves a multiplication per indicator.
 // Contraction is off so that every call site produces the same bits from the same inputs.
 #pragma clang fp contract(off)
 template <typename T>
@@ -80,9 +82,9 @@ __device__ __forceinline__ T weno_d(T c, T dm, T dp, T d2m, T d2p, T em, T ec, T
     const T x0 = fma(T(2), dm, d2m);
     const T x1 = dm + dp;
     const T x2 = fma(T(-2), dp, d2p);
-    const T t0 = fma(T(0.25) * x0, x0, em);
-    const T t1 = fma(T(0.25) * x1, x1, ec);
-    const T t2 = fma(T(0.25) * x2, x2, ep);
+    const T t0 = fma(x0, x0, em);
+    const T t1 = fma(x1, x1, ec);
+    const T t2 = fma(x2, x2, ep);
     const T u0 = t0 * t0, u1 = t1 * t1, u2 = t2 * t2;
     const T a0 = u1 * u2, a1 = T(6) * (u0 * u2), a2 = T(3) * (u0 * u1);
     const T y0 = fma(T(2), d2m, T(3) * dm);
@@ -93,8 +95,9 @@ __device__ __forceinline__ T weno_d(T c, T dm, T dp, T d2m, T d2p, T em, T ec, T
     return fma(num, rcp6(den), c);
 }
 
+// 4 (13/12 d2^2 + eps), the scaled smoothness term of weno_d
 template <typename T>
-__device__ __forceinline__ T e_of(T d2) { return fma(T(13.0 / 12.0) * d2, d2, T(1e-6)); }
+__device__ __forceinline__ T e_of(T d2) { return fma(T(13.0 / 3.0) * d2, d2, T(4e-6)); }
 
 // face value from five cells in upwind order (used where no shared differences are at hand)
 template <typename T>
@@ -138,6 +141,15 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x)
     x ^= x >> 15;
     x *= 0x846ca68bu;
     x ^= x >> 16;
+    return x;
+}
+
+// xorshift32 (G. Marsaglia, 2003): cheap successors of a hashed word for the neighbouring cells
+__device__ __forceinline__ uint32_t xorshift32(uint32_t x)
+{
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
     return x;
 }
 
@@ -262,9 +274,13 @@ struct Win {
     }
 };
 
-// Per-tile staging of the cell tables in LDS, slot-major [slot][64 cells]: the per-cell scalars,
-// then g_y for every j of the instance, then g_x of the block's 16 rows.
+// Per-tile staging of the cell tables in LDS: the per-cell scalars, then g_y for every j of the
+// instance, then g_x of the block's 16 rows.  Inside a slot the 64 cells are stored as
+// [4 cells of a thread][16 threads of a row], so that the 16 lanes of a row read 16 consecutive
+// words; slots are kLdsSlot elements apart, which puts the 4 rows of a wave (reading slots one
+// apart for g_x) on disjoint bank ranges.
 __host__ __device__ constexpr int cell_lds_slots(int qy) { return kNSc + qy + kRows; }
+constexpr int kLdsSlot = kTileCells + kTPR;
 
 // ANALYZE: no update; partials of the current state f[0] (used after set-up or a state upload)
 template <typename T, bool ANALYZE>
@@ -329,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                 const int cell = c0 + 4 * q4;
                 bld4(rcell, ((uint32_t)src * nx + (uint32_t)(cell < nx ? cell : 0)) * es, v4);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) lds_cell[slot * kTileCells + 4 * q4 + c] = v4[c];
+                for (int c = 0; c < 4; ++c) lds_cell[slot * kLdsSlot + c * kTPR + q4] = v4[c];
             }
             // the face on this tile's right edge for each (row, velocity): thread (row, strip) takes
             // velocity k = strip of its row; the edge face F < nx - 3, so no ghost is involved
@@ -377,7 +393,6 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                 const uint32_t stepc = (uint32_t)D.dyn[DY_STEP];
                 rkey = hash32(D.seed ^ hash32(stepc * 3u + (uint32_t)stage + 0x9e3779b9u));
             }
-            const int lc = strip * kStrip;  // first cell of this thread inside the tile (LDS column)
             for (int k = 0; k < vpt; ++k, rowoff += rowstep) {
                 const int v = vbase + k;
                 const int j = v - hi * qy;
@@ -479,9 +494,9 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                     if (D.rounding) {
                         const uint32_t base = rkey ^ ((uint32_t)v * 0x85ebca6bu) ^ ((uint32_t)s0 * 0xc2b2ae35u);
 #pragma unroll
-                        for (int c = 0; c < kStrip; ++c) rbits[c] = hash32(base + (uint32_t)c);
+                        for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : xorshift32(rbits[c - 1]);
                     }
-                    int lcol = lc;
+                    int lcol = strip;
                     // an opaque column index keeps the compiler from hoisting the per-cell terms out of
                     // the velocity loop into registers (they stay in LDS; occupancy 3 instead of 2)
                     __asm__ volatile("" : "+v"(lcol));
@@ -489,13 +504,13 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 #pragma unroll
                     for (int c = 0; c < kStrip; ++c) {
                         const T p = P.w[4 + c], x = X.w[4 + c];
-                        const T ux = Lc[SC_UX * kTileCells + c], uy = Lc[SC_UY * kTileCells + c];
-                        const T Tt = Lc[SC_T * kTileCells + c], itau = Lc[SC_INVTAU * kTileCells + c];
-                        const T AS = Lc[SC_AS * kTileCells + c], A5 = Lc[SC_AS5T * kTileCells + c];
-                        const T qxv = Lc[SC_QX * kTileCells + c], qyv = Lc[SC_QY * kTileCells + c];
-                        const T ijd = Lc[SC_IJD * kTileCells + c];
-                        const T gy = Lc[(kNSc + j) * kTileCells + c];
-                        const T gx = Lc[(kNSc + qy + row) * kTileCells + c];
+                        const T ux = Lc[SC_UX * kLdsSlot + c * kTPR], uy = Lc[SC_UY * kLdsSlot + c * kTPR];
+                        const T Tt = Lc[SC_T * kLdsSlot + c * kTPR], itau = Lc[SC_INVTAU * kLdsSlot + c * kTPR];
+                        const T AS = Lc[SC_AS * kLdsSlot + c * kTPR], A5 = Lc[SC_AS5T * kLdsSlot + c * kTPR];
+                        const T qxv = Lc[SC_QX * kLdsSlot + c * kTPR], qyv = Lc[SC_QY * kLdsSlot + c * kTPR];
+                        const T ijd = Lc[SC_IJD * kLdsSlot + c * kTPR];
+                        const T gy = Lc[(kNSc + j) * kLdsSlot + c * kTPR];
+                        const T gx = Lc[(kNSc + qy + row) * kLdsSlot + c * kTPR];
                         // reduced Shakhov collision, Sec. II
                         const T xx = px - ux, xy = py - uy;
                         const T x2 = xx * xx + xy * xy;
@@ -616,7 +631,6 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 // (4, 8 or 16, by the size of the velocity set): the lanes of a cell split the sums of the moment
 // partials over velocity groups, the auxiliary-rule sums of g_x and the output nodes of g_x and
 // g_y, and combine their partial sums by an xor butterfly (identical bits in every lane).
-constexpr int kCyReg = 32;  // expansion orders N_y below this keep their coefficients in registers
 
 // leaving fluxes through one wall (eq. diffuse_nw): block-wide sums over the leaving directions of
 // p_x F and p_x p_y F, F the wall face value of the current state; fixed-order reduction
@@ -659,8 +673,125 @@ __device__ __forceinline__ double lane_sum(double x, int lanes)
     return x;
 }
 
+// eq. (gx) as the projection of g/omega on h_0..h_{NB-1} (rows beyond N_x are zero) with the
+// auxiliary rule: lane q of the cell takes nodes k = q, q + L, ...; two nodes per iteration keep two
+// independent exponential chains in flight (one node per iteration for the largest row count, whose
+// accumulators already fill the register budget).  Partial sums in k order, then an xor butterfly.
+template <int NB>
+__device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, double ux, const double* s_az,
+                                           const double* s_aw, const double* s_hZ, double (&Ip)[NB],
+                                           double (&Im)[NB])
+{
+#pragma unroll
+    for (int l = 0; l < NB; ++l) Ip[l] = Im[l] = 0.0;
+    const double inv2T = 0.5 / Tm;
+    const double rsT = 1.0 / sqrt(Tm);
+    const double c0 = (Tm - 1.0) * inv2T, c1 = ux * (2.0 * inv2T), c2 = ux * ux * inv2T;
+    int k = q;
+    for (; NB <= 11 && k + LN < kAux; k += 2 * LN) {
+        const double Z0 = s_az[k], Z1 = s_az[k + LN];
+        const double a0 = Z0 * Z0 * c0 - c2, a1 = Z1 * Z1 * c0 - c2;
+        const double b0 = Z0 * c1, b1 = Z1 * c1;
+        const double w0 = s_aw[k] * rsT, w1 = s_aw[k + LN] * rsT;
+        const double ep0 = w0 * exp(a0 + b0), ep1 = w1 * exp(a1 + b1);
+        const double em0 = w0 * exp(a0 - b0), em1 = w1 * exp(a1 - b1);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            const double h0 = s_hZ[l * kAux + k], h1 = s_hZ[l * kAux + k + LN];
+            Ip[l] += ep0 * h0;
+            Im[l] += em0 * h0;
+            Ip[l] += ep1 * h1;
+            Im[l] += em1 * h1;
+        }
+    }
+    for (; k < kAux; k += LN) {
+        const double Z = s_az[k];
+        const double a = Z * Z * c0 - c2, bb = Z * c1;
+        const double wk = s_aw[k] * rsT;
+        const double ep = wk * exp(a + bb), em = wk * exp(a - bb);
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            const double h = s_hZ[l * kAux + k];
+            Ip[l] += ep * h;
+            Im[l] += em * h;
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < NB; ++l)
+        if (l <= nxo) {  // uniform over the block
+            Ip[l] = lane_sum(Ip[l], LN);
+            Im[l] = lane_sum(Im[l], LN);
+        }
+}
+
+// g_x at the 2 Q_x nodes from the projections: n w_i sum_l I_l h_l(z_i)
+template <typename T, int NB>
+__device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, double Tm, double ux, bool on, int s,
+                                         int nx, int qxn, const double* s_wx, const double* s_az, const double* s_aw,
+                                         const double* s_hZ, const double* s_hz, T* cell)
+{
+    double Ip[NB], Im[NB];
+    gx_project<NB>(q, LN, nxo, Tm, ux, s_az, s_aw, s_hZ, Ip, Im);
+    for (int i = q; i < qxn; i += LN) {
+        double ap = 0.0, am = 0.0;
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            const double hz = s_hz[l * qxn + i];
+            ap += Ip[l] * hz;
+            am += Im[l] * hz;
+        }
+        const double nw = n * s_wx[i];
+        if (on) {
+            cell[(kNSc + i) * nx + s] = (T)(nw * ap);
+            cell[(kNSc + qxn + i) * nx + s] = (T)(nw * am);
+        }
+    }
+}
+
+// eq. (gy): c_l = coefficient of t^l in exp(u t + (T-1) t^2/2), l c_l = u c_{l-1} + (T-1) c_{l-2};
+// NB rows of the He table, zero beyond N_y
+template <typename T, int NB>
+__device__ __forceinline__ void gy_nodes(int q, int LN, int nyo, double uy, double Tm, bool on, int s, int nx,
+                                         int qxn, int nqy, const double* s_wy, const double* s_he, T* cell)
+{
+    const double tm1 = Tm - 1.0;
+    double cl[NB];
+    cl[0] = 1.0;
+    cl[1] = uy;
+#pragma unroll
+    for (int l = 2; l < NB; ++l) cl[l] = (uy * cl[l - 1] + tm1 * cl[l - 2]) * (1.0 / l);
+#pragma unroll
+    for (int l = 2; l < NB; ++l) cl[l] = l <= nyo ? cl[l] : 0.0;
+    for (int j = q; j < nqy; j += LN) {
+        double acc = 0.0;
+#pragma unroll
+        for (int l = 0; l < NB; ++l) acc += cl[l] * s_he[l * nqy + j];
+        if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
+    }
+}
+
+// the same for orders beyond the unrolled buckets: the recurrence runs once per output node
 template <typename T>
-__global__ __launch_bounds__(kCellThreads) void cell_kernel(const InstDesc* __restrict__ descs,
+__device__ __forceinline__ void gy_nodes_long(int q, int LN, int nyo, double uy, double Tm, bool on, int s, int nx,
+                                              int qxn, int nqy, const double* s_wy, const double* s_he, T* cell)
+{
+    const double tm1 = Tm - 1.0;
+    for (int j = q; j < nqy; j += LN) {
+        double c2 = 1.0, c1 = uy;
+        double acc = s_he[j] + uy * s_he[nqy + j];
+        for (int l = 2; l <= nyo; ++l) {
+            const double c = (uy * c1 + tm1 * c2) / l;
+            acc += c * s_he[l * nqy + j];
+            c2 = c1;
+            c1 = c;
+        }
+        if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
+    }
+}
+
+// at most 128 registers: 4 waves per SIMD (the largest projection bucket spills a few words)
+template <typename T>
+__global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4))) void cell_kernel(const InstDesc* __restrict__ descs,
                                                             const CellRef* __restrict__ cells, int buf, int flags)
 {
     extern __shared__ double ktab[];
@@ -673,17 +804,36 @@ __global__ __launch_bounds__(kCellThreads) void cell_kernel(const InstDesc* __re
     const bool on = s < nx;
     const int sc = on ? s : 0;
 
-    // the instance's quadrature tables are contiguous from wx to the end of he: stage them in LDS
-    const double* gbase = D.wx;
-    for (int k = threadIdx.x; k < D.ktab_n; k += blockDim.x) ktab[k] = gbase[k];
+    // moment partials of this cell: lane q sums the velocity groups g = q, q + L, ... (issued before
+    // the table staging so that their latency overlaps it)
+    double R[kNMom];
+#pragma unroll
+    for (int m = 0; m < kNMom; ++m) R[m] = 0.0;
+    for (int g = q; g < D.ngroups; g += LN)
+#pragma unroll
+        for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + sc];
+
+    // quadrature tables in LDS, rows of h and He padded with zeros to the unrolled counts
+    const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
+    const CellLds lay = cell_lds(qxn, nqy, nxb, nyb, nyo);
+    for (int k = threadIdx.x; k < qxn; k += blockDim.x) ktab[lay.wx + k] = D.wx[k];
+    for (int k = threadIdx.x; k < nqy; k += blockDim.x) ktab[lay.wy + k] = D.wy[k];
+    for (int k = threadIdx.x; k < kAux; k += blockDim.x) {
+        ktab[lay.az + k] = D.auxZ[k];
+        ktab[lay.aw + k] = D.auxW[k];
+    }
+    for (int k = threadIdx.x; k < nxb * kAux; k += blockDim.x) ktab[lay.hZ + k] = k < (nxo + 1) * kAux ? D.hZ[k] : 0.0;
+    for (int k = threadIdx.x; k < nxb * qxn; k += blockDim.x) ktab[lay.hz + k] = k < (nxo + 1) * qxn ? D.hz[k] : 0.0;
+    const int herows = nyb > 0 ? nyb : nyo + 1;
+    for (int k = threadIdx.x; k < herows * nqy; k += blockDim.x) ktab[lay.he + k] = k < (nyo + 1) * nqy ? D.he[k] : 0.0;
     __syncthreads();
-    const double* s_wx = ktab;
-    const double* s_wy = ktab + (D.wy - gbase);
-    const double* s_hz = ktab + (D.hz - gbase);
-    const double* s_az = ktab + (D.auxZ - gbase);
-    const double* s_aw = ktab + (D.auxW - gbase);
-    const double* s_hZ = ktab + (D.hZ - gbase);
-    const double* s_he = ktab + (D.he - gbase);
+    const double* s_wx = ktab + lay.wx;
+    const double* s_wy = ktab + lay.wy;
+    const double* s_az = ktab + lay.az;
+    const double* s_aw = ktab + lay.aw;
+    const double* s_hZ = ktab + lay.hZ;
+    const double* s_hz = ktab + lay.hz;
+    const double* s_he = ktab + lay.he;
 
     // walls: the block holding cell 0 does the left wall, the one holding cell nx-1 the right wall
     const T* fcur = (const T*)D.f[buf];
@@ -707,12 +857,6 @@ __global__ __launch_bounds__(kCellThreads) void cell_kernel(const InstDesc* __re
         }
     }
 
-    double R[kNMom];
-#pragma unroll
-    for (int m = 0; m < kNMom; ++m) R[m] = 0.0;
-    for (int g = q; g < D.ngroups; g += LN)
-#pragma unroll
-        for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + sc];
 #pragma unroll
     for (int m = 0; m < kNMom; ++m) R[m] = lane_sum(R[m], LN);
 
@@ -732,11 +876,11 @@ __global__ __launch_bounds__(kCellThreads) void cell_kernel(const InstDesc* __re
     const double qx = 0.5 * (R[6] - ux * b - 2.0 * cx + 2.0 * ux * c0 + u2 * (R[1] - ux * R[0]) + R[9] - ux * R[8]);
     const double qy = 0.5 * (R[7] - uy * b - 2.0 * cy + 2.0 * uy * c0 + u2 * (R[2] - uy * R[0]) + R[10] - uy * R[8]);
 
-    // eq. (tau) with mu ~ T^omega; Shakhov prefactor (1 - Pr)/(n K_B^2 T^2)
-    const double invtau = D.collisionless ? 0.0 : D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
-    const double As = (1.0 - D.Pr) / (n * Tm * Tm);
     T* cell = (T*)D.cell;
     if (on && q == 0) {
+        // eq. (tau) with mu ~ T^omega; Shakhov prefactor (1 - Pr)/(n K_B^2 T^2)
+        const double invtau = D.collisionless ? 0.0 : D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
+        const double As = (1.0 - D.Pr) / (n * Tm * Tm);
         double* F = D.fields;
         F[F_N * nx + s] = n;
         F[F_UX * nx + s] = ux;
@@ -759,79 +903,22 @@ __global__ __launch_bounds__(kCellThreads) void cell_kernel(const InstDesc* __re
         cell[SC_IJD * nx + s] = (T)D.inv_jdeta[s];
     }
 
-    // g_x (eq. gx) as the projection of g/omega on h_0..h_N computed with the auxiliary rule; the
-    // exponents for the two half-lines differ only in the sign of the term linear in u.  Lane q of
-    // the cell takes auxiliary nodes k = q mod L; the lanes then sum their partial projections.
-    const int qxn = D.qx, nxo = D.nxo;
-    const double inv2T = 0.5 / Tm;
-    const double rsT = 1.0 / sqrt(Tm);
-    double Ip[kMaxNx + 1], Im[kMaxNx + 1];
-#pragma unroll
-    for (int l = 0; l <= kMaxNx; ++l) Ip[l] = Im[l] = 0.0;
-    for (int k = q; k < kAux; k += LN) {
-        const double Z = s_az[k];
-        const double a = (Z * Z * (Tm - 1.0) - ux * ux) * inv2T;
-        const double bb = Z * ux * (2.0 * inv2T);
-        const double wk = s_aw[k] * rsT;
-        const double ep = wk * exp(a + bb), em = wk * exp(a - bb);
-#pragma unroll
-        for (int l = 0; l <= kMaxNx; ++l)
-            if (l <= nxo) {
-                const double hz = s_hZ[l * kAux + k];
-                Ip[l] += ep * hz;
-                Im[l] += em * hz;
-            }
+    // g_x (eq. gx) and g_y (eq. gy) with the loops over the expansion order unrolled for the case's
+    // padded row count (uniform over the block)
+    switch (nxb) {
+        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
+        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
+        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
+        default: gx_nodes<T, 17>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
     }
-#pragma unroll
-    for (int l = 0; l <= kMaxNx; ++l)
-        if (l <= nxo) {
-            Ip[l] = lane_sum(Ip[l], LN);
-            Im[l] = lane_sum(Im[l], LN);
-        }
-    for (int i = q; i < qxn; i += LN) {
-        double ap = 0.0, am = 0.0;
-#pragma unroll
-        for (int l = 0; l <= kMaxNx; ++l)
-            if (l <= nxo) {
-                const double hz = s_hz[l * qxn + i];
-                ap += Ip[l] * hz;
-                am += Im[l] * hz;
-            }
-        const double nw = n * s_wx[i];
-        if (on) {
-            cell[(kNSc + i) * nx + s] = (T)(nw * ap);
-            cell[(kNSc + qxn + i) * nx + s] = (T)(nw * am);
-        }
-    }
-
-    // g_y (eq. gy): c_l = coefficient of t^l in exp(u t + (T-1) t^2/2), l c_l = u c_{l-1} + (T-1) c_{l-2}
-    const int nqy = D.qy, nyo = D.nyo;
-    const double tm1 = Tm - 1.0;
-    if (nyo < kCyReg) {
-        double cl[kCyReg];
-        cl[0] = 1.0;
-        cl[1] = uy;
-#pragma unroll
-        for (int l = 2; l < kCyReg; ++l) cl[l] = (uy * cl[l - 1] + tm1 * cl[l - 2]) * (1.0 / l);
-        for (int j = q; j < nqy; j += LN) {
-            double acc = 0.0;
-#pragma unroll
-            for (int l = 0; l < kCyReg; ++l)
-                if (l <= nyo) acc += cl[l] * s_he[l * nqy + j];
-            if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
-        }
-    } else {
-        for (int j = q; j < nqy; j += LN) {
-            double c2 = 1.0, c1 = uy;
-            double acc = s_he[j] + uy * s_he[nqy + j];
-            for (int l = 2; l <= nyo; ++l) {
-                const double c = (uy * c1 + tm1 * c2) / l;
-                acc += c * s_he[l * nqy + j];
-                c2 = c1;
-                c1 = c;
-            }
-            if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
-        }
+    switch (nyb) {
+        case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 12: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 16: gy_nodes<T, 16>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 20: gy_nodes<T, 20>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 32: gy_nodes<T, 32>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        default: gy_nodes_long<T>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
     }
 }
 
@@ -900,7 +987,7 @@ using namespace hrlb;
 extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_stage_lds(int fp32, int qy_max)
 {
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
-    const size_t cells = (size_t)cell_lds_slots(qy_max) * kTileCells * es;
+    const size_t cells = (size_t)cell_lds_slots(qy_max) * kLdsSlot * es;
     const size_t moms = sizeof(double) * kMomPerPass * kRows * kTileCells;
     return cells > moms ? cells : moms;
 }
