@@ -282,12 +282,15 @@ struct Win {
 __host__ __device__ constexpr int cell_lds_slots(int qy) { return kNSc + qy + kRows; }
 constexpr int kLdsSlot = kTileCells + kTPR;
 
-// ANALYZE: no update; partials of the current state f[0] (used after set-up or a state upload)
-template <typename T, bool ANALYZE>
+// MODE: kModeAnalyze (no update; partials of the current state f[0], used after set-up or a state
+// upload), kModeStep, kModeResid (a step whose stage 3 also forms the residual partials)
+enum : int { kModeAnalyze = 0, kModeStep = 1, kModeResid = 2 };
+template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restrict__ descs,
                                                          const TileRef* __restrict__ tiles, int ntiles,
-                                                         int stage, int flags)
+                                                         int stage)
 {
+    constexpr bool ANALYZE = MODE == kModeAnalyze;
     // dynamic LDS: [union of (cell tables of the tile) and (moment reduction)] + boundary faces
     extern __shared__ __align__(16) unsigned char smem[];
     double(*lds_mom)[kRows][kTileCells] = reinterpret_cast<double(*)[kRows][kTileCells]>(smem);
@@ -301,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
     const int out_idx = ANALYZE ? 0 : (stage == 0 ? 1 : stage == 1 ? 2 : 0);
     const double ca = stage == 1 ? 0.75 : stage == 2 ? (1.0 / 3.0) : 0.0;
     const double cb = stage == 1 ? 0.25 : stage == 2 ? (2.0 / 3.0) : 1.0;
-    const bool want_res = !ANALYZE && (flags & FLAG_RESID) && stage == 2;
+    constexpr bool want_res = MODE == kModeResid;
     constexpr uint32_t es = sizeof(T);
 
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -584,19 +587,21 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
             for (int mm = 0; mm < kMomPerPass; ++mm) {
                 const int m = pass * kMomPerPass + mm;
                 if (m < kNMom) {
+                    // position c * 16 + strip: the 16 lanes of a row write 16 consecutive words
 #pragma unroll
-                    for (int c = 0; c < kStrip; ++c) lds_mom[mm][row][strip * kStrip + c] = m11[m][c];
+                    for (int c = 0; c < kStrip; ++c) lds_mom[mm][row][c * kTPR + strip] = m11[m][c];
                 }
             }
             __syncthreads();
             {
-                const int mm = tid / kTileCells, cc = tid % kTileCells;
+                // lane l of the reading wave takes position l: cell 4 (l % 16) + l / 16 of the tile
+                const int mm = tid / kTileCells, pos = tid % kTileCells;
                 const int m = pass * kMomPerPass + mm;
-                const int cellx = c0 + cc;
+                const int cellx = c0 + (pos % kTPR) * kStrip + pos / kTPR;
                 if (m < kNMom && cellx < nx) {
                     double s = 0.0;
 #pragma unroll
-                    for (int r = 0; r < kRows; ++r) s += lds_mom[mm][r][cc];
+                    for (int r = 0; r < kRows; ++r) s += lds_mom[mm][r][pos];
                     D.mom_part[((size_t)tr.group * kNMom + m) * nx + cellx] = s;
                 }
             }
@@ -999,15 +1004,18 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_stage(int fp32
     const size_t lds = hrlbk_stage_lds(fp32, qy_max);
     if (stage < 0) {
         if (fp32)
-            hipLaunchKernelGGL((stage_kernel<float, true>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0, 0);
+            hipLaunchKernelGGL((stage_kernel<float, kModeAnalyze>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0);
         else
-            hipLaunchKernelGGL((stage_kernel<double, true>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0, 0);
+            hipLaunchKernelGGL((stage_kernel<double, kModeAnalyze>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0);
+    } else if ((flags & FLAG_RESID) && stage == 2) {
+        if (fp32)
+            hipLaunchKernelGGL((stage_kernel<float, kModeResid>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
+        else
+            hipLaunchKernelGGL((stage_kernel<double, kModeResid>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
     } else if (fp32) {
-        hipLaunchKernelGGL((stage_kernel<float, false>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage,
-                           flags);
+        hipLaunchKernelGGL((stage_kernel<float, kModeStep>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
     } else {
-        hipLaunchKernelGGL((stage_kernel<double, false>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage,
-                           flags);
+        hipLaunchKernelGGL((stage_kernel<double, kModeStep>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
     }
     return hipGetLastError();
 }
