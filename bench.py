@@ -157,6 +157,8 @@ def main(argv=None):
                     help="steps per captured HIP graph (0 launches every kernel directly)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="parts of the batch advanced on separate streams (1-4)")
     ap.add_argument("--cell-lanes", type=int, default=0, help="lanes per cell of the per-cell kernel for every "
                     "instance (0 = each instance's automatic choice)")
     ap.add_argument("--tile-vpt", type=int, default=0, help="velocities per stage-kernel row for every instance "
@@ -184,6 +186,7 @@ def main(argv=None):
                                         cell_lanes=args.cell_lanes)
     units = sum(c.nv * c.ncell for c in cases)
     batch.set_graph_steps(args.graph_steps)
+    batch.set_streams(args.streams)
     stream = torch.cuda.current_stream()
 
     batch.step(args.warmup)
@@ -200,7 +203,11 @@ def main(argv=None):
     ms_per_step = ev0.elapsed_time(ev1) / args.steps
     value = units / (ms_per_step * 1e-3)
 
+    # kernel roofline on whole-batch launches that have the GPU to themselves (one stream), so that a
+    # launch's bytes and duration belong to the same work; the timed steps above use args.streams
+    batch.set_streams(1)
     stage_ms, cell_ms = batch.profile(args.profile_steps)
+    batch.set_streams(args.streams)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -219,9 +226,10 @@ def main(argv=None):
     traffic = profiling.load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_stage_kernel_traffic.txt"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "stage_kernel<%s>" % ("float" if es == 4 else "double"),
+                "kernel": "stage_kernel<%s, 1>" % ("float" if es == 4 else "double"),
                 "kernel_ms": round(stage_ms, 4), "cell_kernel_ms": round(cell_ms, 4),
-                "bytes_per_unit_per_launch": bytes_per_unit, "units_per_launch": units}
+                "bytes_per_unit_per_launch": bytes_per_unit, "units_per_launch": units,
+                "launches": "whole batch on one stream"}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -243,7 +251,7 @@ def main(argv=None):
         "moments_dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "instances": len(cases), "units_per_step": units,
-                   "graph_steps": args.graph_steps, "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
+                   "graph_steps": args.graph_steps, "streams": args.streams, "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
                    "parallelism": "single GPU, instances batched per launch"},
         "wall_s_timed": wall,
         "roofline": roofline,

@@ -150,11 +150,14 @@ void hrlb_free_case(hrlb_case *c);
 void hrlb_free_quadrature(hrlb_quad *q);
 const char *hrlb_last_error(void);
 
-/* ---- batching: several cases, possibly of different sizes and velocity sets, advanced by the
- * same kernel launches (one persistent launch per stage for the whole batch).  Each case keeps
- * its own workspace and results; a case's numbers are the same alone and in any batch.  All
+/* ---- batching: several cases, possibly of different sizes and velocity sets, advanced by shared
+ * kernel launches.  The cases are split into parts of about equal work (velocities x cells); each
+ * part is advanced by one persistent launch per stage and kernel on a stream of its own, forked
+ * from and joined back into the cases' stream, so that one part's per-cell kernel overlaps another
+ * part's stage kernel.  Two parts by default (one for a single case).  Each case keeps its own
+ * workspace and results; a case's numbers are the same alone, in any batch and in any split.  All
  * cases must share one stream and one precision.  The batch needs its own device workspace for
- * descriptors and the tile list. */
+ * descriptors and tile lists (sized for any split into 1 to 4 parts). */
 hrlb_status hrlb_batch_workspace_bytes(hrlb_case *const *cases, int n_cases, size_t *bytes);
 hrlb_status hrlb_batch_create(hrlb_case *const *cases, int n_cases, void *dev_workspace, size_t ws_bytes,
                               hrlb_batch **out);
@@ -164,6 +167,9 @@ hrlb_status hrlb_batch_step(hrlb_batch *b, long n_steps, int check);
 /* Synchronous: residual[i], pxy_mean[i] of case i from the last checked step (NULL allowed). */
 hrlb_status hrlb_batch_poll(hrlb_batch *b, double *residual, double *pxy_mean);
 void hrlb_batch_free(hrlb_batch *b);
+/* Splits the batch into n_streams parts (1..4), each on its own stream; synchronous (waits for the
+ * batch's stream, then re-uploads the launch tables). */
+hrlb_status hrlb_batch_set_streams(hrlb_batch *b, int n_streams);
 
 /* Step blocks of this many steps are captured once as a HIP graph (on a library-private stream)
  * and replayed on the case's or batch's stream; 0 or 1 launches every kernel directly (default:

@@ -780,52 +780,170 @@ extern "C" hrlb_status hrlb_set_state(hrlb_case* c, const double* host_state)
 // ------------------------------------------------------------------------------------------------
 // batches
 namespace {
-struct BatchLayout {
-    size_t descs, tiles, cells, total;
-    int ntiles, ncellblocks;
-};
+constexpr int kMaxBatchParts = 4;
 
-// tile list of a batch: natural sequence over cases, then the XCD-aware order weighted by work
-std::vector<TileRef> batch_tiles(hrlb_case* const* cases, int n)
+// cases of a batch split into n parts of about equal work (units = velocities x cells): largest first
+// onto the least loaded part; each part keeps its cases in ascending order
+std::vector<std::vector<int>> split_batch(hrlb_case* const* cases, int n, int parts)
 {
-    std::vector<PlanShape> shapes(n);
-    for (int i = 0; i < n; ++i)
-        shapes[i] = PlanShape{cases[i]->L.nctiles, cases[i]->L.ngroups, cases[i]->L.vpt, cases[i]->p.n_cells};
+    parts = std::max(1, std::min(parts, n));
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto units = [&](int i) { return (double)cases[i]->nv * cases[i]->p.n_cells; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return units(a) > units(b); });
+    std::vector<std::vector<int>> out(parts);
+    std::vector<double> load(parts, 0.0);
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        out[k].push_back(i);
+        load[k] += units(i);
+    }
+    for (auto& v : out) std::sort(v.begin(), v.end());
+    return out;
+}
+
+// tile list of a set of cases: natural sequence over the cases, then the XCD-aware order
+std::vector<TileRef> part_tiles(hrlb_case* const* cases, const std::vector<int>& idx)
+{
+    std::vector<PlanShape> shapes;
+    for (int i : idx)
+        shapes.push_back(PlanShape{cases[i]->L.nctiles, cases[i]->L.ngroups, cases[i]->L.vpt, cases[i]->p.n_cells});
     return plan_batch_tiles(shapes);
 }
 
-hrlb_status batch_layout(hrlb_case* const* cases, int n, BatchLayout* B)
+struct PartLayout {
+    size_t descs, tiles, cells;
+    int ntiles, ncellblocks;
+};
+
+// workspace layout of a batch split into `parts` parts (descriptors, tile list and cell list per part)
+size_t parts_layout(hrlb_case* const* cases, const std::vector<std::vector<int>>& split, std::vector<PartLayout>* L)
+{
+    size_t off = 0;
+    if (L) L->clear();
+    for (const auto& idx : split) {
+        PartLayout P{};
+        P.ntiles = (int)part_tiles(cases, idx).size();
+        P.ncellblocks = 0;
+        for (int i : idx) P.ncellblocks += cases[i]->L.ncellblocks;
+        P.descs = off;
+        off = align256(off + sizeof(InstDesc) * idx.size());
+        P.tiles = off;
+        off = align256(off + sizeof(TileRef) * P.ntiles);
+        P.cells = off;
+        off = align256(off + sizeof(CellRef) * P.ncellblocks);
+        if (L) L->push_back(P);
+    }
+    return off;
+}
+
+hrlb_status batch_check(hrlb_case* const* cases, int n)
 {
     if (!cases || n < 1) return fail(HRLB_E_INVALID, "empty batch");
-    int nc = 0;
     for (int i = 0; i < n; ++i) {
         if (!cases[i]) return fail(HRLB_E_INVALID, "case %d is NULL", i);
         if (cases[i]->p.precision != cases[0]->p.precision) return fail(HRLB_E_INVALID, "mixed precisions in a batch");
         if (cases[i]->stream != cases[0]->stream) return fail(HRLB_E_INVALID, "cases of a batch must share a stream");
-        nc += cases[i]->L.ncellblocks;
     }
-    const int nt = (int)batch_tiles(cases, n).size();
-    size_t off = 0;
-    B->descs = off;
-    off = align256(off + sizeof(InstDesc) * n);
-    B->tiles = off;
-    off = align256(off + sizeof(TileRef) * nt);
-    B->cells = off;
-    off = align256(off + sizeof(CellRef) * nc);
-    B->total = off;
-    B->ntiles = nt;
-    B->ncellblocks = nc;
+    return HRLB_OK;
+}
+
+// workspace that holds the launch tables of any split into 1..kMaxBatchParts parts
+size_t batch_bytes(hrlb_case* const* cases, int n)
+{
+    size_t m = 0;
+    for (int p = 1; p <= kMaxBatchParts; ++p) m = std::max(m, parts_layout(cases, split_batch(cases, n, p), nullptr));
+    return m;
+}
+
+// (re)builds the parts of a batch inside its workspace and uploads their tables (synchronous)
+hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
+{
+    const int n = (int)b->cases.size();
+    hrlb_case* const* cases = b->cases.data();
+    const auto split = split_batch(cases, n, nparts);
+    std::vector<PartLayout> L;
+    const size_t need = parts_layout(cases, split, &L);
+    if (need > b->ws_bytes) return fail(HRLB_E_INVALID, "internal: batch workspace too small for %d parts", nparts);
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->parts.clear();
+    for (size_t k = 0; k < split.size(); ++k) {
+        auto part = std::make_unique<hrlb_batch_part>();
+        hrlb_batch_part& P = *part;
+        P.idx = split[k];
+        P.d_descs = (InstDesc*)(b->ws + L[k].descs);
+        P.d_tiles = (TileRef*)(b->ws + L[k].tiles);
+        P.d_cells = (CellRef*)(b->ws + L[k].cells);
+        P.ntiles = L[k].ntiles;
+        P.ncellblocks = L[k].ncellblocks;
+        if (k == 0) {
+            P.stream = b->stream;
+        } else {
+            HIP_TRY(hipStreamCreateWithFlags(&P.stream, hipStreamNonBlocking));
+            P.own_stream = true;
+            HIP_TRY(hipEventCreateWithFlags(&P.done, hipEventDisableTiming));
+        }
+        const int ni = (int)P.idx.size();
+        std::vector<InstDesc> descs(ni);
+        std::vector<CellRef> cells;
+        std::vector<int> nct(ni), ngr(ni);
+        for (int q = 0; q < ni; ++q) {
+            const hrlb_case* c = cases[P.idx[q]];
+            descs[q] = c->desc;
+            nct[q] = c->L.nctiles;
+            ngr[q] = c->L.ngroups;
+            for (int t = 0; t < c->L.ncellblocks; ++t) cells.push_back(CellRef{q, t * (kCellThreads / c->L.cell_lanes)});
+        }
+        const std::vector<TileRef> tiles = part_tiles(cases, P.idx);
+        if ((int)tiles.size() != P.ntiles || (int)cells.size() != P.ncellblocks ||
+            !tiles_valid(tiles, (size_t)P.ntiles, ni, nct.data(), ngr.data()))
+            return fail(HRLB_E_INVALID, "internal: inconsistent batch tile list");
+        HIP_TRY(hipMemcpyAsync(P.d_descs, descs.data(), sizeof(InstDesc) * ni, hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(P.d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice,
+                               b->stream));
+        HIP_TRY(hipMemcpyAsync(P.d_cells, cells.data(), sizeof(CellRef) * cells.size(), hipMemcpyHostToDevice,
+                               b->stream));
+        P.run.fp32 = b->fp32;
+        P.run.descs = P.d_descs;
+        P.run.ninst = ni;
+        P.run.tiles = P.d_tiles;
+        P.run.ntiles = P.ntiles;
+        P.run.cells = P.d_cells;
+        P.run.ncellblocks = P.ncellblocks;
+        P.run.shmem = b->shmem;
+        P.run.qy_max = b->qy_max;
+        P.run.stream = P.stream;
+        P.run.graph_steps = b->graph_steps;
+        b->parts.push_back(std::move(part));
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return HRLB_OK;
+}
+
+// parts 1.. start after everything already on the batch's stream and the batch's stream waits for them
+hrlb_status batch_fork(hrlb_batch* b)
+{
+    if (b->parts.size() < 2) return HRLB_OK;
+    HIP_TRY(hipEventRecord(b->fork, b->stream));
+    for (size_t k = 1; k < b->parts.size(); ++k) HIP_TRY(hipStreamWaitEvent(b->parts[k]->stream, b->fork, 0));
+    return HRLB_OK;
+}
+hrlb_status batch_join(hrlb_batch* b)
+{
+    for (size_t k = 1; k < b->parts.size(); ++k) {
+        HIP_TRY(hipEventRecord(b->parts[k]->done, b->parts[k]->stream));
+        HIP_TRY(hipStreamWaitEvent(b->stream, b->parts[k]->done, 0));
+    }
     return HRLB_OK;
 }
 }  // namespace
 
 extern "C" hrlb_status hrlb_batch_workspace_bytes(hrlb_case* const* cases, int n_cases, size_t* bytes)
 {
-    BatchLayout B;
-    hrlb_status st = batch_layout(cases, n_cases, &B);
+    hrlb_status st = batch_check(cases, n_cases);
     if (st != HRLB_OK) return st;
     if (!bytes) return fail(HRLB_E_INVALID, "bytes is NULL");
-    *bytes = B.total;
+    *bytes = batch_bytes(cases, n_cases);
     return HRLB_OK;
 }
 
@@ -834,83 +952,59 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
 {
     if (!out) return fail(HRLB_E_INVALID, "out is NULL");
     *out = nullptr;
-    BatchLayout B;
-    hrlb_status st = batch_layout(cases, n_cases, &B);
+    hrlb_status st = batch_check(cases, n_cases);
     if (st != HRLB_OK) return st;
     if (!dev_workspace || ((uintptr_t)dev_workspace & 255)) return fail(HRLB_E_INVALID, "workspace NULL or misaligned");
-    if (ws_bytes < B.total) return fail(HRLB_E_NOMEM, "batch workspace of %zu bytes < %zu", ws_bytes, B.total);
-    hrlb_batch* b = new (std::nothrow) hrlb_batch;
+    const size_t need = batch_bytes(cases, n_cases);
+    if (ws_bytes < need) return fail(HRLB_E_NOMEM, "batch workspace of %zu bytes < %zu", ws_bytes, need);
+    std::unique_ptr<hrlb_batch> b(new (std::nothrow) hrlb_batch);
     if (!b) return fail(HRLB_E_NOMEM, "host allocation failed");
     b->cases.assign(cases, cases + n_cases);
-    char* ws = (char*)dev_workspace;
-    b->d_descs = (InstDesc*)(ws + B.descs);
-    b->d_tiles = (TileRef*)(ws + B.tiles);
-    b->d_cells = (CellRef*)(ws + B.cells);
-    b->ntiles = B.ntiles;
-    b->ncellblocks = B.ncellblocks;
+    b->ws = (char*)dev_workspace;
+    b->ws_bytes = ws_bytes;
     b->fp32 = cases[0]->p.precision == HRLB_FP32_STORE_FP64_MOM;
     b->stream = cases[0]->stream;
-    b->shmem = 0;
-    b->qy_max = 0;
     for (int i = 0; i < n_cases; ++i) {
         b->shmem = std::max(b->shmem, cases[i]->shmem);
         b->qy_max = std::max(b->qy_max, cases[i]->q->qy);
     }
-    b->run.fp32 = b->fp32;
-    b->run.descs = b->d_descs;
-    b->run.ninst = n_cases;
-    b->run.tiles = b->d_tiles;
-    b->run.ntiles = b->ntiles;
-    b->run.cells = b->d_cells;
-    b->run.ncellblocks = b->ncellblocks;
-    b->run.shmem = b->shmem;
-    b->run.qy_max = b->qy_max;
-    b->run.stream = b->stream;
-    std::vector<InstDesc> descs(n_cases);
-    std::vector<CellRef> cells;
-    std::vector<int> nct(n_cases), ngr(n_cases);
-    for (int i = 0; i < n_cases; ++i) {
-        const hrlb_case* c = cases[i];
-        descs[i] = c->desc;
-        nct[i] = c->L.nctiles;
-        ngr[i] = c->L.ngroups;
-        for (int k = 0; k < c->L.ncellblocks; ++k) cells.push_back(CellRef{i, k * (kCellThreads / c->L.cell_lanes)});
-    }
-    const std::vector<TileRef> tiles = batch_tiles(cases, n_cases);
-    if ((int)tiles.size() != b->ntiles || (int)cells.size() != b->ncellblocks ||
-        !tiles_valid(tiles, (size_t)b->ntiles, n_cases, nct.data(), ngr.data())) {
-        delete b;
-        return fail(HRLB_E_INVALID, "internal: inconsistent batch tile list");
-    }
-    hipError_t e = hipMemcpyAsync(b->d_descs, descs.data(), sizeof(InstDesc) * n_cases, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_cells, cells.data(), sizeof(CellRef) * cells.size(), hipMemcpyHostToDevice, b->stream);
-    // one analysis pass over the whole batch brings every case's moments up to date (it reproduces
-    // bit for bit what a case already analysed holds)
+    HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    // one analysis pass brings every case's moments up to date (it reproduces bit for bit what a
+    // case already analysed holds); it runs on one part holding all cases
     bool any = false;
     for (int i = 0; i < n_cases; ++i) any = any || cases[i]->needs_analyze;
-    if (e == hipSuccess && any) {
-        e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, stage_grid(b->ntiles), -1, 0, b->qy_max, b->stream);
-        if (e == hipSuccess) e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, 0, 0, b->shmem, b->stream);
-        if (e == hipSuccess) e = hrlbk_finalize(b->d_descs, n_cases, 0, b->stream);
+    if (any) {
+        st = batch_build_parts(b.get(), 1);
+        if (st != HRLB_OK) return st;
+        const hrlb_batch_part& P = *b->parts[0];
+        HIP_TRY(hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, stage_grid(P.ntiles), -1, 0, b->qy_max, b->stream));
+        HIP_TRY(hrlbk_cell(b->fp32, P.d_descs, P.d_cells, P.ncellblocks, 0, 0, b->shmem, b->stream));
+        HIP_TRY(hrlbk_finalize(P.d_descs, (int)P.idx.size(), 0, b->stream));
     }
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        delete b;
-        return fail(HRLB_E_DEVICE, "batch upload: %s", hipGetErrorString(e));
-    }
+    // two parts on two streams by default: one part's per-cell kernel overlaps the other's stage
+    // kernel (measured faster on MI355X for large batches)
+    st = batch_build_parts(b.get(), n_cases >= 2 ? 2 : 1);
+    if (st != HRLB_OK) return st;
     for (int i = 0; i < n_cases; ++i) cases[i]->needs_analyze = false;
-    *out = b;
+    *out = b.release();
     return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_batch_set_streams(hrlb_batch* b, int n_streams)
+{
+    if (!b || n_streams < 1 || n_streams > kMaxBatchParts)
+        return fail(HRLB_E_INVALID, "NULL batch or n_streams outside [1, %d]", kMaxBatchParts);
+    return batch_build_parts(b, n_streams);
 }
 
 extern "C" hrlb_status hrlb_batch_step(hrlb_batch* b, long n_steps, int check)
 {
     if (!b) return fail(HRLB_E_INVALID, "batch is NULL");
     if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
-    hrlb_status st = enqueue_steps(b->run, n_steps, check != 0);
+    hrlb_status st = batch_fork(b);
+    for (auto& P : b->parts)
+        if (st == HRLB_OK) st = enqueue_steps(P->run, n_steps, check != 0);
+    if (st == HRLB_OK) st = batch_join(b);
     if (st == HRLB_OK)
         for (hrlb_case* c : b->cases) c->steps_done += n_steps;
     return st;
@@ -946,8 +1040,11 @@ extern "C" hrlb_status hrlb_case_set_graph_steps(hrlb_case* c, int steps_per_gra
 extern "C" hrlb_status hrlb_batch_set_graph_steps(hrlb_batch* b, int steps_per_graph)
 {
     if (!b || steps_per_graph < 0) return fail(HRLB_E_INVALID, "NULL batch or negative steps");
-    b->run.drop_graphs();
-    b->run.graph_steps = steps_per_graph;
+    b->graph_steps = steps_per_graph;
+    for (auto& P : b->parts) {
+        P->run.drop_graphs();
+        P->run.graph_steps = steps_per_graph;
+    }
     return HRLB_OK;
 }
 
@@ -955,34 +1052,41 @@ extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* s
 {
     if (!b || n_steps < 1) return fail(HRLB_E_INVALID, "NULL batch or n_steps < 1");
     const long nl = n_steps * 3;
-    std::vector<hipEvent_t> ev(4 * nl, nullptr);
+    const size_t np = b->parts.size();
+    std::vector<hipEvent_t> ev(4 * nl * np, nullptr);
     hrlb_status st = HRLB_OK;
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
             st = fail(HRLB_E_DEVICE, "hipEventCreate failed");
             break;
         }
-    const int grid = stage_grid(b->ntiles);
-    for (long k = 0; k < nl && st == HRLB_OK; ++k) {
-        const int stage = (int)(k % 3);
-        hipError_t e = hipEventRecord(ev[4 * k], b->stream);
-        if (e == hipSuccess)
-            e = hrlbk_stage(b->fp32, b->d_descs, b->d_tiles, b->ntiles, grid, stage, 0, b->qy_max, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 1], b->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 2], b->stream);
-        if (e == hipSuccess)
-            e = hrlbk_cell(b->fp32, b->d_descs, b->d_cells, b->ncellblocks, stage == 0 ? 1 : stage == 1 ? 2 : 0,
-                           stage == 2 ? FLAG_STEP_DONE : 0, b->shmem, b->stream);
-        if (e == hipSuccess) e = hipEventRecord(ev[4 * k + 3], b->stream);
-        if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profiled launch: %s", hipGetErrorString(e));
+    if (st == HRLB_OK) st = batch_fork(b);
+    // the launch sequence of hrlb_batch_step, with an event pair around every launch on its stream
+    for (size_t q = 0; q < np && st == HRLB_OK; ++q) {
+        const hrlb_batch_part& P = *b->parts[q];
+        const int grid = stage_grid(P.ntiles);
+        for (long k = 0; k < nl && st == HRLB_OK; ++k) {
+            hipEvent_t* e4 = &ev[4 * (q * nl + k)];
+            const int stage = (int)(k % 3);
+            hipError_t e = hipEventRecord(e4[0], P.stream);
+            if (e == hipSuccess) e = hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, grid, stage, 0, b->qy_max, P.stream);
+            if (e == hipSuccess) e = hipEventRecord(e4[1], P.stream);
+            if (e == hipSuccess) e = hipEventRecord(e4[2], P.stream);
+            if (e == hipSuccess)
+                e = hrlbk_cell(b->fp32, P.d_descs, P.d_cells, P.ncellblocks, stage == 0 ? 1 : stage == 1 ? 2 : 0,
+                               stage == 2 ? FLAG_STEP_DONE : 0, b->shmem, P.stream);
+            if (e == hipSuccess) e = hipEventRecord(e4[3], P.stream);
+            if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profiled launch: %s", hipGetErrorString(e));
+        }
     }
+    if (st == HRLB_OK) st = batch_join(b);
     double ts = 0, tc = 0;
     if (st == HRLB_OK) {
         hipError_t e = hipStreamSynchronize(b->stream);
-        for (long k = 0; k < nl && e == hipSuccess; ++k) {
+        for (size_t i = 0; i < nl * np && e == hipSuccess; ++i) {
             float a = 0, c = 0;
-            e = hipEventElapsedTime(&a, ev[4 * k], ev[4 * k + 1]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[4 * k + 2], ev[4 * k + 3]);
+            e = hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[4 * i + 2], ev[4 * i + 3]);
             ts += a;
             tc += c;
         }
@@ -992,7 +1096,7 @@ extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* s
         if (e) (void)hipEventDestroy(e);
     if (st != HRLB_OK) return st;
     for (hrlb_case* c : b->cases) c->steps_done += n_steps;
-    if (stage_kernel_ms) *stage_kernel_ms = ts / nl;
-    if (cell_kernel_ms) *cell_kernel_ms = tc / nl;
+    if (stage_kernel_ms) *stage_kernel_ms = ts / (double)(nl * np);
+    if (cell_kernel_ms) *cell_kernel_ms = tc / (double)(nl * np);
     return HRLB_OK;
 }

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -113,17 +114,41 @@ struct hrlb_case {
     hrlb::Launcher run;
 };
 
+// cases of a batch advanced on one stream by shared launches
+struct hrlb_batch_part {
+    std::vector<int> idx;  // indices into hrlb_batch::cases, ascending
+    hrlb::InstDesc* d_descs = nullptr;
+    hrlb::TileRef* d_tiles = nullptr;
+    hrlb::CellRef* d_cells = nullptr;
+    int ntiles = 0, ncellblocks = 0;
+    hipStream_t stream = nullptr;  // part 0: the batch's stream; others: owned by the library
+    bool own_stream = false;
+    hipEvent_t done = nullptr;     // join event of parts 1..
+    hrlb::Launcher run;
+    ~hrlb_batch_part()
+    {
+        run.drop_graphs();
+        if (done) (void)hipEventDestroy(done);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
 struct hrlb_batch {
     std::vector<hrlb_case*> cases;
-    hrlb::InstDesc* d_descs;
-    hrlb::TileRef* d_tiles;
-    hrlb::CellRef* d_cells;
-    int ntiles, ncellblocks;
-    int fp32;
-    size_t shmem;
-    int qy_max;
-    hipStream_t stream;
-    hrlb::Launcher run;
+    int fp32 = 0;
+    size_t shmem = 0;
+    int qy_max = 0;
+    hipStream_t stream = nullptr;  // the cases' stream: every call is ordered on it
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int graph_steps = 0;
+    std::vector<std::unique_ptr<hrlb_batch_part>> parts;
+    hipEvent_t fork = nullptr;
+    ~hrlb_batch()
+    {
+        parts.clear();
+        if (fork) (void)hipEventDestroy(fork);
+    }
 };
 
 namespace hrlb {

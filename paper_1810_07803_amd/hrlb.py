@@ -28,7 +28,8 @@ EXPORTED = (
     "hrlb_step", "hrlb_run_to_steady", "hrlb_moments", "hrlb_get_state", "hrlb_set_state",
     "hrlb_case_info", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
     "hrlb_batch_workspace_bytes", "hrlb_batch_create", "hrlb_batch_step", "hrlb_batch_poll",
-    "hrlb_batch_free", "hrlb_batch_profile", "hrlb_case_set_graph_steps", "hrlb_batch_set_graph_steps",
+    "hrlb_batch_free", "hrlb_batch_profile", "hrlb_batch_set_streams", "hrlb_case_set_graph_steps",
+    "hrlb_batch_set_graph_steps",
     "hrlb_tune_workspace_bytes", "hrlb_tune_plan",
     "hrlb_server_create", "hrlb_server_clock", "hrlb_server_submit", "hrlb_server_pump", "hrlb_server_request",
     "hrlb_server_free",
@@ -116,6 +117,7 @@ def load() -> C.CDLL:
                 "hrlb_tune_workspace_bytes": [vp, C.POINTER(CaseParams), C.POINTER(C.c_size_t)],
                 "hrlb_tune_plan": [vp, C.POINTER(CaseParams), vp, C.c_size_t, vp, C.c_int, ip, ip, dp],
                 "hrlb_batch_set_graph_steps": [vp, C.c_int],
+                "hrlb_batch_set_streams": [vp, C.c_int],
                 "hrlb_server_create": [C.POINTER(ServerConfig), vp, C.c_size_t, vp, C.POINTER(vp)],
                 "hrlb_server_submit": [vp, C.POINTER(SolveRequest), C.POINTER(C.c_long)],
                 "hrlb_server_pump": [vp, C.POINTER(ServerStats)],
@@ -308,6 +310,10 @@ class Batch:
     def set_graph_steps(self, steps: int):
         """Steps per captured HIP graph (0 disables graphs)."""
         _check(load().hrlb_batch_set_graph_steps(self.handle, steps))
+
+    def set_streams(self, n: int):
+        """Advance the batch as n parts of about equal work, each on its own stream (1..4)."""
+        _check(load().hrlb_batch_set_streams(self.handle, n))
 
     def profile(self, n_steps: int):
         """Mean duration (ms) of one stage-kernel launch and one per-cell-kernel launch."""

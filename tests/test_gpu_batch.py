@@ -44,6 +44,28 @@ def test_batch_equals_alone_bitwise(precision, rounding):
         np.testing.assert_array_equal(a.get_state(), m.get_state())
 
 
+@pytest.mark.parametrize("precision,rounding", [(0, 0), (1, 1)])
+def test_batch_split_over_streams_is_bitwise_the_same(precision, rounding):
+    from paper_1810_07803_amd import hrlb
+
+    say(f"[batch] 1..4 streams, precision={precision}")
+    ref = None
+    for n in (1, 2, 3, 4):
+        cs = _cases(precision, rounding)
+        b = hrlb.Batch(cs)
+        b.set_streams(n)
+        b.step(12, check=True)
+        res, pxy = b.poll()
+        states = [c.get_state() for c in cs]
+        if ref is None:
+            ref = (states, res, pxy)
+            continue
+        for a, m in zip(ref[0], states):
+            np.testing.assert_array_equal(a, m)
+        np.testing.assert_array_equal(ref[1], res)
+        np.testing.assert_array_equal(ref[2], pxy)
+
+
 def test_batch_poll_reports_residual_and_pxy():
     from paper_1810_07803_amd import hrlb
 
