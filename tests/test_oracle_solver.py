@@ -106,3 +106,85 @@ def test_steady_state_does_not_depend_on_time_step():
         dphi, dchi, _ = p.rhs(phi, chi)
         assert np.max(np.abs(dphi)) < 1e-10 * np.max(np.abs(phi)) / p.dt
     np.testing.assert_allclose(out[0], out[1], rtol=0, atol=2e-11)
+
+
+def test_one_step_near_a_fixed_point_is_the_ssp_rk3_polynomial():
+    # At a fixed point f* (R(f*) = 0) every stage of the third-order TVD Runge-Kutta scheme sits at f*,
+    # so the step map linearises to I + dt J + (dt J)^2/2 + (dt J)^3/6 with J = DR(f*) (Sec. III
+    # names the scheme; Shu & Osher 1988).  The rest state with walls at rest is an exact fixed point;
+    # J v is formed by central differences of the oracle's right-hand side, independently of its step.
+    p = OracleProblem(3, 3, 8, stretch_A=0.5, delta=1.0, uw=0.0, omega=0.7)
+    phi0, chi0 = p.init_state()
+    f0 = np.concatenate([phi0.ravel(), chi0.ravel()])
+    n = phi0.size
+
+    def R(f):
+        dp, dc, _ = p.rhs(f[:n].reshape(phi0.shape), f[n:].reshape(chi0.shape))
+        return np.concatenate([dp.ravel(), dc.ravel()])
+
+    def step(f):
+        a, b = f[:n].reshape(phi0.shape).copy(), f[n:].reshape(chi0.shape).copy()
+        p.step(a, b, 1)
+        return np.concatenate([a.ravel(), b.ravel()])
+
+    assert np.max(np.abs(R(f0))) < 1e-15
+    rng = np.random.default_rng(3)
+    d = f0 * rng.uniform(-1.0, 1.0, size=f0.shape)
+    # small enough that WENO's nonlinear weights stay at their linear values (the smoothness
+    # indicators scale with the square of the perturbation against eps = 1e-6), large enough for
+    # round-off
+    eps = 2e-7
+
+    def Jv(v):
+        s = eps / max(np.max(np.abs(v / f0)), 1e-300)
+        return (R(f0 + s * v) - R(f0 - s * v)) / (2 * s)
+
+    z1 = p.dt * Jv(d)
+    z2 = p.dt * Jv(z1)
+    z3 = p.dt * Jv(z2)
+    lhs = (step(f0 + eps * d) - step(f0 - eps * d)) / (2 * eps)
+    rk3 = d + z1 + z2 / 2 + z3 / 6
+    scale = np.max(np.abs(d))
+    assert np.max(np.abs(z2)) > 1e-3 * scale and np.max(np.abs(z3)) > 1e-4 * scale  # terms are visible
+    assert np.max(np.abs(lhs - rk3)) < 1e-7 * scale
+    # a second-order scheme or a mis-weighted third stage would be far off
+    assert np.max(np.abs(lhs - (d + z1 + z2 / 2))) > 1e3 * np.max(np.abs(lhs - rk3))
+
+
+def test_time_marched_steady_state_is_the_zero_of_the_operator():
+    # Brute force on a tiny case: Newton's method on R(f) = 0 with a finite-difference Jacobian and
+    # the total mass fixed (the steady state is unique only up to mass) reaches the same state as
+    # time marching to a residual of 1e-13.
+    p = OracleProblem(4, 4, 8, stretch_A=0.5, delta=1.0, uw=0.2, omega=0.7)
+    phi, chi = p.init_state()
+    n = phi.size
+    m0 = p.mass(phi)
+    taken, res = p.step(phi, chi, 200000, 100, 1e-13)
+    assert res < 1e-13, (taken, res)
+    f_march = np.concatenate([phi.ravel(), chi.ravel()])
+
+    def R(f):
+        dp, dc, _ = p.rhs(f[:n].reshape(phi.shape), f[n:].reshape(chi.shape))
+        return np.concatenate([dp.ravel(), dc.ravel()])
+
+    wmass = np.zeros(2 * n)
+    wmass[:n] = np.tile(p.J * p.deta, p.nv)  # mass = sum_s J_s deta sum_v phi_v,s
+    a, b = p.init_state()
+    f = np.concatenate([a.ravel(), b.ravel()])
+    for _ in range(12):
+        r = R(f)
+        h = 1e-7 * max(np.max(np.abs(f)), 1e-12)
+        Jm = np.empty((2 * n, 2 * n))
+        for k in range(2 * n):
+            e = np.zeros(2 * n)
+            e[k] = h
+            Jm[:, k] = (R(f + e) - R(f - e)) / (2 * h)
+        # least squares on the operator plus the mass constraint
+        A = np.vstack([Jm, wmass[None, :]])
+        rhs = -np.concatenate([r, [wmass @ f - m0]])
+        delta_f = np.linalg.lstsq(A, rhs, rcond=None)[0]
+        f = f + delta_f
+        if np.max(np.abs(delta_f)) < 1e-14 * np.max(np.abs(f)):
+            break
+    assert np.max(np.abs(R(f))) < 1e-11 * np.max(np.abs(f))
+    assert np.max(np.abs(f - f_march)) < 1e-9 * np.max(np.abs(f_march))
