@@ -137,6 +137,16 @@ hrlb_status hrlb_run_to_steady(hrlb_case *c, double tol, long max_steps, int che
  * Any pointer may be NULL. */
 hrlb_status hrlb_moments(hrlb_case *c, double *fields, double *x, double *Pi, double *wall_shear);
 
+/* Time averages of the fields over completed steps (post-processing of a steady state whose FP32
+ * stochastic rounding keeps it fluctuating around the fixed point).  start: clears the running sums
+ * and adds the fields of every step completed from then on (asynchronous, on the case's stream;
+ * works alone and inside batches); stop: no further steps are added.  read: synchronous; fields
+ * [10][n_cells] as hrlb_moments, Pi from the averaged P_xy, *steps the number of steps averaged;
+ * HRLB_E_INVALID if no step was averaged.  Any output pointer may be NULL. */
+hrlb_status hrlb_average_start(hrlb_case *c);
+hrlb_status hrlb_average_stop(hrlb_case *c);
+hrlb_status hrlb_average_read(hrlb_case *c, double *fields, double *Pi, long *steps);
+
 /* Synchronous copies of the populations to/from host [2][Nv][n_cells] doubles (phi, chi).
  * set_state rounds to the storage precision and recomputes the moments; it is how a caller
  * resumes from a checkpoint or starts from a given state. */

@@ -228,6 +228,8 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     off = align256(off + es * (size_t)(kNSc + 2 * qx + qy) * nx);
     L.fields = off;
     off = align256(off + sizeof(double) * kNFields * nx);
+    L.avg = off;
+    off = align256(off + sizeof(double) * kNFields * nx);
     L.mom = off;
     off = align256(off + sizeof(double) * (size_t)L.ngroups * kNMom * nx);
     L.res = off;
@@ -470,6 +472,7 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     for (int k = 0; k < 3; ++k) D.f[k] = ws + L.f[k];
     D.cell = ws + L.cell;
     D.fields = (double*)(ws + L.fields);
+    D.avg = (double*)(ws + L.avg);
     D.mom_part = (double*)(ws + L.mom);
     D.res_part = (double*)(ws + L.res);
     D.dyn = (double*)(ws + L.dyn);
@@ -733,6 +736,46 @@ extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, dou
     if (wall_shear) {
         wall_shear[0] = dy[DY_SHEAR_L];
         wall_shear[1] = dy[DY_SHEAR_R];
+    }
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_average_start(hrlb_case* c)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    HIP_TRY(hrlbk_average(c->d_desc, 1, c->p.n_cells, c->stream));
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_average_stop(hrlb_case* c)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    HIP_TRY(hrlbk_average(c->d_desc, 0, c->p.n_cells, c->stream));
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_average_read(hrlb_case* c, double* fields, double* Pi, long* steps)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    const int nx = c->p.n_cells;
+    std::vector<double> a((size_t)kNFields * nx);
+    double dy[kNDyn];
+    HIP_TRY(hipMemcpyAsync(a.data(), c->desc.avg, sizeof(double) * a.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double m = dy[DY_AVG_STEPS];
+    if (steps) *steps = (long)m;
+    if (!(m > 0.0)) return fail(HRLB_E_INVALID, "no step has been averaged");
+    for (double& v : a) v /= m;
+    if (fields) std::copy(a.begin(), a.end(), fields);
+    if (Pi) {
+        double num = 0, den = 0;
+        for (int s = 0; s < nx; ++s) {
+            num += c->jdeta[s] * a[(size_t)F_PXY * nx + s];
+            den += c->jdeta[s];
+        }
+        const double vref = std::sqrt(c->p.T_w), pref = c->p.T_w;
+        *Pi = c->p.u_w != 0.0 ? -(num / den) * vref / (pref * c->p.u_w * std::sqrt(2.0)) : 0.0;
     }
     return HRLB_OK;
 }

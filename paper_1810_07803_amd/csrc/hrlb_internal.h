@@ -48,6 +48,8 @@ enum : int {
     DY_PXY_MEAN,  // J-weighted channel mean of P_xy at the last check
     DY_MASS,      // sum_s J_s deta n_s at the last check
     DY_FLAGS,     // nonzero if a non-finite value was met
+    DY_AVG_ON,    // nonzero: every completed step adds the fields to the running sums
+    DY_AVG_STEPS, // steps summed since the last start
     kNDyn = 16
 };
 
@@ -79,6 +81,7 @@ struct InstDesc {
     void* f[3];          // state buffers, each [2][nv][nx] in the storage precision
     void* cell;          // [kNSc + 2 qx + qy][nx] storage precision
     double* fields;      // [kNFields][nx]
+    double* avg;         // [kNFields][nx] running sums of the fields over completed steps
     double* mom_part;    // [ngroups][kNMom][nx]
     double* res_part;    // [nctiles * ngroups][2]
     double* dyn;         // [kNDyn]

@@ -849,7 +849,10 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
             const double nwl = -fl / D.den_l;
             D.dyn[DY_NWL] = nwl;
             D.dyn[DY_SHEAR_L] = ml + nwl * D.mom_l;
-            if (flags & FLAG_STEP_DONE) D.dyn[DY_STEP] += 1.0;
+            if (flags & FLAG_STEP_DONE) {
+                D.dyn[DY_STEP] += 1.0;
+                if (D.dyn[DY_AVG_ON] != 0.0) D.dyn[DY_AVG_STEPS] += 1.0;
+            }
         }
     }
     if (cr.cell0 + kCellThreads / LN >= nx) {
@@ -906,6 +909,20 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
         cell[SC_QX * nx + s] = (T)qx;
         cell[SC_QY * nx + s] = (T)qy;
         cell[SC_IJD * nx + s] = (T)D.inv_jdeta[s];
+        if ((flags & FLAG_STEP_DONE) && D.dyn[DY_AVG_ON] != 0.0) {
+            // running sums of the fields at the end of every step (time averages, hrlb_average_*)
+            double* A = D.avg;
+            A[F_N * nx + s] += n;
+            A[F_UX * nx + s] += ux;
+            A[F_UY * nx + s] += uy;
+            A[F_T * nx + s] += Tm;
+            A[F_PXX * nx + s] += pxx;
+            A[F_PXY * nx + s] += pxy;
+            A[F_PYY * nx + s] += pyy;
+            A[F_TZZ * nx + s] += tzz;
+            A[F_QX * nx + s] += qx;
+            A[F_QY * nx + s] += qy;
+        }
     }
 
     // g_x (eq. gx) and g_y (eq. gy) with the loops over the expansion order unrolled for the case's
@@ -965,6 +982,20 @@ __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restric
         D.dyn[DY_MASS] = red[0][3];
         const double chk = red[0][0] + red[0][1] + red[0][2] + red[0][3];
         if (!(chk == chk) || chk - chk != 0.0) D.dyn[DY_FLAGS] = 1.0;
+    }
+}
+
+// ---- time averages of the fields: start (clear the sums and the count, switch on) or stop ------
+__global__ __launch_bounds__(256) void average_kernel(const InstDesc* __restrict__ descs, int start)
+{
+    const InstDesc& D = descs[0];
+    if (start) {
+        const int n = kNFields * D.nx;
+        for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) D.avg[k] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        D.dyn[DY_AVG_ON] = start ? 1.0 : 0.0;
+        if (start) D.dyn[DY_AVG_STEPS] = 0.0;
     }
 }
 
@@ -1035,6 +1066,14 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_finalize(const
 {
     if (ninst <= 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, descs, with_res);
+    return hipGetLastError();
+}
+
+extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_average(const InstDesc* desc, int start, int nx,
+                                                                            hipStream_t st)
+{
+    const int grid = start ? (kNFields * nx + 255) / 256 : 1;
+    hipLaunchKernelGGL(average_kernel, dim3(grid), dim3(256), 0, st, desc, start);
     return hipGetLastError();
 }
 

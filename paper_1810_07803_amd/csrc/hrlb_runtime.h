@@ -18,6 +18,7 @@ extern "C" hipError_t hrlbk_cell(int fp32, const hrlb::InstDesc* descs, const hr
                                  int flags, size_t shmem, hipStream_t st);
 extern "C" hipError_t hrlbk_finalize(const hrlb::InstDesc* descs, int ninst, int with_res, hipStream_t st);
 extern "C" hipError_t hrlbk_init(int fp32, const hrlb::InstDesc* descs, int inst, size_t units, hipStream_t st);
+extern "C" hipError_t hrlbk_average(const hrlb::InstDesc* desc, int start, int nx, hipStream_t st);
 
 namespace hrlb {
 
@@ -72,7 +73,7 @@ hrlb_status steady_update(SteadyTrack& t, const double* dy, long n, double dt, d
 
 // byte offsets of the regions of a case workspace
 struct Layout {
-    size_t desc, dyn, tables, f[3], cell, fields, mom, res, tiles, cells, total;
+    size_t desc, dyn, tables, f[3], cell, fields, avg, mom, res, tiles, cells, total;
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
     int ngroups, nctiles, vpt, ncellblocks, cell_lanes;

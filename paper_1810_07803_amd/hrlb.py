@@ -32,7 +32,7 @@ EXPORTED = (
     "hrlb_batch_set_graph_steps",
     "hrlb_tune_workspace_bytes", "hrlb_tune_plan",
     "hrlb_server_create", "hrlb_server_clock", "hrlb_server_submit", "hrlb_server_pump", "hrlb_server_request",
-    "hrlb_server_free",
+    "hrlb_server_free", "hrlb_average_start", "hrlb_average_stop", "hrlb_average_read",
 )
 HRLB_REQ_WAITING, HRLB_REQ_ACTIVE, HRLB_REQ_DONE, HRLB_REQ_FAILED = 0, 1, 2, 3
 
@@ -118,6 +118,9 @@ def load() -> C.CDLL:
                 "hrlb_tune_plan": [vp, C.POINTER(CaseParams), vp, C.c_size_t, vp, C.c_int, ip, ip, dp],
                 "hrlb_batch_set_graph_steps": [vp, C.c_int],
                 "hrlb_batch_set_streams": [vp, C.c_int],
+                "hrlb_average_start": [vp],
+                "hrlb_average_stop": [vp],
+                "hrlb_average_read": [vp, dp, dp, C.POINTER(C.c_long)],
                 "hrlb_server_create": [C.POINTER(ServerConfig), vp, C.c_size_t, vp, C.POINTER(vp)],
                 "hrlb_server_submit": [vp, C.POINTER(SolveRequest), C.POINTER(C.c_long)],
                 "hrlb_server_pump": [vp, C.POINTER(ServerStats)],
@@ -261,6 +264,20 @@ class Case:
     def set_graph_steps(self, steps: int):
         """Steps per captured HIP graph (0 disables graphs)."""
         _check(load().hrlb_case_set_graph_steps(self.handle, steps))
+
+    def average_start(self):
+        """Start time-averaging the fields over the steps completed from now on."""
+        _check(load().hrlb_average_start(self.handle))
+
+    def average_stop(self):
+        _check(load().hrlb_average_stop(self.handle))
+
+    def average_read(self):
+        """(fields [10][n_cells], Pi, steps) averaged since average_start."""
+        f = np.zeros((10, self.ncell))
+        pi, n = C.c_double(), C.c_long()
+        _check(load().hrlb_average_read(self.handle, _dptr(f), C.byref(pi), C.byref(n)))
+        return f, pi.value, n.value
 
     def steps_done(self) -> int:
         sd = C.c_long()
