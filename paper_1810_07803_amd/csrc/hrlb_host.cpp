@@ -173,7 +173,6 @@ int choose_vpt(int qx, int qy, int requested)
 }
 
 // persistent grid: at most 4096 blocks, a multiple of 8 so that block b stays on XCD b % 8
-int stage_grid(int ntiles) { return std::max(8, std::min(ntiles, 4096) / 8 * 8); }
 
 // lanes per cell of the per-cell kernel: about a quarter of the x nodes of one half-line
 int auto_cell_lanes(int qx)
@@ -239,6 +238,8 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     off = align256(off + sizeof(TileRef) * (size_t)L.ntile_list);
     L.cells = off;
     off = align256(off + sizeof(CellRef) * L.ncellblocks);
+    L.ctr = off;
+    off = align256(off + sizeof(unsigned) * (kXcds + 1));
     L.total = off;
     return L;
 }
@@ -268,12 +269,11 @@ void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<doub
 
 hrlb_status enqueue_eager(const Launcher& L, long n_steps, bool check_last, hipStream_t st)
 {
-    const int grid = stage_grid(L.ntiles);
     for (long s = 0; s < n_steps; ++s) {
         const bool chk = check_last && s + 1 == n_steps;
         for (int stage = 0; stage < 3; ++stage) {
             const int fl = (stage == 2 && chk) ? FLAG_RESID : 0;
-            HIP_TRY(hrlbk_stage(L.fp32, L.descs, L.tiles, L.ntiles, grid, stage, fl, L.qy_max, st));
+            HIP_TRY(hrlbk_stage(L.fp32, L.descs, L.tiles, L.ntiles, L.ctr, stage, fl, L.qy_max, st));
             HIP_TRY(hrlbk_cell(L.fp32, L.descs, L.cells, L.ncellblocks, stage == 0 ? 1 : stage == 1 ? 2 : 0,
                                stage == 2 ? FLAG_STEP_DONE : 0, L.shmem, st));
         }
@@ -317,7 +317,7 @@ hrlb_status graph_for(Launcher& L, bool check, hipGraphExec_t* out)
 hrlb_status analyze_case(hrlb_case* c)
 {
     const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
-    HIP_TRY(hrlbk_stage(fp32, c->d_desc, c->d_tiles, c->ntiles, stage_grid(c->ntiles), -1, 0, c->q->qy, c->stream));
+    HIP_TRY(hrlbk_stage(fp32, c->d_desc, c->d_tiles, c->ntiles, c->d_ctr, -1, 0, c->q->qy, c->stream));
     HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, 0, c->shmem, c->stream));
     HIP_TRY(hrlbk_finalize(c->d_desc, 1, 0, c->stream));
     c->needs_analyze = false;
@@ -493,6 +493,7 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.g0 = tb + L.t_g0;
     c->d_desc = (InstDesc*)(ws + L.desc);
     c->d_tiles = (TileRef*)(ws + L.tiles);
+    c->d_ctr = (unsigned*)(ws + L.ctr);
     c->d_cells = (CellRef*)(ws + L.cells);
 
     std::vector<TileRef> tiles = case_tiles(L.nctiles, L.ngroups);
@@ -505,6 +506,7 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     c->run.descs = c->d_desc;
     c->run.ninst = 1;
     c->run.tiles = c->d_tiles;
+    c->run.ctr = c->d_ctr;
     c->run.ntiles = c->ntiles;
     c->run.cells = c->d_cells;
     c->run.ncellblocks = L.ncellblocks;
@@ -524,6 +526,8 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     cp(L.tables, tab.data(), sizeof(double) * tab.size());
     cp(L.tiles, tiles.data(), sizeof(TileRef) * tiles.size());
     cp(L.cells, cells.data(), sizeof(CellRef) * cells.size());
+    const std::vector<unsigned> zeros(kXcds + 1, 0u);
+    cp(L.ctr, zeros.data(), sizeof(unsigned) * zeros.size());
     if (e == hipSuccess) e = hrlbk_init(p->precision == HRLB_FP32_STORE_FP64_MOM, c->d_desc, 0, (size_t)nv * nx, c->stream);
     // the host staging vectors above must outlive the enqueued copies: wait on every path
     const hipError_t es = hipStreamSynchronize(c->stream);
@@ -855,7 +859,7 @@ std::vector<TileRef> part_tiles(hrlb_case* const* cases, const std::vector<int>&
 }
 
 struct PartLayout {
-    size_t descs, tiles, cells;
+    size_t descs, tiles, cells, ctr;
     int ntiles, ncellblocks;
 };
 
@@ -875,6 +879,8 @@ size_t parts_layout(hrlb_case* const* cases, const std::vector<std::vector<int>>
         off = align256(off + sizeof(TileRef) * P.ntiles);
         P.cells = off;
         off = align256(off + sizeof(CellRef) * P.ncellblocks);
+        P.ctr = off;
+        off = align256(off + sizeof(unsigned) * (kXcds + 1));
         if (L) L->push_back(P);
     }
     return off;
@@ -917,6 +923,7 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
         P.d_descs = (InstDesc*)(b->ws + L[k].descs);
         P.d_tiles = (TileRef*)(b->ws + L[k].tiles);
         P.d_cells = (CellRef*)(b->ws + L[k].cells);
+        P.d_ctr = (unsigned*)(b->ws + L[k].ctr);
         P.ntiles = L[k].ntiles;
         P.ncellblocks = L[k].ncellblocks;
         if (k == 0) {
@@ -946,10 +953,13 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
                                b->stream));
         HIP_TRY(hipMemcpyAsync(P.d_cells, cells.data(), sizeof(CellRef) * cells.size(), hipMemcpyHostToDevice,
                                b->stream));
+        static const unsigned zeros[kXcds + 1] = {};
+        HIP_TRY(hipMemcpyAsync(P.d_ctr, zeros, sizeof zeros, hipMemcpyHostToDevice, b->stream));
         P.run.fp32 = b->fp32;
         P.run.descs = P.d_descs;
         P.run.ninst = ni;
         P.run.tiles = P.d_tiles;
+        P.run.ctr = P.d_ctr;
         P.run.ntiles = P.ntiles;
         P.run.cells = P.d_cells;
         P.run.ncellblocks = P.ncellblocks;
@@ -1020,7 +1030,7 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
         st = batch_build_parts(b.get(), 1);
         if (st != HRLB_OK) return st;
         const hrlb_batch_part& P = *b->parts[0];
-        HIP_TRY(hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, stage_grid(P.ntiles), -1, 0, b->qy_max, b->stream));
+        HIP_TRY(hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, P.d_ctr, -1, 0, b->qy_max, b->stream));
         HIP_TRY(hrlbk_cell(b->fp32, P.d_descs, P.d_cells, P.ncellblocks, 0, 0, b->shmem, b->stream));
         HIP_TRY(hrlbk_finalize(P.d_descs, (int)P.idx.size(), 0, b->stream));
     }
@@ -1107,12 +1117,11 @@ extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* s
     // the launch sequence of hrlb_batch_step, with an event pair around every launch on its stream
     for (size_t q = 0; q < np && st == HRLB_OK; ++q) {
         const hrlb_batch_part& P = *b->parts[q];
-        const int grid = stage_grid(P.ntiles);
         for (long k = 0; k < nl && st == HRLB_OK; ++k) {
             hipEvent_t* e4 = &ev[4 * (q * nl + k)];
             const int stage = (int)(k % 3);
             hipError_t e = hipEventRecord(e4[0], P.stream);
-            if (e == hipSuccess) e = hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, grid, stage, 0, b->qy_max, P.stream);
+            if (e == hipSuccess) e = hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, P.d_ctr, stage, 0, b->qy_max, P.stream);
             if (e == hipSuccess) e = hipEventRecord(e4[1], P.stream);
             if (e == hipSuccess) e = hipEventRecord(e4[2], P.stream);
             if (e == hipSuccess)

@@ -17,6 +17,10 @@
 // tables (moments, equilibria) are staged in LDS.
 #include "hrlb_internal.h"
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 
 namespace hrlb {
 
@@ -285,10 +289,15 @@ constexpr int kLdsSlot = kTileCells + kTPR;
 // MODE: kModeAnalyze (no update; partials of the current state f[0], used after set-up or a state
 // upload), kModeStep, kModeResid (a step whose stage 3 also forms the residual partials)
 enum : int { kModeAnalyze = 0, kModeStep = 1, kModeResid = 2 };
+// Work distribution: one queue per XCD.  Block b runs on XCD b % 8 (blocks are dispatched round
+// robin and the grid is a multiple of 8, sized to the blocks that fit on the chip at once); it takes
+// the next position x + 8 k of its XCD's part of the tile list from the counter ctr[x] until the
+// list is exhausted, so heavy and light tiles balance dynamically.  The last block to finish
+// (counter ctr[8]) clears the counters for the next launch.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restrict__ descs,
                                                          const TileRef* __restrict__ tiles, int ntiles,
-                                                         int stage)
+                                                         int stage, unsigned* __restrict__ ctr)
 {
     constexpr bool ANALYZE = MODE == kModeAnalyze;
     // dynamic LDS: [union of (cell tables of the tile) and (moment reduction)] + boundary faces
@@ -307,7 +316,14 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
     constexpr bool want_res = MODE == kModeResid;
     constexpr uint32_t es = sizeof(T);
 
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    __shared__ int s_next;
+    const int xcd = blockIdx.x % kXcds;
+    for (;;) {
+        __syncthreads();  // every thread has read the previous s_next
+        if (tid == 0) s_next = xcd + kXcds * (int)atomicAdd(&ctr[xcd], 1u);
+        __syncthreads();
+        const int t = s_next;
+        if (t >= ntiles) break;
         const TileRef tr = tiles[t];
         if (tr.inst < 0) continue;  // padding of the XCD-aware tile order (uniform per block)
         const InstDesc& D = descs[tr.inst];
@@ -628,6 +644,11 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
             }
             __syncthreads();
         }
+    }
+    if (tid == 0) {
+        // no block touches the counters after its own increment of ctr[kXcds]: the last one resets
+        if (atomicAdd(&ctr[kXcds], 1u) == gridDim.x - 1)
+            for (int x = 0; x <= kXcds; ++x) ctr[x] = 0u;
     }
 }
 
@@ -1028,27 +1049,54 @@ extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_stage_lds(int fp32
     return cells > moms ? cells : moms;
 }
 
-extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_stage(int fp32, const InstDesc* descs, const TileRef* tiles, int ntiles, int grid,
-                                  int stage, int flags, int qy_max, hipStream_t st)
+namespace {
+// blocks of one stage-kernel variant that fit on the device at once, as a multiple of the XCD count
+template <typename T, int MODE>
+int resident_grid(size_t lds)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find({dev, lds});
+    if (it != cache.end()) return it->second;
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)stage_kernel<T, MODE>, kThreads, lds) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -1;
+    const int g = std::max(kXcds, (std::max(1, per_cu) * ncu) / kXcds * kXcds);
+    cache.emplace(std::make_pair(dev, lds), g);
+    return g;
+}
+
+template <typename T, int MODE>
+hipError_t launch_stage(const InstDesc* descs, const TileRef* tiles, int ntiles, int stage, unsigned* ctr, size_t lds,
+                        hipStream_t st)
+{
+    int grid = resident_grid<T, MODE>(lds);
+    if (grid < 0) return hipErrorInvalidValue;
+    grid = std::min(grid, std::max(kXcds, (ntiles + kXcds - 1) / kXcds * kXcds));  // a tile list is 8k long
+    hipLaunchKernelGGL((stage_kernel<T, MODE>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage, ctr);
+    return hipGetLastError();
+}
+}  // namespace
+
+// ctr: kXcds + 1 zeroed counters owned by the caller's launch list (the kernel leaves them zeroed)
+extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_stage(int fp32, const InstDesc* descs, const TileRef* tiles, int ntiles,
+                                  unsigned* ctr, int stage, int flags, int qy_max, hipStream_t st)
 {
     if (ntiles <= 0) return hipSuccess;
     const size_t lds = hrlbk_stage_lds(fp32, qy_max);
-    if (stage < 0) {
-        if (fp32)
-            hipLaunchKernelGGL((stage_kernel<float, kModeAnalyze>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0);
-        else
-            hipLaunchKernelGGL((stage_kernel<double, kModeAnalyze>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, 0);
-    } else if ((flags & FLAG_RESID) && stage == 2) {
-        if (fp32)
-            hipLaunchKernelGGL((stage_kernel<float, kModeResid>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
-        else
-            hipLaunchKernelGGL((stage_kernel<double, kModeResid>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
-    } else if (fp32) {
-        hipLaunchKernelGGL((stage_kernel<float, kModeStep>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
-    } else {
-        hipLaunchKernelGGL((stage_kernel<double, kModeStep>), dim3(grid), dim3(kThreads), lds, st, descs, tiles, ntiles, stage);
-    }
-    return hipGetLastError();
+    if (stage < 0)
+        return fp32 ? launch_stage<float, kModeAnalyze>(descs, tiles, ntiles, 0, ctr, lds, st)
+                    : launch_stage<double, kModeAnalyze>(descs, tiles, ntiles, 0, ctr, lds, st);
+    if ((flags & FLAG_RESID) && stage == 2)
+        return fp32 ? launch_stage<float, kModeResid>(descs, tiles, ntiles, stage, ctr, lds, st)
+                    : launch_stage<double, kModeResid>(descs, tiles, ntiles, stage, ctr, lds, st);
+    return fp32 ? launch_stage<float, kModeStep>(descs, tiles, ntiles, stage, ctr, lds, st)
+                : launch_stage<double, kModeStep>(descs, tiles, ntiles, stage, ctr, lds, st);
 }
 
 extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_cell(int fp32, const InstDesc* descs, const CellRef* cells, int ncells, int buf,

@@ -12,7 +12,7 @@
 #include "hrlb_internal.h"
 #include "hrlb_plan.h"
 
-extern "C" hipError_t hrlbk_stage(int fp32, const hrlb::InstDesc* descs, const hrlb::TileRef* tiles, int ntiles, int grid,
+extern "C" hipError_t hrlbk_stage(int fp32, const hrlb::InstDesc* descs, const hrlb::TileRef* tiles, int ntiles, unsigned* ctr,
                                   int stage, int flags, int qy_max, hipStream_t st);
 extern "C" hipError_t hrlbk_cell(int fp32, const hrlb::InstDesc* descs, const hrlb::CellRef* cells, int ncells, int buf,
                                  int flags, size_t shmem, hipStream_t st);
@@ -41,6 +41,7 @@ struct Launcher {
     int ninst = 0;
     const TileRef* tiles = nullptr;
     int ntiles = 0;
+    unsigned* ctr = nullptr;  // work-queue counters of the stage kernel (kXcds + 1, zeroed)
     const CellRef* cells = nullptr;
     int ncellblocks = 0;
     size_t shmem = 0;
@@ -73,7 +74,7 @@ hrlb_status steady_update(SteadyTrack& t, const double* dy, long n, double dt, d
 
 // byte offsets of the regions of a case workspace
 struct Layout {
-    size_t desc, dyn, tables, f[3], cell, fields, avg, mom, res, tiles, cells, total;
+    size_t desc, dyn, tables, f[3], cell, fields, avg, mom, res, tiles, cells, ctr, total;
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
     int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
@@ -104,6 +105,7 @@ struct hrlb_case {
     hrlb::InstDesc* d_desc;
     hrlb::TileRef* d_tiles;
     hrlb::CellRef* d_cells;
+    unsigned* d_ctr;
     int ntiles;
     int nv;
     size_t shmem;  // dynamic LDS of the per-cell kernel
@@ -121,6 +123,7 @@ struct hrlb_batch_part {
     hrlb::InstDesc* d_descs = nullptr;
     hrlb::TileRef* d_tiles = nullptr;
     hrlb::CellRef* d_cells = nullptr;
+    unsigned* d_ctr = nullptr;
     int ntiles = 0, ncellblocks = 0;
     hipStream_t stream = nullptr;  // part 0: the batch's stream; others: owned by the library
     bool own_stream = false;
