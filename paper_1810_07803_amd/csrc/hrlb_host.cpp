@@ -828,6 +828,7 @@ extern "C" hrlb_status hrlb_set_state(hrlb_case* c, const double* host_state)
 // batches
 namespace {
 constexpr int kMaxBatchParts = 4;
+constexpr double kSplitUnits = 3e7;  // cell-velocity units from which a batch is split over two streams
 
 // cases of a batch split into n parts of about equal work (units = velocities x cells): largest first
 // onto the least loaded part; each part keeps its cases in ascending order
@@ -1034,9 +1035,12 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
         HIP_TRY(hrlbk_cell(b->fp32, P.d_descs, P.d_cells, P.ncellblocks, 0, 0, b->shmem, b->stream));
         HIP_TRY(hrlbk_finalize(P.d_descs, (int)P.idx.size(), 0, b->stream));
     }
-    // two parts on two streams by default: one part's per-cell kernel overlaps the other's stage
-    // kernel (measured faster on MI355X for large batches)
-    st = batch_build_parts(b.get(), n_cases >= 2 ? 2 : 1);
+    // two parts on two streams for large batches: one part's per-cell kernel overlaps the other's
+    // stage kernel.  Measured on MI355X: +8% at 5.2e7 units, -16% at 1e7 units (the parts' launches
+    // then compete for the chip), hence one part below kSplitUnits
+    double units = 0.0;
+    for (int i = 0; i < n_cases; ++i) units += (double)cases[i]->nv * cases[i]->p.n_cells;
+    st = batch_build_parts(b.get(), (n_cases >= 2 && units >= kSplitUnits) ? 2 : 1);
     if (st != HRLB_OK) return st;
     for (int i = 0; i < n_cases; ++i) cases[i]->needs_analyze = false;
     *out = b.release();
