@@ -11,10 +11,10 @@
 //                 equilibria of eqs. (gx), (gy) that the next stage's collision uses; per instance:
 //                 the leaving wall fluxes and the wall densities of eq. (diffuse_nw).
 // Layout: populations [dist][v][cell] with cells contiguous.  A thread owns 4 consecutive cells of
-// one velocity and reconstructs their left faces; the right face comes from the next lane (the
-// neighbour's left face) or, at a tile edge, from a per-tile pre-pass, so every face is
-// reconstructed once per tile row.  A block covers 64 cells x 16 velocity rows; the tile's cell
-// tables (moments, equilibria) are staged in LDS.
+// one velocity and reconstructs their 5 faces from a 12-cell window (the right face is also the
+// next thread's left face; recomputing it costs less than fetching it: a per-tile pre-pass that
+// read the tile-edge cells once more cost 20% extra HBM reads).  A block covers 64 cells x 16
+// velocity rows; the tile's cell tables (moments, equilibria) are staged in LDS.
 #include "hrlb_internal.h"
 
 #include <map>
@@ -238,40 +238,41 @@ __device__ __forceinline__ double bld1<double>(__amdgpu_buffer_rsrc_t r, uint32_
 }
 
 // The window of a thread owning cells s0..s0+3 is w[m] = cell s0 - 4 + m, m = 0..11; its faces
-// f = 0..3 lie between cells s0+f-1 and s0+f (face 4, its right face, is the next lane's face 0).
+// f = 0..4 lie between cells s0+f-1 and s0+f (face 4 is also the next thread's face 0: both are
+// formed from the same five cells in the same order, so they agree bit for bit).
 // Differences: dl[m] = w[m+1] - w[m], d2[m] = dl[m] - dl[m-1].
 template <typename T>
 struct Win {
     T w[12];
-    T dl[9], d2[9], e[9];
-    // p_x > 0: faces 0..3 have upwind cell C = f + 3 and need dl[1..7], d2[2..7]
+    T dl[10], d2[10], e[10];
+    // p_x > 0: face f has upwind cell C = f + 3 and needs dl[1..8], d2[2..8]
     __device__ __forceinline__ void faces_pos(T (&F)[5])
     {
 #pragma unroll
-        for (int m = 1; m <= 7; ++m) dl[m] = w[m + 1] - w[m];
+        for (int m = 1; m <= 8; ++m) dl[m] = w[m + 1] - w[m];
 #pragma unroll
-        for (int m = 2; m <= 7; ++m) {
+        for (int m = 2; m <= 8; ++m) {
             d2[m] = dl[m] - dl[m - 1];
             e[m] = e_of(d2[m]);
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < 5; ++f) {
             const int C = f + 3;
             F[f] = weno_d(w[C], dl[C - 1], dl[C], d2[C - 1], d2[C + 1], e[C - 1], e[C], e[C + 1]);
         }
     }
-    // p_x < 0: faces 0..3 have upwind cell C = f + 4 (cells mirrored) and need dl[2..8], d2[3..8]
+    // p_x < 0: face f has upwind cell C = f + 4 (cells mirrored) and needs dl[2..9], d2[3..9]
     __device__ __forceinline__ void faces_neg(T (&F)[5])
     {
 #pragma unroll
-        for (int m = 2; m <= 8; ++m) dl[m] = w[m + 1] - w[m];
+        for (int m = 2; m <= 9; ++m) dl[m] = w[m + 1] - w[m];
 #pragma unroll
-        for (int m = 3; m <= 8; ++m) {
+        for (int m = 3; m <= 9; ++m) {
             d2[m] = dl[m] - dl[m - 1];
             e[m] = e_of(d2[m]);
         }
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
+        for (int f = 0; f < 5; ++f) {
             const int C = f + 4;
             F[f] = weno_d(w[C], -dl[C], -dl[C - 1], d2[C + 1], d2[C - 1], e[C + 1], e[C], e[C - 1]);
         }
@@ -304,7 +305,6 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
     extern __shared__ __align__(16) unsigned char smem[];
     double(*lds_mom)[kRows][kTileCells] = reinterpret_cast<double(*)[kRows][kTileCells]>(smem);
     T* lds_cell = reinterpret_cast<T*>(smem);
-    __shared__ T lds_bface[2][kRows][kTPR];
     __shared__ double lds_red[kThreads / 64][2];
 
     const int tid = threadIdx.x;
@@ -333,7 +333,6 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
         const int seg = tr.group * kRows + row;
         const bool row_on = seg < D.nseg;
         const bool active = row_on && s0 < nx;
-        const bool final_tile = c0 + kTileCells >= nx;
         const int hi = row_on ? seg / D.segs_per_line : 0;
         const int jc = seg - hi * D.segs_per_line;
         const double pxd = row_on ? D.px[hi] : 0.0;
@@ -365,21 +364,6 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                 bld4(rcell, ((uint32_t)src * nx + (uint32_t)(cell < nx ? cell : 0)) * es, v4);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) lds_cell[slot * kLdsSlot + c * kTPR + q4] = v4[c];
-            }
-            // the face on this tile's right edge for each (row, velocity): thread (row, strip) takes
-            // velocity k = strip of its row; the edge face F < nx - 3, so no ghost is involved
-            if (!final_tile && row_on && strip < vpt) {
-                const int v = vbase + strip;
-                const int F = c0 + kTileCells;
-#pragma unroll
-                for (int dist = 0; dist < 2; ++dist) {
-                    const uint32_t rowoff = ((uint32_t)dist * nv + v) * (uint32_t)nx;
-                    T a[6];
-#pragma unroll
-                    for (int m = 0; m < 6; ++m) a[m] = bld1<T>(rin, (rowoff + F - 3 + m) * es);
-                    lds_bface[dist][row][strip] =
-                        px > T(0) ? weno5_cells(a[0], a[1], a[2], a[3], a[4]) : weno5_cells(a[5], a[4], a[3], a[2], a[1]);
-                }
             }
             __syncthreads();
         }
@@ -492,14 +476,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                             Fc[0] = wall_face_left(X.w[4], X.w[5], X.w[6]);
                         }
                     }
-                    // right face: the next lane's left face, the pre-pass value at a tile edge, or
-                    // the wall face at the end of the channel
-                    Fp[4] = __shfl_down(Fp[0], 1, kTPR);
-                    Fc[4] = __shfl_down(Fc[0], 1, kTPR);
-                    if (strip == kTPR - 1 && !final_tile) {
-                        Fp[4] = lds_bface[0][row][k];
-                        Fc[4] = lds_bface[1][row][k];
-                    }
+                    // right face: from the thread's own window, or the wall face at the end of the channel
                     if (last) {
                         if (px > T(0)) {
                             Fp[4] = wall_face_right(P.w[5], P.w[6], P.w[7]);
