@@ -137,3 +137,32 @@ def test_checkpoint_resume_is_bitwise():
             # stochastic rounding keys on the step counter, which set_state does not reset
             pass
         np.testing.assert_array_equal(a.get_state(), b.get_state())
+
+
+@pytest.mark.parametrize("precision,rounding,tol", [(0, 0, FP64_TOL), (1, 1, FP32_TOL)])
+def test_full_size_parity_nx2048_q80x20_in_the_tuned_plan(precision, rounding, tol):
+    # the largest single case (3200 velocities, 2048 stretched cells, delta = 0.01) at its full size,
+    # in the plan the autotuner picks (the plan bench.py times), from a perturbed start
+    from oracle.oracle import OracleProblem
+    from paper_1810_07803_amd import hrlb
+
+    kw = dict(delta=0.01, uw=0.5, omega=0.7, stretch_A=0.9)
+    orc = OracleProblem(80, 20, 2048, **kw)
+    q = hrlb.Quadrature(80, 20, orc.Nx, orc.Ny)
+    params = hrlb.make_params(ncell=2048, precision=precision, rounding=rounding, dt=orc.dt, seed=9,
+                              delta=kw["delta"], uw=kw["uw"], omega=kw["omega"], stretch_A=kw["stretch_A"])
+    vpt, lanes, ms = hrlb.tune_plan(q, params, n_steps=3)
+    say(f"[parity] nx2048 q80x20 precision={precision}: tuned plan vpt={vpt} lanes={lanes} ({ms:.3f} ms/step)")
+    params = hrlb.make_params(ncell=2048, precision=precision, rounding=rounding, dt=orc.dt, seed=9,
+                              tile_vpt=vpt, cell_lanes=lanes, delta=kw["delta"], uw=kw["uw"],
+                              omega=kw["omega"], stretch_A=kw["stretch_A"])
+    case = hrlb.Case(q, params)
+    phi, chi = _perturbed_start(case, orc, 0.05, 21)
+    case.step(3)
+    orc.step(phi, chi, 3)
+    st = case.get_state()
+    e_state = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
+    e_fields = field_errs(case.moments()[0], orc.moments(phi, chi))
+    say(f"   state err {e_state:.3e}  field errs {np.array2string(e_fields, precision=2)}")
+    assert e_state < tol
+    assert np.all(e_fields < tol)
