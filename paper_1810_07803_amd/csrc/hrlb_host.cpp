@@ -722,9 +722,13 @@ extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, dou
     const int nx = c->p.n_cells;
     std::vector<double> f((size_t)kNFields * nx);
     double dy[kNDyn];
-    HIP_TRY(hipMemcpyAsync(f.data(), c->desc.fields, sizeof(double) * f.size(), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    {
+        Copies cp(c->stream);
+        cp.add(f.data(), c->desc.fields, sizeof(double) * f.size(), hipMemcpyDeviceToHost);
+        cp.add(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost);
+        const hrlb_status sc = cp.finish("moments");
+        if (sc != HRLB_OK) return sc;
+    }
     if (fields) std::copy(f.begin(), f.end(), fields);
     if (x) std::copy(c->x.begin(), c->x.end(), x);
     if (Pi) {
@@ -764,9 +768,13 @@ extern "C" hrlb_status hrlb_average_read(hrlb_case* c, double* fields, double* P
     const int nx = c->p.n_cells;
     std::vector<double> a((size_t)kNFields * nx);
     double dy[kNDyn];
-    HIP_TRY(hipMemcpyAsync(a.data(), c->desc.avg, sizeof(double) * a.size(), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    {
+        Copies cp(c->stream);
+        cp.add(a.data(), c->desc.avg, sizeof(double) * a.size(), hipMemcpyDeviceToHost);
+        cp.add(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost);
+        const hrlb_status sc = cp.finish("average read");
+        if (sc != HRLB_OK) return sc;
+    }
     const double m = dy[DY_AVG_STEPS];
     if (steps) *steps = (long)m;
     if (!(m > 0.0)) return fail(HRLB_E_INVALID, "no step has been averaged");
@@ -949,13 +957,14 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
         if ((int)tiles.size() != P.ntiles || (int)cells.size() != P.ncellblocks ||
             !tiles_valid(tiles, (size_t)P.ntiles, ni, nct.data(), ngr.data()))
             return fail(HRLB_E_INVALID, "internal: inconsistent batch tile list");
-        HIP_TRY(hipMemcpyAsync(P.d_descs, descs.data(), sizeof(InstDesc) * ni, hipMemcpyHostToDevice, b->stream));
-        HIP_TRY(hipMemcpyAsync(P.d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice,
-                               b->stream));
-        HIP_TRY(hipMemcpyAsync(P.d_cells, cells.data(), sizeof(CellRef) * cells.size(), hipMemcpyHostToDevice,
-                               b->stream));
         static const unsigned zeros[kXcds + 1] = {};
-        HIP_TRY(hipMemcpyAsync(P.d_ctr, zeros, sizeof zeros, hipMemcpyHostToDevice, b->stream));
+        Copies cp(b->stream);  // the staging vectors end with this iteration
+        cp.add(P.d_descs, descs.data(), sizeof(InstDesc) * ni, hipMemcpyHostToDevice);
+        cp.add(P.d_tiles, tiles.data(), sizeof(TileRef) * tiles.size(), hipMemcpyHostToDevice);
+        cp.add(P.d_cells, cells.data(), sizeof(CellRef) * cells.size(), hipMemcpyHostToDevice);
+        cp.add(P.d_ctr, zeros, sizeof zeros, hipMemcpyHostToDevice);
+        const hrlb_status sc = cp.finish("batch upload");
+        if (sc != HRLB_OK) return sc;
         P.run.fp32 = b->fp32;
         P.run.descs = P.d_descs;
         P.run.ninst = ni;
@@ -1072,10 +1081,13 @@ extern "C" hrlb_status hrlb_batch_poll(hrlb_batch* b, double* residual, double* 
     if (!b) return fail(HRLB_E_INVALID, "batch is NULL");
     const int n = (int)b->cases.size();
     std::vector<double> dy((size_t)kNDyn * n);
-    for (int i = 0; i < n; ++i)
-        HIP_TRY(hipMemcpyAsync(dy.data() + (size_t)i * kNDyn, b->cases[i]->desc.dyn, sizeof(double) * kNDyn,
-                               hipMemcpyDeviceToHost, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
+    {
+        Copies cp(b->stream);
+        for (int i = 0; i < n; ++i)
+            cp.add(dy.data() + (size_t)i * kNDyn, b->cases[i]->desc.dyn, sizeof(double) * kNDyn, hipMemcpyDeviceToHost);
+        const hrlb_status sc = cp.finish("batch poll");
+        if (sc != HRLB_OK) return sc;
+    }
     for (int i = 0; i < n; ++i) {
         const double* d = dy.data() + (size_t)i * kNDyn;
         if (residual) residual[i] = std::sqrt(d[DY_RES_NUM]) / (b->cases[i]->dt * std::sqrt(d[DY_RES_DEN]));

@@ -34,6 +34,25 @@ hrlb_status fail(hrlb_status st, const char* fmt, ...) __attribute__((format(pri
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Copies between device memory and host buffers that end with the caller's scope: every copy is
+// enqueued on one stream, and finish() always waits for that stream (also after a failed copy), so
+// that no copy outlives its host buffer.
+struct Copies {
+    explicit Copies(hipStream_t s) : st(s) {}
+    void add(void* dst, const void* src, size_t bytes, hipMemcpyKind kind)
+    {
+        if (e == hipSuccess) e = hipMemcpyAsync(dst, src, bytes, kind, st);
+    }
+    hrlb_status finish(const char* what)
+    {
+        const hipError_t es = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = es;
+        return e == hipSuccess ? HRLB_OK : fail(HRLB_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+    }
+    hipStream_t st;
+    hipError_t e = hipSuccess;
+};
+
 // launch parameters of a case or a batch, with its cached step-block graphs
 struct Launcher {
     int fp32 = 0;

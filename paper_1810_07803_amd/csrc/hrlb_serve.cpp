@@ -258,10 +258,13 @@ extern "C" hrlb_status hrlb_server_pump(hrlb_server* s, hrlb_server_stats* stats
         hrlb_status st = hrlb_batch_step(s->batch, n, 1);
         if (st != HRLB_OK) return st;
         std::vector<double> dy((size_t)kNDyn * s->active.size());
-        for (size_t i = 0; i < s->active.size(); ++i)
-            HIP_TRY(hipMemcpyAsync(dy.data() + i * kNDyn, s->active[i]->c->desc.dyn, sizeof(double) * kNDyn,
-                                   hipMemcpyDeviceToHost, s->stream));
-        HIP_TRY(hipStreamSynchronize(s->stream));
+        {
+            Copies cp(s->stream);
+            for (size_t i = 0; i < s->active.size(); ++i)
+                cp.add(dy.data() + i * kNDyn, s->active[i]->c->desc.dyn, sizeof(double) * kNDyn, hipMemcpyDeviceToHost);
+            st = cp.finish("server check");
+            if (st != HRLB_OK) return st;
+        }
         steps = n;
         std::vector<Request*> keep;
         for (size_t i = 0; i < s->active.size(); ++i) {
