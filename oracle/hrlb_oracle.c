@@ -22,6 +22,9 @@
  *   advection       WENO-5 of Jiang & Shu (J. Comput. Phys. 126, 1996) in finite-difference
  *                   form on the stretched grid of equation (stretch); Sec. III names the scheme.
  *   orc_step        third-order TVD Runge-Kutta of Shu & Osher (1988); Sec. III names it.
+ *   half channel    Sec. II: phi and chi are invariant under (x, p_x, p_y) -> (-x, -p_x, -p_y),
+ *                   so the right half [0, 1/2] with one diffuse wall at x = 1/2 is enough; the
+ *                   grid of equation (stretch) is then the paper's own (eta in [0, artanh A]).
  *
  * Readings where the paper is silent (each also listed in the design notes):
  *   - full channel [-1/2, 1/2]; left wall moves with -u_w, right wall with +u_w; both diffuse.
@@ -36,6 +39,9 @@
  *     makes the discrete wall mass flux exactly zero.
  *   - WENO-5 is applied to phi and chi independently, eps = 1e-6, upwinded by sign(p_x).
  *   - initial state: rest equilibrium n = 1, u = 0, T = T_w.
+ *   - half channel: the ghost cells -1, -2, -3 of velocity (p_x, p_y) hold the values of the
+ *     mirrored velocity (-p_x, -p_y) in cells 0, 1, 2 (the symmetry above at x_{-1-s} = -x_s);
+ *     the face at x = 0 is an ordinary WENO face for both signs of p_x.
  *
  * Velocity ordering (shared convention with the GPU library, no shared code):
  *   v = (h*Qx + i)*Qy + j,  p_x = +z_i for h = 0 and -z_i for h = 1,  p_y = z_j (ascending).
@@ -62,6 +68,7 @@ typedef struct {
     double delta, uw, Tw, Pr, omega;
     double dt;
     int collisionless;             /* 1: no collision term (delta -> 0 limit)                       */
+    int half;                      /* 1: right half [0, 1/2] with the point symmetry at x = 0        */
 } orc_problem;
 
 /* ----------------------------------------------------------------------------------------- */
@@ -78,11 +85,40 @@ static double vel_px(const orc_problem *P, int v)
 
 static double vel_py(const orc_problem *P, int v) { return P->zy[v % P->Qy]; }
 
-/* grid of equation (stretch), extended to the full channel */
+/* the velocity (-p_x, -p_y) of velocity v: the other sign of the same half-range node, and the
+ * full-range node of opposite sign (the nodes are symmetric about 0, ascending) */
+static int vel_mirror(const orc_problem *P, int v)
+{
+    int hi = v / P->Qy, j = v % P->Qy;
+    int h = hi / P->Qx, i = hi % P->Qx;
+    return ((1 - h) * P->Qx + i) * P->Qy + (P->Qy - 1 - j);
+}
+
+/* grid of equation (stretch): eta uniform on [0, artanh A] for the half channel (the paper's
+ * cells), on [-artanh A, artanh A] for the full channel */
 int orc_grid(const orc_problem *P, double *x, double *J, double *deta)
 {
     int N = P->ncell;
     if (N < 1) return -1;
+    if (P->half) {
+        if (P->stretch_A == 0.0) {
+            *deta = 0.5 / N;
+            for (int s = 0; s < N; ++s) {
+                x[s] = (s + 0.5) * (*deta);
+                J[s] = 1.0;
+            }
+        } else {
+            double A = P->stretch_A;
+            *deta = atanh(A) / N;
+            for (int s = 0; s < N; ++s) {
+                double eta = (s + 0.5) * (*deta);
+                double c = cosh(eta);
+                x[s] = tanh(eta) / (2.0 * A);
+                J[s] = 1.0 / (2.0 * A * c * c);
+            }
+        }
+        return 0;
+    }
     if (P->stretch_A == 0.0) {
         *deta = 1.0 / N;
         for (int s = 0; s < N; ++s) {
@@ -303,6 +339,12 @@ static void fill_left_extrap(double *e)
     for (int k = 1; k <= NG; ++k) e[NG - k] = extrap_quadratic(e[NG], e[NG + 1], e[NG + 2], -k);
 }
 
+/* half channel: cell -k holds the mirrored velocity's value in cell k-1 */
+static void fill_left_mirror(double *e, const double *fm)
+{
+    for (int k = 1; k <= NG; ++k) e[NG - k] = fm[k - 1];
+}
+
 static void fill_right_extrap(double *e, int N)
 {
     for (int k = 0; k < NG; ++k)
@@ -344,7 +386,7 @@ static void free_wall_tables(wall_tables *W)
 /* ----------------------------------------------------------------------------------------- */
 /* right-hand side L(f) of the reduced equations (boltz_red) for both distributions           */
 /* wall_info (optional, 4 doubles): n_wL, n_wR, and the y-momentum fluxes sum_v p_x p_y F at  */
-/* the left and right wall faces.                                                              */
+/* the left and right wall faces (half channel: n_wL = 0 and the flux through the face x = 0).  */
 /* ----------------------------------------------------------------------------------------- */
 int orc_rhs(const orc_problem *P, const double *phi, const double *chi, double *dphi, double *dchi,
             double *wall_info)
@@ -403,7 +445,7 @@ int orc_rhs(const orc_problem *P, const double *phi, const double *chi, double *
             denl += px * W.gxw[hi] * W.gyl[j];
         }
     }
-    double nwl = -numl / denl, nwr = -numr / denr;
+    double nwl = P->half ? 0.0 : -numl / denl, nwr = -numr / denr;
 
     double mflux_l = 0, mflux_r = 0;
     double *face_l = malloc(sizeof(double) * V), *face_r = malloc(sizeof(double) * V);
@@ -428,8 +470,9 @@ int orc_rhs(const orc_problem *P, const double *phi, const double *chi, double *
                 fill_left_extrap(e);
                 for (int k = 0; k < NG; ++k) e[NG + N + k] = wscale * wr;
             }
+            if (P->half) fill_left_mirror(e, (dist == 0 ? phi : chi) + (size_t)vel_mirror(P, v) * N);
             for (int fc = 0; fc <= N; ++fc) {
-                if (px > 0 && fc == 0)
+                if (px > 0 && fc == 0 && !P->half)
                     F[fc] = wscale * wl;
                 else if (px < 0 && fc == N)
                     F[fc] = wscale * wr;

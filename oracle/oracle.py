@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg o
 benchmark may import this module.  It shares no code with the GPU library.
 
 ``OracleProblem`` gathers one Couette case (paper, Secs. II-III): quadrature orders
-HHLB(Nx;Qx) x HLB(Ny;Qy), the grid of equation (stretch) extended to the full channel, the
+HHLB(Nx;Qx) x HLB(Ny;Qy), the grid of equation (stretch) over the full channel (or over the
+right half, with the point symmetry of Sec. II at x = 0, when ``half_channel`` is set), the
 rarefaction parameter delta of equation (delta), wall speed, wall temperature, Prandtl number
 and the viscosity index of equation (mu).  Every array is float64, velocities ordered
 v = (h*Qx + i)*Qy + j (h = 0: p_x = +z_i, h = 1: p_x = -z_i), cells contiguous.
@@ -49,7 +50,7 @@ class _Problem(C.Structure):
         ("zy", C.POINTER(C.c_double)), ("wy", C.POINTER(C.c_double)),
         ("ncell", C.c_int), ("stretch_A", C.c_double),
         ("delta", C.c_double), ("uw", C.c_double), ("Tw", C.c_double), ("Pr", C.c_double),
-        ("omega", C.c_double), ("dt", C.c_double), ("collisionless", C.c_int),
+        ("omega", C.c_double), ("dt", C.c_double), ("collisionless", C.c_int), ("half", C.c_int),
     ]
 
 
@@ -98,11 +99,12 @@ class OracleProblem:
     def __init__(self, Qx: int, Qy: int, ncell: int, *, Nx: int | None = None, Ny: int | None = None,
                  stretch_A: float = 0.0, delta: float = 1.0, uw: float = 0.05, Tw: float = 1.0,
                  Pr: float = 2.0 / 3.0, omega: float = 0.7, dt: float | None = None, cfl: float = 0.5,
-                 collisionless: bool = False):
+                 collisionless: bool = False, half_channel: bool = False):
         self.Qx, self.Qy = Qx, Qy
         self.Nx = min(Qx - 1, 10) if Nx is None else Nx
         self.Ny = Qy - 1 if Ny is None else Ny
         self.ncell, self.stretch_A = ncell, stretch_A
+        self.half = bool(half_channel)
         self.delta, self.uw, self.Tw, self.Pr, self.omega = delta, uw, Tw, Pr, omega
         self.collisionless = bool(collisionless or delta == 0.0)
         hr = quad.half_range_rule(Qx)
@@ -123,11 +125,20 @@ class OracleProblem:
         self.dt = float(dt)
         self._p = _Problem(Qx, self.Nx, Qy, self.Ny, _ptr(self.zx), _ptr(self.wx), _ptr(self.phi_hi),
                            _ptr(self.phi_lo), _ptr(self.zy), _ptr(self.wy), ncell, stretch_A,
-                           delta, uw, Tw, Pr, omega, self.dt, int(self.collisionless))
+                           delta, uw, Tw, Pr, omega, self.dt, int(self.collisionless), int(self.half))
 
     # -- grid and time step ------------------------------------------------------------------
     def _grid(self):
         N = self.ncell
+        if self.half:
+            # equation (stretch) as the paper states it: eta_s = (s - 1/2) artanh(A)/S, s = 1..S
+            if self.stretch_A == 0.0:
+                deta = 0.5 / N
+                return (np.arange(N) + 0.5) * deta, np.ones(N), deta
+            A = self.stretch_A
+            deta = math.atanh(A) / N
+            eta = (np.arange(N) + 0.5) * deta
+            return np.tanh(eta) / (2 * A), 1.0 / (2 * A * np.cosh(eta) ** 2), deta
         if self.stretch_A == 0.0:
             deta = 1.0 / N
             x = -0.5 + (np.arange(N) + 0.5) / N

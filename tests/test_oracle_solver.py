@@ -57,6 +57,47 @@ def test_point_symmetry_of_the_couette_problem():
         assert np.max(np.abs(f[k][::-1] - parity * f[k])) <= 1e-12 * scale, k
 
 
+@pytest.mark.parametrize("Qx,Qy,S,A", [(4, 4, 24, 0.9), (8, 7, 20, 0.0)])
+def test_half_channel_is_the_right_half_of_the_full_channel(Qx, Qy, S, A):
+    # Sec. II: the symmetry (x, p_x, p_y) -> (-x, -p_x, -p_y) lets the right half [0, 1/2] stand for
+    # the channel.  The half grid of equation (stretch) is the right half of the full grid with 2S
+    # cells, and the mirrored ghosts at x = 0 reproduce the full channel's left neighbours, so both
+    # runs agree to round-off (a wrong mirror index, grid or face at x = 0 breaks this at O(1e-3)).
+    kw = dict(stretch_A=A, delta=1.0, uw=0.3, omega=0.7)
+    h = OracleProblem(Qx, Qy, S, half_channel=True, **kw)
+    f = OracleProblem(Qx, Qy, 2 * S, **kw)
+    assert h.dt == f.dt
+    np.testing.assert_allclose(h.x, f.x[S:], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(h.J * h.deta, f.J[S:] * f.deta, rtol=1e-15)
+    ph, ch = h.init_state()
+    pf, cf = f.init_state()
+    h.step(ph, ch, 150)
+    f.step(pf, cf, 150)
+    assert np.max(np.abs(ph - pf[:, S:])) <= 1e-13 * np.max(np.abs(pf))
+    assert np.max(np.abs(ch - cf[:, S:])) <= 1e-13 * np.max(np.abs(cf))
+    mh, mf = h.moments(ph, ch), f.moments(pf, cf)
+    assert abs(h.Pi(mh) - f.Pi(mf)) <= 1e-13 * abs(f.Pi(mf))
+    assert abs(h.mass(ph) - 0.5 * f.mass(pf)) <= 1e-14
+    # the wall at x = 1/2 sees the same n_w and momentum flux
+    _, _, ih = h.rhs(ph, ch)
+    _, _, iff = f.rhs(pf, cf)
+    assert abs(ih[1] - iff[1]) <= 1e-13 and abs(ih[3] - iff[3]) <= 1e-13 * abs(iff[3])
+
+
+def test_half_channel_conserves_mass_and_keeps_the_rest_state():
+    # no mass crosses x = 0 (the mirrored fluxes cancel) nor the diffuse wall (diffuse_nw)
+    p = OracleProblem(4, 4, 16, stretch_A=0.9, delta=1.0, uw=0.3, half_channel=True)
+    phi, chi = p.init_state()
+    m0 = p.mass(phi)
+    p.step(phi, chi, 300)
+    assert abs(p.mass(phi) - m0) <= 1e-13 * m0
+    r = OracleProblem(4, 4, 16, stretch_A=0.9, delta=1.0, uw=0.0, half_channel=True)
+    phi, chi = r.init_state()
+    phi0 = phi.copy()
+    r.step(phi, chi, 20)
+    assert np.max(np.abs(phi - phi0)) <= 1e-14 * np.max(phi0)
+
+
 def test_free_molecular_limit_gives_pi_equal_one_over_sqrt_pi():
     # delta -> 0: each half-range stream carries its wall's Maxwellian, so n = 1,
     # T = 1 + u_w^2/3, P_xy = -u_w sqrt(2/pi) and equation (Pi) gives 1/sqrt(pi)
