@@ -16,7 +16,9 @@
  *                   (gx) is ill-conditioned in FP64 for expansion orders near 10.
  *   orc_gy          equation (gy), Sec. III: full-range truncation of g(p_y,u_y,T), FP64.
  *   orc_moments     moment definitions of Sec. II (n, u_i, T_ij, T_zz, q_x, q_y, T), two-pass.
- *   orc_tau         equation (tau) with the power-law viscosity of equation (mu).
+ *   orc_tau         equation (tau) with the power-law viscosity of equation (mu), or with the
+ *                   tabulated law of equations (mun) and (interp) when a table is given.
+ *   orc_prandtl     Pr: the constant, or the piecewise-constant Pr_n of equation (interp).
  *   collision       reduced Shakhov equations (boltz_red) with S_phi, S_chi of Sec. II.
  *   walls           diffuse reflection, equations (diffuse) and (diffuse_nw).
  *   advection       WENO-5 of Jiang & Shu (J. Comput. Phys. 126, 1996) in finite-difference
@@ -69,6 +71,8 @@ typedef struct {
     double dt;
     int collisionless;             /* 1: no collision term (delta -> 0 limit)                       */
     int half;                      /* 1: right half [0, 1/2] with the point symmetry at x = 0        */
+    int ntab;                      /* 0: mu ~ T^omega and constant Pr; >= 2: the tabulated law      */
+    const double *tabT, *tabMu, *tabPr; /* [ntab] T_n ascending, mu_n, Pr_n (= c_p mu_n / kappa_n)   */
 } orc_problem;
 
 /* ----------------------------------------------------------------------------------------- */
@@ -263,10 +267,41 @@ int orc_moments(const orc_problem *P, const double *phi, const double *chi, doub
     return 0;
 }
 
-/* equation (tau) with mu/mu(T_w) = (T/T_w)^omega, t_ref = L/v_ref = 1/sqrt(T_w) */
+/* index of the table interval that holds T: the largest k with T_k <= T, -1 below T_0
+ * (0-based: the paper's T_n is tabT[n-1]) */
+static int table_index(const orc_problem *P, double T)
+{
+    int k = -1;
+    for (int m = 0; m < P->ntab; ++m)
+        if (P->tabT[m] <= T) k = m;
+    return k;
+}
+
+/* equations (mun) and (interp): on the paper's interval [T_n, T_{n+1}] the power law through the two
+ * tabulated values, mu_n (T/T_n)^omega_n with omega_n = ln(mu_{n+1}/mu_n)/ln(T_{n+1}/T_n); below T_2
+ * the first interval's law, above T_N the last one's */
+static double mu_table(const orc_problem *P, double T)
+{
+    int k = table_index(P, T);
+    int s = k < 0 ? 0 : (k > P->ntab - 2 ? P->ntab - 2 : k);
+    double om = log(P->tabMu[s + 1] / P->tabMu[s]) / log(P->tabT[s + 1] / P->tabT[s]);
+    return P->tabMu[s] * pow(T / P->tabT[s], om);
+}
+
+/* equation (interp) for Pr: Pr_1 below T_2, Pr_n on T_n <= T < T_{n+1}, Pr_N from T_N on */
+double orc_prandtl(const orc_problem *P, double T)
+{
+    if (P->ntab < 2) return P->Pr;
+    int N = P->ntab;
+    if (T < P->tabT[1]) return P->tabPr[0];
+    if (T >= P->tabT[N - 1]) return P->tabPr[N - 1];
+    return P->tabPr[table_index(P, T)];
+}
+
+/* equation (tau) with mu(T)/mu(T_w) from equation (mu) or the table, t_ref = L/v_ref = 1/sqrt(T_w) */
 double orc_tau(const orc_problem *P, double n, double T)
 {
-    double mu_ratio = pow(T / P->Tw, P->omega);
+    double mu_ratio = P->ntab >= 2 ? mu_table(P, T) / mu_table(P, P->Tw) : pow(T / P->Tw, P->omega);
     return mu_ratio / (n * (T / P->Tw)) / (P->delta * sqrt(2.0)) / sqrt(P->Tw);
 }
 
@@ -282,7 +317,7 @@ int orc_collision_target(const orc_problem *P, const double *cell /* n,ux,uy,T,q
     if (!gx || !gy) { free(gx); free(gy); return -1; }
     orc_gx(P, ux, T, gx);
     orc_gy(P, uy, T, gy);
-    double pref = (1.0 - P->Pr) / (n * T * T);
+    double pref = (1.0 - orc_prandtl(P, T)) / (n * T * T);
     for (int v = 0; v < V; ++v) {
         int hi = v / Qy, j = v % Qy;
         double feq = n * gx[hi] * gy[j];

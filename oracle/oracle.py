@@ -51,6 +51,8 @@ class _Problem(C.Structure):
         ("ncell", C.c_int), ("stretch_A", C.c_double),
         ("delta", C.c_double), ("uw", C.c_double), ("Tw", C.c_double), ("Pr", C.c_double),
         ("omega", C.c_double), ("dt", C.c_double), ("collisionless", C.c_int), ("half", C.c_int),
+        ("ntab", C.c_int), ("tabT", C.POINTER(C.c_double)), ("tabMu", C.POINTER(C.c_double)),
+        ("tabPr", C.POINTER(C.c_double)),
     ]
 
 
@@ -67,6 +69,8 @@ def _load():
             lib.orc_moments.argtypes = [pp, dp, dp, dp]
             lib.orc_tau.argtypes = [pp, C.c_double, C.c_double]
             lib.orc_tau.restype = C.c_double
+            lib.orc_prandtl.argtypes = [pp, C.c_double]
+            lib.orc_prandtl.restype = C.c_double
             lib.orc_collision_target.argtypes = [pp, dp, dp, dp]
             lib.orc_weno5.argtypes = [C.c_double] * 5
             lib.orc_weno5.restype = C.c_double
@@ -99,12 +103,14 @@ class OracleProblem:
     def __init__(self, Qx: int, Qy: int, ncell: int, *, Nx: int | None = None, Ny: int | None = None,
                  stretch_A: float = 0.0, delta: float = 1.0, uw: float = 0.05, Tw: float = 1.0,
                  Pr: float = 2.0 / 3.0, omega: float = 0.7, dt: float | None = None, cfl: float = 0.5,
-                 collisionless: bool = False, half_channel: bool = False):
+                 collisionless: bool = False, half_channel: bool = False, visc_table=None):
         self.Qx, self.Qy = Qx, Qy
         self.Nx = min(Qx - 1, 10) if Nx is None else Nx
         self.Ny = Qy - 1 if Ny is None else Ny
         self.ncell, self.stretch_A = ncell, stretch_A
         self.half = bool(half_channel)
+        # equations (mun), (interp): rows (T_n, mu_n, Pr_n) with T_n ascending; replaces omega and Pr
+        self.table = None if visc_table is None else np.ascontiguousarray(np.asarray(visc_table, np.float64).T)
         self.delta, self.uw, self.Tw, self.Pr, self.omega = delta, uw, Tw, Pr, omega
         self.collisionless = bool(collisionless or delta == 0.0)
         hr = quad.half_range_rule(Qx)
@@ -119,13 +125,19 @@ class OracleProblem:
         self.px = np.repeat(px, Qy)
         self.py = np.tile(self.zy, 2 * Qx)
         self._keep = [self.zx, self.wx, self.zy, self.wy, self.phi_hi, self.phi_lo]
+        if self.table is not None:
+            assert self.table.shape[0] == 3 and self.table.shape[1] >= 2
+            self._tab = [np.ascontiguousarray(r) for r in self.table]
+            self._keep += self._tab
         self.x, self.J, self.deta = self._grid()
         if dt is None:
             dt = self.default_dt(cfl)
         self.dt = float(dt)
         self._p = _Problem(Qx, self.Nx, Qy, self.Ny, _ptr(self.zx), _ptr(self.wx), _ptr(self.phi_hi),
                            _ptr(self.phi_lo), _ptr(self.zy), _ptr(self.wy), ncell, stretch_A,
-                           delta, uw, Tw, Pr, omega, self.dt, int(self.collisionless), int(self.half))
+                           delta, uw, Tw, Pr, omega, self.dt, int(self.collisionless), int(self.half),
+                           0 if self.table is None else self.table.shape[1],
+                           *([None] * 3 if self.table is None else [_ptr(r) for r in self._tab]))
 
     # -- grid and time step ------------------------------------------------------------------
     def _grid(self):
@@ -175,6 +187,9 @@ class OracleProblem:
 
     def tau(self, n: float, T: float) -> float:
         return _load().orc_tau(C.byref(self._p), n, T)
+
+    def prandtl(self, T: float) -> float:
+        return _load().orc_prandtl(C.byref(self._p), T)
 
     def collision_target(self, n, ux, uy, T, qx, qy):
         cell = np.array([n, ux, uy, T, qx, qy], dtype=np.float64)

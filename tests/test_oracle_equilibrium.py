@@ -156,3 +156,84 @@ def test_tau_reproduces_delta_and_viscosity_law(delta, omega):
     for n, T in [(0.9, 1.2), (1.3, 0.8)]:
         mu = p.tau(n, T) * n * T
         assert mu / mu_w == pytest.approx(T ** omega, rel=1e-14)
+
+
+# ---- tabulated transport law, equations (mun) and (interp) -------------------------------------
+POWER_TABLE_T = [0.5, 0.8, 1.0, 1.3, 2.0]
+
+
+def _power_table(omega, Pr, c=3.7):
+    return [(T, c * T ** omega, Pr) for T in POWER_TABLE_T]
+
+
+def test_table_sampled_from_a_power_law_reproduces_it():
+    # every interval's omega_n of (mun) is the sampled exponent, inside and outside the table
+    omega, Pr = 0.7, 2.0 / 3.0
+    a = OracleProblem(4, 4, 16, delta=0.8, omega=omega, Pr=Pr, stretch_A=0.9, uw=0.3)
+    b = OracleProblem(4, 4, 16, delta=0.8, stretch_A=0.9, uw=0.3, visc_table=_power_table(omega, Pr))
+    for T in (0.3, 0.5, 0.66, 0.8, 0.97, 1.0, 1.2, 1.3, 1.9, 2.0, 3.1):
+        assert b.tau(1.1, T) == pytest.approx(a.tau(1.1, T), rel=1e-14)
+        assert b.prandtl(T) == Pr
+    pa, ca = a.init_state()
+    pb, cb = b.init_state()
+    a.step(pa, ca, 100)
+    b.step(pb, cb, 100)
+    assert np.max(np.abs(pa - pb)) <= 1e-13 * np.max(pa)
+
+
+def _random_table(seed, N=6):
+    rng = np.random.default_rng(seed)
+    T = np.sort(rng.uniform(0.4, 2.5, N))
+    mu = np.exp(rng.uniform(-0.5, 0.5, N)) * T ** 0.7
+    Pr = rng.uniform(0.6, 0.75, N)
+    return T, mu, Pr
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_table_law_passes_through_the_tabulated_values(seed):
+    # mu^(n)(T_n) = mu_n and mu^(n)(T_{n+1}) = mu_{n+1}: with T_w placed on node k, eq. (tau) gives
+    # tau n T / T_w = (mu(T)/mu_k) / (delta sqrt 2) / sqrt(T_w) at every node, from either side
+    T, mu, Pr = _random_table(seed)
+    k, delta = 2, 0.9
+    p = OracleProblem(4, 4, 8, delta=delta, Tw=T[k], visc_table=list(zip(T, mu, Pr)))
+
+    def ratio(Tq):
+        return p.tau(1.0, Tq) * (Tq / T[k]) * delta * math.sqrt(2.0) * math.sqrt(T[k])
+
+    for n in range(len(T)):
+        assert ratio(T[n]) == pytest.approx(mu[n] / mu[k], rel=1e-13)
+        for eps in (1e-12, -1e-12):  # continuity from both sides (|omega_n| stays below 1e3 here)
+            assert ratio(T[n] * (1 + eps)) == pytest.approx(mu[n] / mu[k], rel=1e-9)
+    # beyond the table the end intervals continue: (T/T_1)^omega_1 below, (T/T_N)^omega_{N-1} above
+    om1 = math.log(mu[1] / mu[0]) / math.log(T[1] / T[0])
+    omN = math.log(mu[-1] / mu[-2]) / math.log(T[-1] / T[-2])
+    assert ratio(0.5 * T[0]) == pytest.approx(mu[0] * 0.5 ** om1 / mu[k], rel=1e-13)
+    assert ratio(1.5 * T[-1]) == pytest.approx(mu[-1] * 1.5 ** omN / mu[k], rel=1e-13)
+
+
+def test_table_prandtl_is_piecewise_constant_as_in_interp():
+    # Pr_1 below T_2 (also below T_1), Pr_n on [T_n, T_{n+1}), Pr_N from T_N on
+    T, mu, Pr = _random_table(5)
+    p = OracleProblem(4, 4, 8, visc_table=list(zip(T, mu, Pr)))
+    N = len(T)
+    assert p.prandtl(0.5 * T[0]) == Pr[0]
+    assert p.prandtl(T[0]) == Pr[0]
+    assert p.prandtl(0.5 * (T[0] + T[1])) == Pr[0]
+    for n in range(1, N - 1):
+        assert p.prandtl(T[n]) == Pr[n]
+        assert p.prandtl(0.5 * (T[n] + T[n + 1])) == Pr[n]
+    assert p.prandtl(T[N - 1]) == Pr[N - 1]
+    assert p.prandtl(2.0 * T[N - 1]) == Pr[N - 1]
+
+
+def test_shakhov_target_uses_the_tabulated_prandtl_number():
+    # the heat flux of the collision target is (1 - Pr(T)) q with Pr(T) from the table's interval
+    T, mu, Pr = _random_table(7)
+    p = OracleProblem(8, 8, 8, Nx=7, Ny=7, visc_table=list(zip(T, mu, Pr)))
+    for Tc in (0.5 * (T[1] + T[2]), 0.5 * (T[3] + T[4])):
+        n, qx, qy = 1.05, 0.02, -0.01
+        tp, tc = p.collision_target(n, 0.01, -0.03, Tc, qx, qy)
+        m = p.moments(np.repeat(tp[:, None], 8, axis=1), np.repeat(tc[:, None], 8, axis=1))[:, 0]
+        pr = Pr[int(np.searchsorted(T, Tc, side="right")) - 1]
+        assert m[8] == pytest.approx((1 - pr) * qx, rel=1e-10)
+        assert m[9] == pytest.approx((1 - pr) * qy, rel=1e-10)
