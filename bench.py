@@ -31,6 +31,11 @@ WORKLOADS = {
     "couette_nx512_q16x8_fp32": dict(kind="single", name="couette_nx512_q16x8", precision=1, rounding=1),
     "couette_nx2048_q80x20_fp32": dict(kind="single", name="couette_nx2048_q80x20", precision=1, rounding=1),
     "couette_nx2048_q80x20_fp64": dict(kind="single", name="couette_nx2048_q80x20", precision=0, rounding=0),
+    # the same flows as their right halves (point symmetry of Sec. II): n_cells/2 cells per instance,
+    # one diffuse wall, half the updates per step
+    "couette_batch512_ragged_half_fp32": dict(kind="batch", precision=1, rounding=1, half=True),
+    "couette_nx512_q16x8_half_fp32": dict(kind="single", name="couette_nx512_q16x8", precision=1, rounding=1,
+                                          half=True),
     # serving: 64 solves drawn like the ragged batch with Nx up to 2048 (seed 1), Poisson arrivals at
     # 200 requests/s (seed 2), FP32 storage; each stops when its P_xy drift rate falls below 2e-6 per
     # unit time or after 100k steps
@@ -59,9 +64,11 @@ def _build(spec, insts, tune: bool, tile_vpt: int = 0, cell_lanes: int = 0):
         key = (d["Qx"], d["Qy"])
         if key not in quads:
             quads[key] = hrlb.Quadrature(d["Qx"], d["Qy"])
-        kw = dict(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
-                  Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
-                  precision=spec["precision"], rounding=spec["rounding"], seed=d.get("seed", 0))
+        half = bool(spec.get("half"))
+        kw = dict(delta=d["delta"], uw=d["uw"], ncell=d["ncell"] // 2 if half else d["ncell"],
+                  stretch_A=d["stretch_A"], Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
+                  precision=spec["precision"], rounding=spec["rounding"], seed=d.get("seed", 0),
+                  half_channel=int(half))
         if cell_lanes > 0:
             kw["cell_lanes"] = cell_lanes
         if tile_vpt > 0 and d["Qy"] % tile_vpt == 0:
@@ -73,15 +80,16 @@ def _build(spec, insts, tune: bool, tile_vpt: int = 0, cell_lanes: int = 0):
     return quads, cases, hrlb.Batch(cases), tuned
 
 
-def _cpu_baseline(insts, budget_s: float):
+def _cpu_baseline(insts, budget_s: float, half: bool = False):
     """The oracle as it stands, on a bounded sample of the same workload (host cores, OpenMP)."""
     from oracle.oracle import OracleProblem, num_threads
 
     sample = insts[: min(len(insts), 6)]
     probs = []
     for d in sample:
-        probs.append(OracleProblem(d["Qx"], d["Qy"], d["ncell"], stretch_A=d["stretch_A"], delta=d["delta"],
-                                   uw=d["uw"], omega=d["omega"]))
+        probs.append(OracleProblem(d["Qx"], d["Qy"], d["ncell"] // 2 if half else d["ncell"],
+                                   stretch_A=d["stretch_A"], delta=d["delta"], uw=d["uw"], omega=d["omega"],
+                                   half_channel=half))
     # one calibration step each, then as many steps as fit in the budget
     t0 = time.perf_counter()
     states = []
@@ -234,7 +242,7 @@ def main(argv=None):
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        cpu = _cpu_baseline(insts, args.cpu_seconds)
+        cpu = _cpu_baseline(insts, args.cpu_seconds, half=bool(spec.get("half")))
 
     out = {
         "metric": "cell·velocity updates/s",
@@ -251,6 +259,7 @@ def main(argv=None):
         "moments_dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "instances": len(cases), "units_per_step": units,
+                   "half_channel": bool(spec.get("half")),
                    "graph_steps": args.graph_steps, "streams": args.streams, "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
                    "parallelism": "single GPU, instances batched per launch"},
         "wall_s_timed": wall,

@@ -75,7 +75,8 @@ typedef struct {
     double T_w;       /* wall temperature (> 0); the units assume T_w = 1 but any value works  */
     double Pr;        /* Prandtl number of the Shakhov model, > 0                             */
     double omega;     /* viscosity index of eq. (mu): mu ~ T^omega                             */
-    int n_cells;      /* cells across the full channel: a multiple of 4, 8 <= n_cells <= 65536 */
+    int n_cells;      /* cells across the channel (its right half when half_channel is set):    */
+                      /* a multiple of 4, 8 <= n_cells <= 65536                                 */
     double stretch_A; /* grid stretching of eq. (stretch), 0 <= A < 1 (0 = uniform)           */
     int precision;    /* HRLB_FP64 or HRLB_FP32_STORE_FP64_MOM                                 */
     int rounding;     /* FP32 storage only: HRLB_ROUND_NEAREST or HRLB_ROUND_STOCHASTIC        */
@@ -88,6 +89,25 @@ typedef struct {
                       /* bitwise the same numbers alone and in any batch for a given tile_vpt. */
     int cell_lanes;   /* lanes per cell of the per-cell kernel: 1, 2, 4, 8 or 16; 0 = automatic */
                       /* (2).  Also part of the plan that fixes the summation order.            */
+    int half_channel; /* 0: full channel [-1/2, 1/2] with two diffuse walls.  1: the right half   */
+                      /* [0, 1/2] only, using the point symmetry of Sec. II (phi and chi are     */
+                      /* unchanged by x, p_x, p_y -> -x, -p_x, -p_y): the ghost cells left of    */
+                      /* x = 0 hold the mirrored velocities of the first cells, one diffuse wall */
+                      /* at x = 1/2, and the grid of eq. (stretch) on eta in [0, artanh A] as in */
+                      /* Sec. III.  Same flow as the full channel with 2 n_cells cells, half the */
+                      /* work per step.                                                          */
+    /* Transport law.  visc_table_n = 0: eq. (mu) with omega above and the constant Pr.
+     * visc_table_n in [2, 256]: the tabulated law of eqs. (mun) and (interp), Sec. II.  Rows
+     * (visc_T[k], visc_mu[k], visc_Pr[k]): temperatures in the units of T_w, strictly increasing and
+     * positive; viscosities in any unit (only ratios enter); Prandtl numbers Pr_k = c_p mu_k / kappa_k
+     * from the tabulated heat conductivity.  Between consecutive rows mu is the power law through
+     * both values; below the second row the first interval's law and above the last row the last
+     * interval's law are extended.  Pr is Pr_k on [T_k, T_{k+1}), the first value below the second
+     * row and the last value from the last row on.  eq. (tau) then uses mu(T)/mu(T_w) and the
+     * Shakhov factor Pr(T) per cell; omega and Pr are ignored.  The arrays are host memory, copied
+     * by hrlb_init_case (and by hrlb_server_submit); the caller keeps ownership. */
+    int visc_table_n;
+    const double *visc_T, *visc_mu, *visc_Pr;
 } hrlb_case_params;
 
 /* Device workspace size (bytes) needed by a case with these parameters. */
@@ -133,7 +153,8 @@ hrlb_status hrlb_run_to_steady(hrlb_case *c, double tol, long max_steps, int che
  *   fields [10][n_cells]: n, u_x, u_y, T, P_xx, P_xy, P_yy, T_zz, q_x, q_y (moment definitions
  *                         of Sec. II, accumulated in FP64 for both precisions),
  *   x [n_cells]: cell centres,  Pi: equation (Pi) with the J-weighted channel mean of P_xy,
- *   wall_shear [2]: y-momentum flux sum_v p_x p_y F through the left and right wall faces.
+ *   wall_shear [2]: y-momentum flux sum_v p_x p_y F through the left and right wall faces
+ *                   (half channel: the wall at x = 1/2 in both, its mirror image being the same).
  * Any pointer may be NULL. */
 hrlb_status hrlb_moments(hrlb_case *c, double *fields, double *x, double *Pi, double *wall_shear);
 

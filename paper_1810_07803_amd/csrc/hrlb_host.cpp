@@ -157,6 +157,20 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
         return fail(HRLB_E_INVALID, "tile_vpt=%d must be 0 or a divisor of Qy=%d up to %d", p->tile_vpt, q->qy, kMaxVpt);
     if (p->cell_lanes < 0 || p->cell_lanes > kMaxCellLanes || (p->cell_lanes & (p->cell_lanes - 1)))
         return fail(HRLB_E_INVALID, "cell_lanes=%d must be 0 or a power of two up to %d", p->cell_lanes, kMaxCellLanes);
+    if (p->half_channel != 0 && p->half_channel != 1) return fail(HRLB_E_INVALID, "half_channel must be 0 or 1");
+    if (p->visc_table_n != 0) {
+        const int nt = p->visc_table_n;
+        if (nt < 2 || nt > kMaxViscTable) return fail(HRLB_E_INVALID, "visc_table_n=%d outside [2, %d]", nt, kMaxViscTable);
+        if (!p->visc_T || !p->visc_mu || !p->visc_Pr) return fail(HRLB_E_INVALID, "NULL transport table");
+        for (int k = 0; k < nt; ++k) {
+            if (!(p->visc_T[k] > 0.0) || !std::isfinite(p->visc_T[k]) || (k > 0 && !(p->visc_T[k] > p->visc_T[k - 1])))
+                return fail(HRLB_E_INVALID, "visc_T must be positive, finite and strictly increasing (row %d)", k);
+            if (!(p->visc_mu[k] > 0.0) || !std::isfinite(p->visc_mu[k]))
+                return fail(HRLB_E_INVALID, "visc_mu[%d] must be positive and finite", k);
+            if (!(p->visc_Pr[k] > 0.0) || !std::isfinite(p->visc_Pr[k]))
+                return fail(HRLB_E_INVALID, "visc_Pr[%d] must be positive and finite", k);
+        }
+    }
     return HRLB_OK;
 }
 
@@ -217,6 +231,11 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     L.t_gwl = t; t += nv;
     L.t_gwr = t; t += nv;
     L.t_g0 = t; t += nv;
+    const int nt = p->visc_table_n;
+    L.t_vT = t; t += nt;
+    L.t_vMu = t; t += nt;
+    L.t_vOm = t; t += nt > 0 ? nt - 1 : 0;
+    L.t_vPr = t; t += nt;
     L.t_n = t;
     off = align256(off + sizeof(double) * t);
     for (int k = 0; k < 3; ++k) {
@@ -244,11 +263,30 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     return L;
 }
 
+// cell centres and J_s deta of eq. (stretch): eta uniform on [0, artanh A] for the half channel
+// (Sec. III), on [-artanh A, artanh A] for the full one; A = 0 is the uniform grid
 void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<double>& jdeta)
 {
     const int N = p->n_cells;
     x.resize(N);
     jdeta.resize(N);
+    if (p->half_channel) {
+        if (p->stretch_A == 0.0) {
+            for (int s = 0; s < N; ++s) {
+                x[s] = (s + 0.5) * (0.5 / N);
+                jdeta[s] = 0.5 / N;
+            }
+        } else {
+            const double A = p->stretch_A, de = std::atanh(A) / N;
+            for (int s = 0; s < N; ++s) {
+                const double eta = (s + 0.5) * de;
+                const double c = std::cosh(eta);
+                x[s] = std::tanh(eta) / (2.0 * A);
+                jdeta[s] = de / (2.0 * A * c * c);
+            }
+        }
+        return;
+    }
     if (p->stretch_A == 0.0) {
         for (int s = 0; s < N; ++s) {
             x[s] = -0.5 + (s + 0.5) / N;
@@ -396,6 +434,15 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
         tab[L.t_ijd + s] = 1.0 / c->jdeta[s];
         tab[L.t_jd + s] = c->jdeta[s];
     }
+    // tabulated transport law: rows and the exponent of each interval, eq. (mun)
+    const int nt = p->visc_table_n;
+    for (int k = 0; k < nt; ++k) {
+        tab[L.t_vT + k] = p->visc_T[k];
+        tab[L.t_vMu + k] = p->visc_mu[k];
+        tab[L.t_vPr + k] = p->visc_Pr[k];
+        if (k + 1 < nt)
+            tab[L.t_vOm + k] = std::log(p->visc_mu[k + 1] / p->visc_mu[k]) / std::log(p->visc_T[k + 1] / p->visc_T[k]);
+    }
     std::vector<double> gxw(2 * qx), gyl(qy), gyr(qy), gy0(qy);
     eval_gx(qx, q->nxo, q->wx.data(), q->hz.data(), q->auxZ.data(), q->auxW.data(), q->hZ.data(), 0.0, p->T_w,
             gxw.data());
@@ -455,6 +502,13 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.nyb = gy_rows(q->nyo);
     D.ktab_n = cell_lds(qx, qy, D.nxb, D.nyb, q->nyo).total;
     D.cell_lanes = L.cell_lanes;
+    D.half = p->half_channel;
+    D.ntab = nt;
+    if (nt > 0) {
+        double prw = 0.0;
+        visc_lookup(tab.data() + L.t_vT, tab.data() + L.t_vMu, tab.data() + L.t_vOm, tab.data() + L.t_vPr, nt, p->T_w,
+                    &D.mu_w, &prw);
+    }
     c->shmem = sizeof(double) * (size_t)D.ktab_n;
     c->run.shmem = c->shmem;
     D.dt = dt;
@@ -491,6 +545,10 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.gw_l = tb + L.t_gwl;
     D.gw_r = tb + L.t_gwr;
     D.g0 = tb + L.t_g0;
+    D.vT = tb + L.t_vT;
+    D.vMu = tb + L.t_vMu;
+    D.vOm = tb + L.t_vOm;
+    D.vPr = tb + L.t_vPr;
     c->d_desc = (InstDesc*)(ws + L.desc);
     c->d_tiles = (TileRef*)(ws + L.tiles);
     c->d_ctr = (unsigned*)(ws + L.ctr);
@@ -742,7 +800,7 @@ extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, dou
         *Pi = c->p.u_w != 0.0 ? -pxy * vref / (pref * c->p.u_w * std::sqrt(2.0)) : 0.0;
     }
     if (wall_shear) {
-        wall_shear[0] = dy[DY_SHEAR_L];
+        wall_shear[0] = c->p.half_channel ? dy[DY_SHEAR_R] : dy[DY_SHEAR_L];
         wall_shear[1] = dy[DY_SHEAR_R];
     }
     return HRLB_OK;

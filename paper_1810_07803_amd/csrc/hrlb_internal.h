@@ -30,6 +30,7 @@ constexpr int kMaxCellLanes = 16;             // lanes per cell of the per-cell 
 constexpr int kAux = 48;
 
 constexpr int kMaxQx = 128, kMaxNx = 16, kMaxQy = 64;
+constexpr int kMaxViscTable = 256;  // rows of a tabulated transport law
 constexpr int kNMom = 11;  // raw moment accumulators per cell
 
 // per-cell scalars stored in the storage precision, slot-major [slot][nx]
@@ -71,8 +72,11 @@ struct InstDesc {
     int cell_lanes;  // lanes per cell in the per-cell kernel (1, 2, 4, 8 or 16)
     int nxb;       // rows of the padded h tables: gx_rows(nxo)
     int nyb;       // rows of the padded He table: gy_rows(nyo), 0 = evaluated without the table padding
-    int pad1;
+    int half;      // 1: right half of the channel, mirrored ghosts at x = 0 (no left wall)
+    int ntab;      // 0: mu ~ T^omega, constant Pr; >= 2: rows of the tabulated transport law
+    int pad2;
     double dt, Tw, Pr, omega;
+    double mu_w;         // tabulated law: mu(T_w)
     double tau_pref;     // delta sqrt(2) sqrt(T_w): 1/tau = tau_pref n (T/T_w)^(1-omega)
     double den_l, den_r; // sum over entering directions of p_x g_x(0,T_w) g_y(-/+u_w,T_w)
     double mom_l, mom_r; // same sums weighted by p_y (incoming momentum flux per unit n_w)
@@ -99,6 +103,10 @@ struct InstDesc {
     const double* gw_l;  // [nv] g_x(0,T_w) g_y(-u_w,T_w)
     const double* gw_r;  // [nv] g_x(0,T_w) g_y(+u_w,T_w)
     const double* g0;    // [nv] initial populations (rest equilibrium, n = 1)
+    const double* vT;    // [ntab] tabulated law: T_k ascending
+    const double* vMu;   // [ntab] mu_k
+    const double* vOm;   // [ntab - 1] omega_k = ln(mu_{k+1}/mu_k) / ln(T_{k+1}/T_k)
+    const double* vPr;   // [ntab] Pr_k
 };
 
 // ---- padded table shapes of the per-cell kernel ---------------------------------------------
@@ -129,6 +137,26 @@ __host__ __device__ inline CellLds cell_lds(int qx, int qy, int nxb, int nyb, in
     o.he = o.hz + nxb * qx;
     o.total = o.he + (nyb > 0 ? nyb : nyo + 1) * qy;
     return o;
+}
+
+// ---- tabulated transport law (host and device) -------------------------------------------
+// eqs. (mun), (interp): k = the last row with T_k <= t (binary search, rows strictly increasing);
+// mu from the power law of interval clamp(k, 0, n-2), i.e. the first interval's law below T_1 and the
+// last one's above T_{n-1}; Pr = Pr_0 below T_1, Pr_k on [T_k, T_{k+1}), Pr_{n-1} from T_{n-1} on.
+__host__ __device__ inline void visc_lookup(const double* T, const double* mu, const double* om, const double* pr,
+                                            int n, double t, double* mu_out, double* pr_out)
+{
+    int lo = -1, hi = n;  // T[lo] <= t < T[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (T[mid] <= t)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int s = lo < 0 ? 0 : (lo > n - 2 ? n - 2 : lo);
+    *mu_out = mu[s] * pow(t / T[s], om[s]);
+    *pr_out = lo < 1 ? pr[0] : pr[lo];
 }
 
 // ---- equilibrium truncations (host and device) ------------------------------------------

@@ -379,8 +379,13 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
             const __amdgpu_buffer_rsrc_t rfn = make_rsrc(D.f[0], state_bytes);
             const __amdgpu_buffer_rsrc_t rout = make_rsrc(D.f[out_idx], state_bytes);
             const int sc = active ? s0 : 0;  // idle lanes read cells 0..3
-            const bool first = s0 == 0, last = s0 + kStrip == nx;
-            const uint32_t oL = (uint32_t)(active && !first ? s0 - 4 : sc) * es;
+            const bool last = s0 + kStrip == nx;
+            // the strip at cell 0: the left wall closure (full channel) or the mirrored ghosts (half channel)
+            const bool first = s0 == 0 && !D.half, mirror = s0 == 0 && D.half;
+            // rows of the mirrored velocities (-p_x, -p_y): the other sign of the half-range node, the
+            // full-range node of opposite sign (nodes symmetric about 0, ascending)
+            const int hmir = hi < qx ? hi + qx : hi - qx;
+            const uint32_t oL = (uint32_t)(active && s0 != 0 ? s0 - 4 : sc) * es;
             const uint32_t oC = (uint32_t)sc * es;
             const uint32_t oR = (uint32_t)(active && !last ? s0 + 4 : sc) * es;
             const uint32_t rowstep = (uint32_t)nx * es;
@@ -422,6 +427,18 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                     bld4(rin, chi_off + rowoff + oR, tmp);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) X.w[8 + c] = tmp[c];
+                }
+                if (!ANALYZE && mirror) {
+                    // point symmetry of Sec. II about x = 0: ghost cells -1..-4 of (p_x, p_y) hold
+                    // the values of (-p_x, -p_y) in cells 0..3
+                    const uint32_t moff = (uint32_t)(hmir * qy + (qy - 1 - j)) * rowstep;
+                    T tmp[4];
+                    bld4(rin, moff, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) P.w[3 - c] = tmp[c];
+                    bld4(rin, chi_off + moff, tmp);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) X.w[3 - c] = tmp[c];
                 }
                 T op[kStrip], oc[kStrip];
                 if (ANALYZE) {
@@ -841,16 +858,18 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     // walls: the block holding cell 0 does the left wall, the one holding cell nx-1 the right wall
     const T* fcur = (const T*)D.f[buf];
     if (cr.cell0 == 0) {
-        double fl, ml;
-        wall_sums<T>(D, fcur, false, fl, ml);
-        if (threadIdx.x == 0) {
-            const double nwl = -fl / D.den_l;
-            D.dyn[DY_NWL] = nwl;
-            D.dyn[DY_SHEAR_L] = ml + nwl * D.mom_l;
-            if (flags & FLAG_STEP_DONE) {
-                D.dyn[DY_STEP] += 1.0;
-                if (D.dyn[DY_AVG_ON] != 0.0) D.dyn[DY_AVG_STEPS] += 1.0;
+        if (!D.half) {  // the half channel has no wall at x = 0
+            double fl, ml;
+            wall_sums<T>(D, fcur, false, fl, ml);
+            if (threadIdx.x == 0) {
+                const double nwl = -fl / D.den_l;
+                D.dyn[DY_NWL] = nwl;
+                D.dyn[DY_SHEAR_L] = ml + nwl * D.mom_l;
             }
+        }
+        if (threadIdx.x == 0 && (flags & FLAG_STEP_DONE)) {
+            D.dyn[DY_STEP] += 1.0;
+            if (D.dyn[DY_AVG_ON] != 0.0) D.dyn[DY_AVG_STEPS] += 1.0;
         }
     }
     if (cr.cell0 + kCellThreads / LN >= nx) {
@@ -884,9 +903,18 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
 
     T* cell = (T*)D.cell;
     if (on && q == 0) {
-        // eq. (tau) with mu ~ T^omega; Shakhov prefactor (1 - Pr)/(n K_B^2 T^2)
-        const double invtau = D.collisionless ? 0.0 : D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
-        const double As = (1.0 - D.Pr) / (n * Tm * Tm);
+        // eq. (tau) with mu ~ T^omega (eq. mu) or the tabulated law; Shakhov prefactor (1 - Pr)/(n K_B^2 T^2)
+        double invtau, pr = D.Pr;
+        if (D.ntab > 0) {
+            // tabulated law, eqs. (mun) and (interp): 1/tau = tau_pref n (T/T_w) mu(T_w)/mu(T)
+            double mu;
+            visc_lookup(D.vT, D.vMu, D.vOm, D.vPr, D.ntab, Tm, &mu, &pr);
+            invtau = D.tau_pref * n * (Tm / D.Tw) * (D.mu_w / mu);
+        } else {
+            invtau = D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
+        }
+        if (D.collisionless) invtau = 0.0;
+        const double As = (1.0 - pr) / (n * Tm * Tm);
         double* F = D.fields;
         F[F_N * nx + s] = n;
         F[F_UX * nx + s] = ux;

@@ -95,7 +95,8 @@ hrlb_status steady_update(SteadyTrack& t, const double* dy, long n, double dt, d
 struct Layout {
     size_t desc, dyn, tables, f[3], cell, fields, avg, mom, res, tiles, cells, ctr, total;
     // table offsets in doubles relative to `tables`
-    size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_n;
+    size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_vT, t_vMu, t_vOm,
+        t_vPr, t_n;
     int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
     int ntile_list;  // records in the case's tile list (XCD-aware order, padded)
 };

@@ -36,6 +36,7 @@ struct Request {
     double t_arrival = -1.0, t_admit = -1.0, t_done = -1.0;
     double pi = 0.0, mass_drift = 0.0, sim_time = 0.0;
     std::vector<double> fields, x;
+    std::vector<double> vT, vMu, vPr;  // the request's transport table (its params point here)
 };
 
 using QuadKey = std::tuple<int, int, int, int>;
@@ -176,6 +177,15 @@ extern "C" hrlb_status hrlb_server_submit(hrlb_server* s, const hrlb_solve_reque
     auto rq = std::make_unique<Request>();
     rq->id = s->next_id++;
     rq->r = *r;
+    if (r->params.visc_table_n > 0) {  // validated above; the caller's arrays may go away after this call
+        const int nt = r->params.visc_table_n;
+        rq->vT.assign(r->params.visc_T, r->params.visc_T + nt);
+        rq->vMu.assign(r->params.visc_mu, r->params.visc_mu + nt);
+        rq->vPr.assign(r->params.visc_Pr, r->params.visc_Pr + nt);
+        rq->r.params.visc_T = rq->vT.data();
+        rq->r.params.visc_mu = rq->vMu.data();
+        rq->r.params.visc_Pr = rq->vPr.data();
+    }
     rq->q = it->second;
     rq->bytes = bytes;
     rq->t_arrival = r->arrival_s >= 0.0 ? r->arrival_s : s->now();
