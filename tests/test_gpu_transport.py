@@ -50,11 +50,11 @@ def _pair(Qx, Qy, nx, steps, *, precision=0, rounding=0, table, **kw):
     return e_state, e_fields, T
 
 
-@pytest.mark.parametrize("Qx,Qy,nx,steps,kw", [
-    (8, 7, 132, 20, dict(delta=0.5, uw=0.3, stretch_A=0.9)),
-    (4, 4, 64, 40, dict(delta=2.0, uw=0.45)),
+@pytest.mark.parametrize("Qx,Qy,nx,steps,kw,min_intervals", [
+    (8, 7, 132, 20, dict(delta=0.5, uw=0.3, stretch_A=0.9), 3),
+    (4, 4, 64, 40, dict(delta=2.0, uw=0.45), 2),
 ])
-def test_tabulated_law_fixed_step_parity_fp64(Qx, Qy, nx, steps, kw):
+def test_tabulated_law_fixed_step_parity_fp64(Qx, Qy, nx, steps, kw, min_intervals):
     table = _table(3)
     say(f"[table] Q{Qx}x{Qy} nx={nx} {steps} steps {kw}, {len(table)} rows")
     e_state, e_fields, T = _pair(Qx, Qy, nx, steps, table=table, **kw)
@@ -62,7 +62,7 @@ def test_tabulated_law_fixed_step_parity_fp64(Qx, Qy, nx, steps, kw):
     visited = np.unique(np.searchsorted(rows, T, side="right"))
     say(f"   state err {e_state:.3e} field err max {e_fields.max():.2e}; T in [{T.min():.4f}, {T.max():.4f}], "
         f"{len(visited)} intervals")
-    assert len(visited) >= 3
+    assert len(visited) >= min_intervals
     assert e_state < FP64_TOL and np.all(e_fields < FP64_TOL)
 
 
