@@ -24,6 +24,7 @@
  *   advection       WENO-5 of Jiang & Shu (J. Comput. Phys. 126, 1996) in finite-difference
  *                   form on the stretched grid of equation (stretch); Sec. III names the scheme.
  *   orc_step        third-order TVD Runge-Kutta of Shu & Osher (1988); Sec. III names it.
+ *                   Optional local time steps for steady states (not in the paper, see below).
  *   half channel    Sec. II: phi and chi are invariant under (x, p_x, p_y) -> (-x, -p_x, -p_y),
  *                   so the right half [0, 1/2] with one diffuse wall at x = 1/2 is enough; the
  *                   grid of equation (stretch) is then the paper's own (eta in [0, artanh A]).
@@ -41,6 +42,13 @@
  *     makes the discrete wall mass flux exactly zero.
  *   - WENO-5 is applied to phi and chi independently, eps = 1e-6, upwinded by sign(p_x).
  *   - initial state: rest equilibrium n = 1, u = 0, T = T_w.
+ *   - local time steps (lts_cap > 1, a steady-state accelerator that is not in the paper): cell s
+ *     advances with dt_s = dt * max(1, min(J_s / min J, lts_cap, tau_w / (2 dt))), tau_w the
+ *     relaxation time at n = 1, T = T_w (no last term when collisionless), so every cell runs at
+ *     the Courant number of the smallest one.  Fluxes then leave and enter neighbouring cells with
+ *     different weights, so the transient does not conserve mass: at every residual check the
+ *     populations are rescaled to the rest-state mass sum_s J_s deta (n_ref = 1).  The residual is
+ *     || (f_new - f_old) / dt_s || / || f_old ||.  The fixed point R(f) = 0 is the same.
  *   - half channel: the ghost cells -1, -2, -3 of velocity (p_x, p_y) hold the values of the
  *     mirrored velocity (-p_x, -p_y) in cells 0, 1, 2 (the symmetry above at x_{-1-s} = -x_s);
  *     the face at x = 0 is an ordinary WENO face for both signs of p_x.
@@ -73,6 +81,7 @@ typedef struct {
     int half;                      /* 1: right half [0, 1/2] with the point symmetry at x = 0        */
     int ntab;                      /* 0: mu ~ T^omega and constant Pr; >= 2: the tabulated law      */
     const double *tabT, *tabMu, *tabPr; /* [ntab] T_n ascending, mu_n, Pr_n (= c_p mu_n / kappa_n)   */
+    double lts_cap;                /* > 1: local time steps up to lts_cap * dt (steady states only)  */
 } orc_problem;
 
 /* ----------------------------------------------------------------------------------------- */
@@ -570,20 +579,41 @@ int orc_init_state(const orc_problem *P, double *phi, double *chi)
     return 0;
 }
 
-/* relative residual || f_new - f_old || / (dt || f_old ||), J-weighted L2 over cells,
- * velocities and both distributions */
-static double residual(const orc_problem *P, const double *J, const double *p0, const double *c0,
-                       const double *p1, const double *c1)
+/* relative residual || (f_new - f_old)/dt_s || / || f_old ||, J-weighted L2 over cells,
+ * velocities and both distributions (dt_s = dt without local time steps) */
+static double residual(const orc_problem *P, const double *J, const double *dts, const double *p0,
+                       const double *c0, const double *p1, const double *c1)
 {
     int N = P->ncell, V = nvel(P);
     double num = 0, den = 0;
     for (int v = 0; v < V; ++v)
         for (int s = 0; s < N; ++s) {
             size_t k = (size_t)v * N + s;
-            num += J[s] * ((p1[k] - p0[k]) * (p1[k] - p0[k]) + (c1[k] - c0[k]) * (c1[k] - c0[k]));
+            double d2 = (p1[k] - p0[k]) * (p1[k] - p0[k]) + (c1[k] - c0[k]) * (c1[k] - c0[k]);
+            num += J[s] * d2 / (dts[s] * dts[s]);
             den += J[s] * (p0[k] * p0[k] + c0[k] * c0[k]);
         }
-    return sqrt(num) / (P->dt * sqrt(den));
+    return sqrt(num) / sqrt(den);
+}
+
+/* per-cell time steps: dt everywhere, or the local steps of lts_cap (see the header) */
+static void cell_time_steps(const orc_problem *P, const double *J, double *dts)
+{
+    int N = P->ncell;
+    double jmin = J[0];
+    for (int s = 1; s < N; ++s) jmin = J[s] < jmin ? J[s] : jmin;
+    double rcoll = HUGE_VAL;
+    if (!P->collisionless) rcoll = 0.5 * orc_tau(P, 1.0, P->Tw) / P->dt;
+    for (int s = 0; s < N; ++s) {
+        double f = 1.0;
+        if (P->lts_cap > 1.0) {
+            f = J[s] / jmin;
+            if (f > P->lts_cap) f = P->lts_cap;
+            if (f > rcoll) f = rcoll;
+            if (f < 1.0) f = 1.0;
+        }
+        dts[s] = P->dt * f;
+    }
 }
 
 /* Advance n_steps SSP-RK3 steps in place:
@@ -598,32 +628,52 @@ long orc_step(const orc_problem *P, double *phi, double *chi, long n_steps, int 
     size_t M = (size_t)V * N;
     double *buf = malloc(sizeof(double) * M * 8);
     double *x = malloc(sizeof(double) * N), *J = malloc(sizeof(double) * N), deta;
-    if (!buf || !x || !J) return -1;
+    double *dts = malloc(sizeof(double) * N);
+    if (!buf || !x || !J || !dts) return -1;
     orc_grid(P, x, J, &deta);
+    cell_time_steps(P, J, dts);
     double *p1 = buf, *c1 = buf + M, *p2 = buf + 2 * M, *c2 = buf + 3 * M;
     double *dp = buf + 4 * M, *dc = buf + 5 * M, *p0 = buf + 6 * M, *c0 = buf + 7 * M;
-    double dt = P->dt, res = -1.0;
+    double res = -1.0;
     long step;
     for (step = 0; step < n_steps; ++step) {
         memcpy(p0, phi, sizeof(double) * M);
         memcpy(c0, chi, sizeof(double) * M);
         orc_rhs(P, phi, chi, dp, dc, NULL);
         for (size_t k = 0; k < M; ++k) {
+            double dt = dts[k % N];
             p1[k] = phi[k] + dt * dp[k];
             c1[k] = chi[k] + dt * dc[k];
         }
         orc_rhs(P, p1, c1, dp, dc, NULL);
         for (size_t k = 0; k < M; ++k) {
+            double dt = dts[k % N];
             p2[k] = 0.75 * phi[k] + 0.25 * (p1[k] + dt * dp[k]);
             c2[k] = 0.75 * chi[k] + 0.25 * (c1[k] + dt * dc[k]);
         }
         orc_rhs(P, p2, c2, dp, dc, NULL);
         for (size_t k = 0; k < M; ++k) {
+            double dt = dts[k % N];
             phi[k] = phi[k] / 3.0 + 2.0 / 3.0 * (p2[k] + dt * dp[k]);
             chi[k] = chi[k] / 3.0 + 2.0 / 3.0 * (c2[k] + dt * dc[k]);
         }
         if (check_every > 0 && (step + 1) % check_every == 0) {
-            res = residual(P, J, p0, c0, phi, chi);
+            res = residual(P, J, dts, p0, c0, phi, chi);
+            if (P->lts_cap > 1.0) {
+                /* local steps: back to the rest-state mass sum_s J_s deta (n = 1) */
+                double m = 0.0, m0 = 0.0;
+                for (int s = 0; s < N; ++s) {
+                    double n = 0.0;
+                    for (int v = 0; v < V; ++v) n += phi[(size_t)v * N + s];
+                    m += J[s] * deta * n;
+                    m0 += J[s] * deta;
+                }
+                double scale = m0 / m;
+                for (size_t k = 0; k < M; ++k) {
+                    phi[k] *= scale;
+                    chi[k] *= scale;
+                }
+            }
             if (tol > 0 && res < tol) {
                 ++step;
                 break;
@@ -638,6 +688,7 @@ long orc_step(const orc_problem *P, double *phi, double *chi, long n_steps, int 
     free(buf);
     free(x);
     free(J);
+    free(dts);
     return step;
 }
 

@@ -52,7 +52,7 @@ class _Problem(C.Structure):
         ("delta", C.c_double), ("uw", C.c_double), ("Tw", C.c_double), ("Pr", C.c_double),
         ("omega", C.c_double), ("dt", C.c_double), ("collisionless", C.c_int), ("half", C.c_int),
         ("ntab", C.c_int), ("tabT", C.POINTER(C.c_double)), ("tabMu", C.POINTER(C.c_double)),
-        ("tabPr", C.POINTER(C.c_double)),
+        ("tabPr", C.POINTER(C.c_double)), ("lts_cap", C.c_double),
     ]
 
 
@@ -103,7 +103,8 @@ class OracleProblem:
     def __init__(self, Qx: int, Qy: int, ncell: int, *, Nx: int | None = None, Ny: int | None = None,
                  stretch_A: float = 0.0, delta: float = 1.0, uw: float = 0.05, Tw: float = 1.0,
                  Pr: float = 2.0 / 3.0, omega: float = 0.7, dt: float | None = None, cfl: float = 0.5,
-                 collisionless: bool = False, half_channel: bool = False, visc_table=None):
+                 collisionless: bool = False, half_channel: bool = False, visc_table=None,
+                 local_dt_cap: float = 0.0):
         self.Qx, self.Qy = Qx, Qy
         self.Nx = min(Qx - 1, 10) if Nx is None else Nx
         self.Ny = Qy - 1 if Ny is None else Ny
@@ -137,7 +138,8 @@ class OracleProblem:
                            _ptr(self.phi_lo), _ptr(self.zy), _ptr(self.wy), ncell, stretch_A,
                            delta, uw, Tw, Pr, omega, self.dt, int(self.collisionless), int(self.half),
                            0 if self.table is None else self.table.shape[1],
-                           *([None] * 3 if self.table is None else [_ptr(r) for r in self._tab]))
+                           *([None] * 3 if self.table is None else [_ptr(r) for r in self._tab]),
+                           float(local_dt_cap))
 
     # -- grid and time step ------------------------------------------------------------------
     def _grid(self):

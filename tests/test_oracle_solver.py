@@ -98,6 +98,51 @@ def test_half_channel_conserves_mass_and_keeps_the_rest_state():
     assert np.max(np.abs(phi - phi0)) <= 1e-14 * np.max(phi0)
 
 
+def test_local_time_steps_reach_the_same_steady_state_in_fewer_steps():
+    # local steps change the transient only: the fixed point R(f) = 0 at the rest-state mass is the
+    # one the global time step reaches (A = 0.98 gives cells 24x apart in size)
+    kw = dict(stretch_A=0.98, delta=1.0, uw=0.5, omega=0.7, half_channel=True)
+    g = OracleProblem(4, 4, 16, **kw)
+    loc = OracleProblem(4, 4, 16, local_dt_cap=64.0, **kw)
+    pg, cg = g.init_state()
+    pl, cl = loc.init_state()
+    ng, rg = g.step(pg, cg, 200000, 200, 1e-10)
+    nl, rl = loc.step(pl, cl, 200000, 200, 1e-10)
+    assert rg < 1e-10 and rl < 1e-10
+    assert nl * 4 < ng
+    fg, fl = g.moments(pg, cg), loc.moments(pl, cl)
+    for k in range(10):
+        assert np.max(np.abs(fg[k] - fl[k])) <= 1e-8 * max(1.0, np.max(np.abs(fg[k])))
+    assert abs(loc.Pi(fl) - g.Pi(fg)) <= 1e-8 * abs(g.Pi(fg))
+    # every check rescales to the rest-state mass sum_s J_s deta
+    assert loc.mass(pl) == pytest.approx(float(np.sum(loc.J * loc.deta)), rel=1e-14)
+
+
+def test_local_time_steps_on_a_uniform_grid_are_the_global_step():
+    # with equal cells every local step equals dt: the run differs from the global one only by the
+    # mass rescaling at checks, which is 1 to round-off (the global step conserves mass)
+    kw = dict(stretch_A=0.0, delta=1.0, uw=0.3)
+    g = OracleProblem(4, 4, 16, **kw)
+    loc = OracleProblem(4, 4, 16, local_dt_cap=64.0, **kw)
+    pg, cg = g.init_state()
+    pl, cl = loc.init_state()
+    g.step(pg, cg, 300, 100)
+    loc.step(pl, cl, 300, 100)
+    assert np.max(np.abs(pg - pl)) <= 1e-13 * np.max(pg)
+
+
+def test_local_time_steps_rescale_mass_at_every_check():
+    # without checks the stretched-grid transient drifts in mass; with a check it is restored
+    kw = dict(stretch_A=0.98, delta=1.0, uw=0.5, half_channel=True, local_dt_cap=64.0)
+    p = OracleProblem(4, 4, 16, **kw)
+    m0 = float(np.sum(p.J * p.deta))
+    phi, chi = p.init_state()
+    p.step(phi, chi, 50)
+    assert abs(p.mass(phi) / m0 - 1) > 1e-6
+    p.step(phi, chi, 10, 10)
+    assert p.mass(phi) == pytest.approx(m0, rel=1e-14)
+
+
 def test_free_molecular_limit_gives_pi_equal_one_over_sqrt_pi():
     # delta -> 0: each half-range stream carries its wall's Maxwellian, so n = 1,
     # T = 1 + u_w^2/3, P_xy = -u_w sqrt(2/pi) and equation (Pi) gives 1/sqrt(pi)
