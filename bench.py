@@ -47,6 +47,9 @@ WORKLOADS = {
     # HHLB(10;50) x HLB(6;7) on S = 48 cells, every solve in FP64 to a P_xy drift rate of tol per unit
     # time, served together; mu ~ T^0.66 stands in for the helium tables
     "couette_paper_convergence": dict(kind="study", tol=1e-7, max_steps=4000000, check_every=2000),
+    # the same six solves with local time steps (steady-state acceleration, cap 64)
+    "couette_paper_convergence_lts": dict(kind="study", tol=1e-7, max_steps=4000000, check_every=2000,
+                                          local_dt_cap=64.0),
 }
 
 
@@ -174,7 +177,7 @@ def _study_main(args, spec):
     ids = []
     for r in runs:
         p = hrlb.make_params(delta=r["delta"], uw=uw, ncell=r["S"], stretch_A=0.98, omega=0.66,
-                             precision=hrlb.HRLB_FP64, half_channel=1)
+                             precision=hrlb.HRLB_FP64, half_channel=1, local_dt_cap=spec.get("local_dt_cap", 0.0))
         ids.append(srv.submit(r["Qx"], 7, p, tol=spec["tol"], max_steps=spec["max_steps"], Nx=r["Nx"], Ny=6))
     units, last = 0.0, t0
     while True:
@@ -208,6 +211,7 @@ def _study_main(args, spec):
         "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "moments_dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "solves": len(runs), "half_channel": True, "stretch_A": 0.98,
+                   "local_dt_cap": spec.get("local_dt_cap", 0.0),
                    "u_w": uw, "omega": 0.66, "stop": {"rule": "pxy_drift", "tol": spec["tol"],
                                                       "check_every": spec["check_every"]},
                    "parallelism": "single GPU, continuous batching"},

@@ -108,6 +108,15 @@ typedef struct {
      * by hrlb_init_case (and by hrlb_server_submit); the caller keeps ownership. */
     int visc_table_n;
     const double *visc_T, *visc_mu, *visc_Pr;
+    /* Steady-state acceleration (not in the paper).  0 (or 1): every cell advances with dt.  > 1: local
+     * time steps, cell s advancing with dt_s = dt max(1, min(J_s/min J, local_dt_cap, tau_w/(2 dt)))
+     * (J_s deta the cell width, tau_w = tau(n = 1, T_w), no tau term when collisionless), so every
+     * cell runs at the Courant number of the smallest one.  The transient is then not time-accurate
+     * and does not conserve mass: every checked step (hrlb_run_to_steady, hrlb_batch_step with check,
+     * the server's rounds) rescales the populations to the rest-state mass sum_s J_s deta and
+     * recomputes the moments.  The residual becomes ||(f_new - f_old)/dt_s|| / ||f_old||.  The
+     * fixed point R(f) = 0, and so the steady state, is the one of the global step.  At most 1e6. */
+    double local_dt_cap;
 } hrlb_case_params;
 
 /* Device workspace size (bytes) needed by a case with these parameters. */

@@ -158,6 +158,7 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
     if (p->cell_lanes < 0 || p->cell_lanes > kMaxCellLanes || (p->cell_lanes & (p->cell_lanes - 1)))
         return fail(HRLB_E_INVALID, "cell_lanes=%d must be 0 or a power of two up to %d", p->cell_lanes, kMaxCellLanes);
     if (p->half_channel != 0 && p->half_channel != 1) return fail(HRLB_E_INVALID, "half_channel must be 0 or 1");
+    if (!(p->local_dt_cap >= 0.0 && p->local_dt_cap <= 1e6)) return fail(HRLB_E_INVALID, "local_dt_cap outside [0, 1e6]");
     if (p->visc_table_n != 0) {
         const int nt = p->visc_table_n;
         if (nt < 2 || nt > kMaxViscTable) return fail(HRLB_E_INVALID, "visc_table_n=%d outside [2, %d]", nt, kMaxViscTable);
@@ -236,6 +237,8 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     L.t_vMu = t; t += nt;
     L.t_vOm = t; t += nt > 0 ? nt - 1 : 0;
     L.t_vPr = t; t += nt;
+    L.t_dts = t; t += nx;
+    L.t_jres = t; t += nx;
     L.t_n = t;
     off = align256(off + sizeof(double) * t);
     for (int k = 0; k < 3; ++k) {
@@ -316,6 +319,14 @@ hrlb_status enqueue_eager(const Launcher& L, long n_steps, bool check_last, hipS
                                stage == 2 ? FLAG_STEP_DONE : 0, L.shmem, st));
         }
         if (chk) HIP_TRY(hrlbk_finalize(L.descs, L.ninst, 1, st));
+        if (chk && L.any_lts) {
+            // local time steps: rescale to the rest-state mass, then recompute the moments, walls and
+            // equilibrium tables of the rescaled state (reproduces bit for bit what the other
+            // instances of the launch already hold)
+            HIP_TRY(hrlbk_renorm(L.fp32, L.descs, L.ninst, st));
+            HIP_TRY(hrlbk_stage(L.fp32, L.descs, L.tiles, L.ntiles, L.ctr, -1, 0, L.qy_max, st));
+            HIP_TRY(hrlbk_cell(L.fp32, L.descs, L.cells, L.ncellblocks, 0, 0, L.shmem, st));
+        }
     }
     return HRLB_OK;
 }
@@ -479,6 +490,25 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
         }
     }
     c->dt = dt;
+    // time step of each cell: dt, or the local steps of local_dt_cap (every cell at the Courant
+    // number of the smallest, capped, and within half the rest-state relaxation time)
+    {
+        double jmin = c->jdeta[0];
+        for (int s = 1; s < nx; ++s) jmin = std::min(jmin, c->jdeta[s]);
+        const double rcoll = p->delta > 0.0 ? 0.5 * (1.0 / (p->delta * std::sqrt(2.0)) / std::sqrt(p->T_w)) / dt : HUGE_VAL;
+        for (int s = 0; s < nx; ++s) {
+            double f = 1.0;
+            if (p->local_dt_cap > 1.0) {
+                f = c->jdeta[s] / jmin;
+                if (f > p->local_dt_cap) f = p->local_dt_cap;
+                if (f > rcoll) f = rcoll;
+                if (f < 1.0) f = 1.0;
+            }
+            const double dts = dt * f;
+            tab[L.t_dts + s] = dts;
+            tab[L.t_jres + s] = c->jdeta[s] * ((dt / dts) * (dt / dts));
+        }
+    }
 
     // descriptor
     InstDesc& D = c->desc;
@@ -503,6 +533,7 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.ktab_n = cell_lds(qx, qy, D.nxb, D.nyb, q->nyo).total;
     D.cell_lanes = L.cell_lanes;
     D.half = p->half_channel;
+    D.lts = p->local_dt_cap > 1.0;
     D.ntab = nt;
     if (nt > 0) {
         double prw = 0.0;
@@ -549,6 +580,8 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.vMu = tb + L.t_vMu;
     D.vOm = tb + L.t_vOm;
     D.vPr = tb + L.t_vPr;
+    D.dts = tb + L.t_dts;
+    D.jres = tb + L.t_jres;
     c->d_desc = (InstDesc*)(ws + L.desc);
     c->d_tiles = (TileRef*)(ws + L.tiles);
     c->d_ctr = (unsigned*)(ws + L.ctr);
@@ -569,6 +602,7 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     c->run.cells = c->d_cells;
     c->run.ncellblocks = L.ncellblocks;
     c->run.qy_max = qy;
+    c->run.any_lts = p->local_dt_cap > 1.0;
     c->run.stream = c->stream;
     std::vector<CellRef> cells;
     for (int b = 0; b < L.ncellblocks; ++b) cells.push_back(CellRef{0, b * (kCellThreads / L.cell_lanes)});
@@ -1033,6 +1067,8 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
         P.run.ncellblocks = P.ncellblocks;
         P.run.shmem = b->shmem;
         P.run.qy_max = b->qy_max;
+        P.run.any_lts = false;
+        for (int i : P.idx) P.run.any_lts = P.run.any_lts || cases[i]->p.local_dt_cap > 1.0;
         P.run.stream = P.stream;
         P.run.graph_steps = b->graph_steps;
         b->parts.push_back(std::move(part));

@@ -74,7 +74,7 @@ struct InstDesc {
     int nyb;       // rows of the padded He table: gy_rows(nyo), 0 = evaluated without the table padding
     int half;      // 1: right half of the channel, mirrored ghosts at x = 0 (no left wall)
     int ntab;      // 0: mu ~ T^omega, constant Pr; >= 2: rows of the tabulated transport law
-    int pad2;
+    int lts;       // 1: local time steps (mass rescaled at checked steps)
     double dt, Tw, Pr, omega;
     double mu_w;         // tabulated law: mu(T_w)
     double tau_pref;     // delta sqrt(2) sqrt(T_w): 1/tau = tau_pref n (T/T_w)^(1-omega)
@@ -107,6 +107,8 @@ struct InstDesc {
     const double* vMu;   // [ntab] mu_k
     const double* vOm;   // [ntab - 1] omega_k = ln(mu_{k+1}/mu_k) / ln(T_{k+1}/T_k)
     const double* vPr;   // [ntab] Pr_k
+    const double* dts;   // [nx] time step of each cell (dt everywhere without local time steps)
+    const double* jres;  // [nx] residual weight J_s deta (dt/dt_s)^2
 };
 
 // ---- padded table shapes of the per-cell kernel ---------------------------------------------

@@ -391,11 +391,17 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
             const uint32_t rowstep = (uint32_t)nx * es;
             const uint32_t chi_off = (uint32_t)nv * rowstep;
             uint32_t rowoff = (uint32_t)vbase * rowstep;
-            double jw[kStrip] = {0, 0, 0, 0};
+            // residual weights: J_s deta for ||f_old||, J_s deta (dt/dt_s)^2 for ||f_new - f_old|| / dt
+            double jw[kStrip] = {0, 0, 0, 0}, jr[kStrip] = {0, 0, 0, 0};
             if (want_res && active)
 #pragma unroll
-                for (int c = 0; c < kStrip; ++c) jw[c] = D.jdeta[s0 + c];
-            const double dt = D.dt;
+                for (int c = 0; c < kStrip; ++c) {
+                    jw[c] = D.jdeta[s0 + c];
+                    jr[c] = D.jres[s0 + c];
+                }
+            double dtc[kStrip];  // time step of each cell (local time steps, or dt everywhere)
+#pragma unroll
+            for (int c = 0; c < kStrip; ++c) dtc[c] = ANALYZE ? 0.0 : D.dts[sc + c];
             uint32_t rkey = 0;
             if (!ANALYZE && D.rounding) {
                 const uint32_t stepc = (uint32_t)D.dyn[DY_STEP];
@@ -537,13 +543,13 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                         const T Lx = -px * (Fc[c + 1] - Fc[c]) * ijd + (tc - x) * itau;
                         // SSP-RK3 stage: out = a f^n + b (f_in + dt L(f_in)), combined in FP64
                         const double fnpd = (double)fnp[c], fncd = (double)fnc[c];
-                        const double ope = ca * fnpd + cb * ((double)p + dt * (double)Lp);
-                        const double oce = ca * fncd + cb * ((double)x + dt * (double)Lx);
+                        const double ope = ca * fnpd + cb * ((double)p + dtc[c] * (double)Lp);
+                        const double oce = ca * fncd + cb * ((double)x + dtc[c] * (double)Lx);
                         op[c] = store_round<T>(ope, D.rounding, rbits[c]);
                         oc[c] = store_round<T>(oce, D.rounding, rbits[c] >> 16);
                         if (want_res) {
                             const double dp = ope - fnpd, dc = oce - fncd;
-                            rnum += jw[c] * (dp * dp + dc * dc);
+                            rnum += jr[c] * (dp * dp + dc * dc);
                             rden += jw[c] * (fnpd * fnpd + fncd * fncd);
                         }
                     }
@@ -971,6 +977,20 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
 }
 
 // ---- per-instance reductions at a check point: residual, mean P_xy, mass ----------------------
+// local time steps: after a checked step (DY_MASS from finalize_kernel), the populations of instance
+// blockIdx.y are rescaled to the rest-state mass sum_s J_s deta; other instances are left alone
+template <typename T>
+__global__ __launch_bounds__(256) void renorm_kernel(const InstDesc* __restrict__ descs)
+{
+    const InstDesc& D = descs[blockIdx.y];
+    if (!D.lts) return;
+    const double scale = D.jsum / D.dyn[DY_MASS];
+    T* f = (T*)D.f[0];
+    const size_t n = 2 * (size_t)D.nv * (size_t)D.nx;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+        f[k] = (T)((double)f[k] * scale);
+}
+
 __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restrict__ descs, int with_res)
 {
     __shared__ double red[256][4];
@@ -1113,6 +1133,20 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_cell(int fp32,
     else
         hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellThreads), shmem, st, descs, cells, buf, flags);
     return hipGetLastError();
+}
+
+extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_renorm(int fp32, const InstDesc* descs, int ninst, hipStream_t st)
+{
+    for (int i0 = 0; i0 < ninst; i0 += 65535) {  // gridDim.y is at most 65535
+        const dim3 grid(256, (unsigned)std::min(65535, ninst - i0));
+        if (fp32)
+            hipLaunchKernelGGL(renorm_kernel<float>, grid, dim3(256), 0, st, descs + i0);
+        else
+            hipLaunchKernelGGL(renorm_kernel<double>, grid, dim3(256), 0, st, descs + i0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_finalize(const InstDesc* descs, int ninst, int with_res, hipStream_t st)

@@ -16,6 +16,7 @@ extern "C" hipError_t hrlbk_stage(int fp32, const hrlb::InstDesc* descs, const h
                                   int stage, int flags, int qy_max, hipStream_t st);
 extern "C" hipError_t hrlbk_cell(int fp32, const hrlb::InstDesc* descs, const hrlb::CellRef* cells, int ncells, int buf,
                                  int flags, size_t shmem, hipStream_t st);
+extern "C" hipError_t hrlbk_renorm(int fp32, const hrlb::InstDesc* descs, int ninst, hipStream_t st);
 extern "C" hipError_t hrlbk_finalize(const hrlb::InstDesc* descs, int ninst, int with_res, hipStream_t st);
 extern "C" hipError_t hrlbk_init(int fp32, const hrlb::InstDesc* descs, int inst, size_t units, hipStream_t st);
 extern "C" hipError_t hrlbk_average(const hrlb::InstDesc* desc, int start, int nx, hipStream_t st);
@@ -65,6 +66,7 @@ struct Launcher {
     int ncellblocks = 0;
     size_t shmem = 0;
     int qy_max = 0;
+    bool any_lts = false;  // some instance takes local time steps: rescale + re-analyse after checks
     hipStream_t stream = nullptr;
     int graph_steps = 0;  // steps per captured graph; < 2 launches directly (faster on this stack)
     int graph_len = 0;
@@ -96,7 +98,7 @@ struct Layout {
     size_t desc, dyn, tables, f[3], cell, fields, avg, mom, res, tiles, cells, ctr, total;
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_vT, t_vMu, t_vOm,
-        t_vPr, t_n;
+        t_vPr, t_dts, t_jres, t_n;
     int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
     int ntile_list;  // records in the case's tile list (XCD-aware order, padded)
 };

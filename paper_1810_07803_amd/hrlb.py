@@ -50,7 +50,7 @@ class CaseParams(C.Structure):
         ("precision", C.c_int), ("rounding", C.c_int), ("cfl", C.c_double), ("dt", C.c_double),
         ("seed", C.c_uint), ("tile_vpt", C.c_int), ("cell_lanes", C.c_int), ("half_channel", C.c_int),
         ("visc_table_n", C.c_int), ("visc_T", C.POINTER(C.c_double)), ("visc_mu", C.POINTER(C.c_double)),
-        ("visc_Pr", C.POINTER(C.c_double)),
+        ("visc_Pr", C.POINTER(C.c_double)), ("local_dt_cap", C.c_double),
     ]
 
 
@@ -184,11 +184,12 @@ def init_quadrature(Qx, Nx, Qy, Ny, p0=1.0) -> Quadrature:
 
 def make_params(*, delta, uw, ncell, stretch_A=0.0, Tw=1.0, Pr=2.0 / 3.0, omega=0.7, precision=HRLB_FP64,
                 rounding=HRLB_ROUND_NEAREST, cfl=0.5, dt=0.0, seed=0, tile_vpt=0, cell_lanes=0,
-                half_channel=0, visc_table=None) -> CaseParams:
+                half_channel=0, visc_table=None, local_dt_cap=0.0) -> CaseParams:
     """Case parameters.  visc_table: rows (T_k, mu_k, Pr_k) of the tabulated transport law (copied by
     the library when the case is created; the returned struct keeps the arrays alive until then)."""
     p = CaseParams(delta, uw, Tw, Pr, omega, ncell, stretch_A, precision, rounding, cfl, dt, seed & 0xFFFFFFFF,
                    tile_vpt, cell_lanes, int(half_channel))
+    p.local_dt_cap = float(local_dt_cap)
     if visc_table is not None:
         cols = [np.ascontiguousarray(c, dtype=np.float64) for c in np.asarray(visc_table, np.float64).T]
         p.visc_table_n = len(cols[0])
