@@ -41,6 +41,9 @@ WORKLOADS = {
     # unit time or after 100k steps
     "couette_serve_poisson200": dict(kind="serve", precision=1, rounding=1, requests=64, rate=200.0,
                                      tol=2e-6, max_steps=100000, check_every=1000),
+    # the same trace with local time steps (steady-state acceleration, cap 64)
+    "couette_serve_poisson200_lts": dict(kind="serve", precision=1, rounding=1, requests=64, rate=200.0,
+                                         tol=2e-6, max_steps=100000, check_every=1000, local_dt_cap=64.0),
     # the quadrature-convergence claim of Sec. IV in its own setting: half channel, A = 0.98,
     # u_w = sqrt(2 K_B T_w/m), delta in {10, 1, 0.1}; the production models HHLB(6;7) x HLB(6;7)
     # (delta = 10, 1) and HHLB(10;16) x HLB(6;7) (delta = 0.1) on S = 16 cells against the reference
@@ -136,7 +139,7 @@ def _serve_main(args, spec):
         pass
     print(f"# serving {len(reqs)} requests", file=sys.stderr, flush=True)
     records, tot = serve.run_trace(srv, reqs, arrivals, tol=spec["tol"], max_steps=spec["max_steps"],
-                                   wall_limit_s=args.serve_wall_s)
+                                   wall_limit_s=args.serve_wall_s, local_dt_cap=spec.get("local_dt_cap", 0.0))
     summ = serve.latency_summary(records)
     summ["solves_per_s"] = summ["finished"] / tot["wall_s"]
     summ["rounds"] = tot["rounds"]
@@ -151,7 +154,8 @@ def _serve_main(args, spec):
         "config": {"workload": args.workload, "requests": len(reqs), "arrival_rate_per_s": spec["rate"],
                    "stop": {"rule": "pxy_drift", "tol": spec["tol"], "max_steps": spec["max_steps"],
                             "check_every": spec["check_every"]},
-                   "arena_mib": args.arena_mib, "parallelism": "single GPU, continuous batching"},
+                   "arena_mib": args.arena_mib, "local_dt_cap": spec.get("local_dt_cap", 0.0),
+                   "parallelism": "single GPU, continuous batching"},
         "serving": summ,
         "roofline": None,
         "cpu_baseline": None,

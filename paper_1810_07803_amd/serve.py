@@ -15,11 +15,12 @@ from . import hrlb
 
 
 def run_trace(server: "hrlb.Server", requests, arrivals, *, tol: float, max_steps: int,
-              stop_rule: int = hrlb.HRLB_STOP_PXY, wall_limit_s: float = 600.0):
+              stop_rule: int = hrlb.HRLB_STOP_PXY, wall_limit_s: float = 600.0, local_dt_cap: float = 0.0):
     """requests: dicts with Qx, Qy, ncell, stretch_A, delta, uw, Tw, Pr, omega, seed (hrlb_inputs
     draws); arrivals: seconds after the trace start.  Returns (records, totals): one record per
     request (arrival, admit and done times relative to the trace start, steps, status, Pi) and the
-    totals of the run (wall time, cell-velocity updates, rounds)."""
+    totals of the run (wall time, cell-velocity updates, rounds).  local_dt_cap > 1 runs every solve with
+    local time steps (steady-state acceleration)."""
     order = np.argsort(arrivals, kind="stable")
     t_start = server.clock()
     ids = {}
@@ -33,7 +34,7 @@ def run_trace(server: "hrlb.Server", requests, arrivals, *, tol: float, max_step
             p = hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
                                  Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
                                  precision=server.precision, rounding=hrlb.HRLB_ROUND_STOCHASTIC,
-                                 seed=d.get("seed", k))
+                                 seed=d.get("seed", k), local_dt_cap=local_dt_cap)
             ids[k] = server.submit(d["Qx"], d["Qy"], p, tol=tol, max_steps=max_steps, stop_rule=stop_rule,
                                    arrival_s=t_start + float(arrivals[k]))
             nxt += 1
