@@ -53,6 +53,9 @@ WORKLOADS = {
     # the same six solves with local time steps (steady-state acceleration, cap 64)
     "couette_paper_convergence_lts": dict(kind="study", tol=1e-7, max_steps=4000000, check_every=2000,
                                           local_dt_cap=64.0),
+    # and with each solve's plan from the autotuner
+    "couette_paper_convergence_lts_tuned": dict(kind="study", tol=1e-7, max_steps=4000000, check_every=2000,
+                                                local_dt_cap=64.0, tune=True),
 }
 
 
@@ -180,9 +183,15 @@ def _study_main(args, spec):
     t0 = time.perf_counter()
     ids = []
     for r in runs:
-        p = hrlb.make_params(delta=r["delta"], uw=uw, ncell=r["S"], stretch_A=0.98, omega=0.66,
-                             precision=hrlb.HRLB_FP64, half_channel=1, local_dt_cap=spec.get("local_dt_cap", 0.0))
-        ids.append(srv.submit(r["Qx"], 7, p, tol=spec["tol"], max_steps=spec["max_steps"], Nx=r["Nx"], Ny=6))
+        kw = dict(delta=r["delta"], uw=uw, ncell=r["S"], stretch_A=0.98, omega=0.66, precision=hrlb.HRLB_FP64,
+                  half_channel=1, local_dt_cap=spec.get("local_dt_cap", 0.0))
+        if spec.get("tune"):
+            # these solves are small enough to be latency bound: the autotuner's plan per solve
+            q = hrlb.Quadrature(r["Qx"], 7, r["Nx"], 6)
+            kw["tile_vpt"], kw["cell_lanes"], _ = hrlb.tune_plan(q, hrlb.make_params(**kw), n_steps=20)
+            r["plan"] = [kw["tile_vpt"], kw["cell_lanes"]]
+        ids.append(srv.submit(r["Qx"], 7, hrlb.make_params(**kw), tol=spec["tol"], max_steps=spec["max_steps"],
+                              Nx=r["Nx"], Ny=6))
     units, last = 0.0, t0
     while True:
         st = srv.pump()
@@ -215,7 +224,7 @@ def _study_main(args, spec):
         "n_gpus": 1, "steps": None, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "moments_dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "solves": len(runs), "half_channel": True, "stretch_A": 0.98,
-                   "local_dt_cap": spec.get("local_dt_cap", 0.0),
+                   "local_dt_cap": spec.get("local_dt_cap", 0.0), "tuned_plans": bool(spec.get("tune")),
                    "u_w": uw, "omega": 0.66, "stop": {"rule": "pxy_drift", "tol": spec["tol"],
                                                       "check_every": spec["check_every"]},
                    "parallelism": "single GPU, continuous batching"},

@@ -1,0 +1,54 @@
+"""Edge sizes of the C ABI against the oracle: the smallest grid (8 cells, both walls' stencils
+overlapping) with the smallest velocity set, the largest velocity set (Qx = 128, Qy = 64: 16384
+velocities, the runtime-order g_y path), and the highest expansion order of eq. (gx) (N_x = 16)."""
+import numpy as np
+import pytest
+
+from hrlb_inputs import perturb
+from tests.gpu_helpers import field_errs, make_pair, rel_state_err, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _parity(Qx, Qy, nx, steps, *, precision=0, rounding=0, Nx=None, half=False, **kw):
+    from oracle.oracle import OracleProblem
+    from paper_1810_07803_amd import hrlb
+
+    orc = OracleProblem(Qx, Qy, nx, Nx=Nx, half_channel=half, **kw)
+    q = hrlb.Quadrature(Qx, Qy, orc.Nx, orc.Ny)
+    case = hrlb.Case(q, hrlb.make_params(delta=kw["delta"], uw=kw["uw"], ncell=nx, stretch_A=kw.get("stretch_A", 0.0),
+                                         precision=precision, rounding=rounding, dt=orc.dt, seed=5,
+                                         half_channel=int(half)))
+    case._quad_ref = q
+    phi, chi = orc.init_state()
+    phi, chi = perturb(phi, 0.05, 61), perturb(chi, 0.05, 62)
+    case.set_state(np.stack([phi, chi]))
+    case.step(steps)
+    orc.step(phi, chi, steps)
+    st = case.get_state()
+    e = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
+    ef = field_errs(case.moments()[0], orc.moments(phi, chi))
+    say(f"   Q{Qx}x{Qy} Nx={orc.Nx} Ny={orc.Ny} nx={nx} half={half} precision={precision}: state err {e:.3e}, "
+        f"field err max {ef.max():.2e}")
+    return e, ef
+
+
+@pytest.mark.parametrize("precision,rounding,tol", [(0, 0, 1e-12), (1, 1, 1e-5)])
+@pytest.mark.parametrize("half", [False, True])
+def test_smallest_grid_and_velocity_set(precision, rounding, tol, half):
+    say("[extremes] 8 cells, HHLB(2;3) x HLB(2;3)")
+    e, ef = _parity(3, 3, 8, 30, precision=precision, rounding=rounding, half=half, delta=1.0, uw=0.4,
+                    stretch_A=0.9)
+    assert e < tol and np.all(ef < tol)
+
+
+def test_largest_velocity_set():
+    say("[extremes] HHLB(10;128) x HLB(63;64): 16384 velocities, 8 cells")
+    e, ef = _parity(128, 64, 8, 3, delta=1.0, uw=0.3, stretch_A=0.9)
+    assert e < 1e-12 and np.all(ef < 1e-12)
+
+
+def test_highest_expansion_order_of_gx():
+    say("[extremes] HHLB(16;32) x HLB(7;8), 40 cells")
+    e, ef = _parity(32, 8, 40, 10, Nx=16, delta=0.5, uw=0.3, stretch_A=0.9)
+    assert e < 1e-12 and np.all(ef < 1e-12)
