@@ -5,14 +5,16 @@
  * The library advances the reduced Shakhov equations (Sec. II, equation boltz_red) for the two
  * reduced distributions phi and chi on a mixed velocity set HHLB(Nx;Qx) x HLB(Ny;Qy)
  * (Sec. III): half-range Gauss-Hermite on the wall-normal axis p_x, full-range Gauss-Hermite on
- * p_y.  Space: WENO-5 finite differences on the stretched grid of equation (stretch), extended
- * to the full channel x in [-1/2, 1/2].  Time: third-order TVD (SSP) Runge-Kutta.  Walls: diffuse
- * reflection, equations (diffuse) and (diffuse_nw); the left wall moves with -u_w, the right
- * one with +u_w, both at T_w.
+ * p_y.  Space: WENO-5 finite differences on the stretched grid of equation (stretch), over the
+ * full channel x in [-1/2, 1/2] or, using the point symmetry of Sec. II, its right half [0, 1/2]
+ * (hrlb_case_params.half_channel).  Time: third-order TVD (SSP) Runge-Kutta, optionally with
+ * local time steps for steady states (local_dt_cap).  Walls: diffuse reflection, equations
+ * (diffuse) and (diffuse_nw); the left wall moves with -u_w, the right one with +u_w, both at T_w.
  *
  * Units: m = K_B = L = 1, average density n_ref = 1, reference momentum p0 = 1.  With these,
  * the relaxation time of equation (tau) with mu ~ T^omega is
- *     tau = (T/T_w)^(omega-1) / (n delta sqrt(2)) / sqrt(T_w).
+ *     tau = (T/T_w)^(omega-1) / (n delta sqrt(2)) / sqrt(T_w),
+ * and with the tabulated law of equations (mun), (interp) mu(T)/mu(T_w) replaces (T/T_w)^omega.
  *
  * Velocity ordering (also used by every host array below):
  *     v = (h*Qx + i)*Qy + j,  p_x = +z_i (h = 0) or -z_i (h = 1),  p_y = y_j ascending,
