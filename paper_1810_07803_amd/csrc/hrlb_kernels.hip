@@ -10,6 +10,10 @@
 //                 the relaxation time of eq. (tau), the Shakhov prefactor and the truncated
 //                 equilibria of eqs. (gx), (gy) that the next stage's collision uses; per instance:
 //                 the leaving wall fluxes and the wall densities of eq. (diffuse_nw).
+// The half channel (point symmetry of Sec. II) replaces the left wall by ghosts read from the
+// mirrored velocities of the first cells.  Around the step: finalize_kernel (residual, channel mean
+// of P_xy, mass at a checked step), renorm_kernel (local time steps: back to the rest-state mass
+// after a check), average_kernel (time averages), init_kernel (rest equilibrium).
 // Layout: populations [dist][v][cell] with cells contiguous.  A thread owns 4 consecutive cells of
 // one velocity and reconstructs their 5 faces from a 12-cell window (the right face is also the
 // next thread's left face; recomputing it costs less than fetching it: a per-tile pre-pass that
