@@ -4,8 +4,9 @@
 * ``traffic``: HBM bytes per dispatch of one kernel from two counter runs (``--pmc FETCH_SIZE`` and
   ``--pmc WRITE_SIZE``, values in KiB per dispatch), each scaled by what the same counter reads for
   the largest plain device copy in the same run (``bench.py --copy-probe-mib N`` issues one of a
-  known size).  The summary records a digest of the kernel sources; ``load_traffic`` returns the
-  figures only while the sources still have that digest.
+  known size).  The summary records a digest of the kernel sources (their code with comments
+  removed and white space collapsed, so that an edit of a comment keeps it); ``load_traffic``
+  returns the figures only while the sources still have that digest.
 
 Command line:
     python -m paper_1810_07803_amd.profiling stats <kernel_stats.csv> [command...]
@@ -16,17 +17,27 @@ from __future__ import annotations
 import csv
 import hashlib
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("csrc/hrlb_kernels.hip", "csrc/hrlb_internal.h", "csrc/hrlb_plan.h", "csrc/hrlb_host.cpp")
 
 
-def source_digest() -> str:
+_TOKENS = re.compile(r'"(?:\\.|[^"\\])*"|(?:\s|//[^\n]*|/\*.*?\*/)+', re.S)
+
+
+def code_only(text: str) -> str:
+    """C/C++ source with every run of white space and comments made one space (string literals
+    kept as written)."""
+    return _TOKENS.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", text).strip()
+
+
+def source_digest(root: str = HERE) -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root, rel), encoding="utf-8") as fh:
+            h.update(code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -68,3 +68,15 @@ def test_workspace_size_scales_with_the_state():
     units = 512 * 2 * 16 * 8
     assert a > 3 * 2 * units * 8 and b > 3 * 2 * units * 4
     assert a - b >= 3 * 2 * units * 4
+
+
+def test_kernel_source_digest_ignores_comments_but_not_code():
+    # the traffic summaries stay valid across comment edits of the kernel sources and are dropped
+    # by any change of the code
+    from paper_1810_07803_amd import profiling
+
+    base = 'int a = 1; // note\n/* block\n comment */ const char* s = "x // y";\nfloat f(float v) { return v - -v; }\n'
+    same = 'int a = 1;\n// another note\nconst char* s = "x // y";   /* c */\nfloat f(float v) {\n  return v - -v;\n}\n'
+    assert profiling.code_only(base) == profiling.code_only(same)
+    for changed in (base.replace("1;", "2;"), base.replace('"x // y"', '"x / y"'), base.replace("- -v", "--v")):
+        assert profiling.code_only(changed) != profiling.code_only(base)
