@@ -52,3 +52,21 @@ def test_highest_expansion_order_of_gx():
     say("[extremes] HHLB(16;32) x HLB(7;8), 40 cells")
     e, ef = _parity(32, 8, 40, 10, Nx=16, delta=0.5, uw=0.3, stretch_A=0.9)
     assert e < 1e-12 and np.all(ef < 1e-12)
+
+
+def test_zero_steps_leave_the_state_unchanged():
+    # n_steps = 0 on a case and on a batch, and a checked zero-step batch call, do nothing
+    from paper_1810_07803_amd import hrlb
+
+    say("[extremes] zero-step calls")
+    case, _ = make_pair(8, 4, 64, delta=1.0, uw=0.3, stretch_A=0.9)
+    case.step(3)
+    s0 = case.get_state()
+    f0 = case.moments()[0]
+    case.step(0)
+    b = hrlb.Batch([case])
+    b.step(0)
+    b.step(0, check=True)
+    np.testing.assert_array_equal(case.get_state(), s0)
+    np.testing.assert_array_equal(case.moments()[0], f0)
+    assert case.steps_done() == 3

@@ -80,3 +80,42 @@ def test_kernel_source_digest_ignores_comments_but_not_code():
     assert profiling.code_only(base) == profiling.code_only(same)
     for changed in (base.replace("1;", "2;"), base.replace('"x // y"', '"x / y"'), base.replace("- -v", "--v")):
         assert profiling.code_only(changed) != profiling.code_only(base)
+
+
+def test_new_case_parameters_and_empty_batches_are_validated():
+    # everything below is rejected on the host, before any device work
+    import ctypes as C
+
+    from paper_1810_07803_amd import hrlb
+
+    q = hrlb.Quadrature(4, 4)
+    good_table = [(0.5, 0.7, 0.66), (1.0, 1.0, 0.67), (2.0, 1.6, 0.68)]
+    assert hrlb.workspace_bytes(q, hrlb.make_params(delta=1.0, uw=0.1, ncell=32, half_channel=1,
+                                                    visc_table=good_table, local_dt_cap=64.0)) > 0
+    bad = [
+        dict(half_channel=2),
+        dict(visc_table=good_table[:1]),                                   # one row
+        dict(visc_table=[(1.0, 1.0, 0.6)] * 257),                         # too many rows
+        dict(visc_table=[(1.0, 1.0, 0.6), (1.0, 1.2, 0.6)]),              # T not increasing
+        dict(visc_table=[(-1.0, 1.0, 0.6), (1.0, 1.2, 0.6)]),             # T not positive
+        dict(visc_table=[(0.5, 0.0, 0.6), (1.0, 1.2, 0.6)]),              # mu not positive
+        dict(visc_table=[(0.5, 1.0, float("nan")), (1.0, 1.2, 0.6)]),     # Pr not finite
+        dict(local_dt_cap=-1.0),
+        dict(local_dt_cap=2e6),
+        dict(ncell=65540),
+    ]
+    for b in bad:
+        kw = dict(delta=1.0, uw=0.1, ncell=32)
+        kw.update(b)
+        with pytest.raises(hrlb.HrlbError) as ei:
+            hrlb.workspace_bytes(q, hrlb.make_params(**kw))
+        assert ei.value.status == hrlb.HRLB_E_INVALID, b
+    p = hrlb.make_params(delta=1.0, uw=0.1, ncell=32, visc_table=good_table)
+    p.visc_mu = None                                                       # NULL row pointer
+    with pytest.raises(hrlb.HrlbError):
+        hrlb.workspace_bytes(q, p)
+    for Qx, Qy in ((129, 4), (4, 65)):
+        with pytest.raises(hrlb.HrlbError):
+            hrlb.Quadrature(Qx, Qy)
+    n = C.c_size_t()
+    assert hrlb.load().hrlb_batch_workspace_bytes(None, 0, C.byref(n)) == hrlb.HRLB_E_INVALID
