@@ -116,3 +116,24 @@ def test_half_channel_steady_state_against_oracle():
     assert np.all(e < 1e-10)
     assert pi_gpu == pytest.approx(orc.Pi(f_orc), rel=1e-10)
     assert abs(info.mass_drift) < 1e-12
+
+
+def test_served_half_channel_solve_equals_alone():
+    from paper_1810_07803_amd import hrlb
+
+    kw = dict(delta=1.0, uw=0.5, ncell=24, stretch_A=0.95, half_channel=1)
+    q = hrlb.Quadrature(4, 4)
+    alone = hrlb.Case(q, hrlb.make_params(**kw))
+    st, info = alone.run_to_steady(1e-4, 20000, 100, hrlb.HRLB_STOP_PXY)
+    srv = hrlb.Server(64 << 20, max_active=4, check_every=100, max_bypass=2, precision=0)
+    rid = srv.submit(4, 4, hrlb.make_params(**kw), tol=1e-4, max_steps=20000)
+    srv.submit(8, 4, hrlb.make_params(delta=0.5, uw=0.2, ncell=64, stretch_A=0.9), tol=1e-4, max_steps=20000)
+    while srv.pump().active:
+        pass
+    info_s, f_served, x_served = srv.request(rid)
+    say(f"[half] served steps {info_s.steps} alone {info.steps}, Pi {info_s.Pi:.12f}")
+    assert info_s.state == hrlb.HRLB_REQ_DONE and info_s.steps == info.steps
+    f, x, pi, _ = alone.moments()
+    np.testing.assert_array_equal(f_served, f)
+    np.testing.assert_array_equal(x_served, x)
+    assert info_s.Pi == pi
