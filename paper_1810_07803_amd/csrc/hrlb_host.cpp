@@ -210,7 +210,7 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     L.nctiles = (nx + kTileCells - 1) / kTileCells;
     L.cell_lanes = p->cell_lanes > 0 ? p->cell_lanes : auto_cell_lanes(qx);
     const int cpb = kCellThreads / L.cell_lanes;
-    L.ncellblocks = (nx + cpb - 1) / cpb;
+    L.ncellblocks = cell_block_count(nx, cpb, wall_blocks_of_their_own(qx, qy));
     size_t off = 0;
     L.desc = off;
     off = align256(off + sizeof(InstDesc));
@@ -605,7 +605,12 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     c->run.any_lts = p->local_dt_cap > 1.0;
     c->run.stream = c->stream;
     std::vector<CellRef> cells;
-    for (int b = 0; b < L.ncellblocks; ++b) cells.push_back(CellRef{0, b * (kCellThreads / L.cell_lanes)});
+    cells = plan_cell_blocks(std::vector<int>{nx}, std::vector<int>{kCellThreads / L.cell_lanes},
+                             std::vector<char>{(char)wall_blocks_of_their_own(qx, qy)});
+    if ((int)cells.size() != L.ncellblocks) {
+        delete c;
+        return fail(HRLB_E_INVALID, "internal: inconsistent cell-block list");
+    }
     std::vector<double> dyn(kNDyn, 0.0);
     dyn[DY_NWL] = dyn[DY_NWR] = 1.0;
 
@@ -1036,15 +1041,18 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
         }
         const int ni = (int)P.idx.size();
         std::vector<InstDesc> descs(ni);
-        std::vector<CellRef> cells;
-        std::vector<int> nct(ni), ngr(ni);
+        std::vector<int> nct(ni), ngr(ni), ncell(ni), cpb(ni);
+        std::vector<char> own(ni);
         for (int q = 0; q < ni; ++q) {
             const hrlb_case* c = cases[P.idx[q]];
             descs[q] = c->desc;
             nct[q] = c->L.nctiles;
             ngr[q] = c->L.ngroups;
-            for (int t = 0; t < c->L.ncellblocks; ++t) cells.push_back(CellRef{q, t * (kCellThreads / c->L.cell_lanes)});
+            ncell[q] = c->p.n_cells;
+            cpb[q] = kCellThreads / c->L.cell_lanes;
+            own[q] = wall_blocks_of_their_own(c->q->qx, c->q->qy);
         }
+        const std::vector<CellRef> cells = plan_cell_blocks(ncell, cpb, own);
         const std::vector<TileRef> tiles = part_tiles(cases, P.idx);
         if ((int)tiles.size() != P.ntiles || (int)cells.size() != P.ncellblocks ||
             !tiles_valid(tiles, (size_t)P.ntiles, ni, nct.data(), ngr.data()))

@@ -23,6 +23,7 @@ static_assert(kTileCells == kPlanTileCells, "tile width of the work lists");
 constexpr int kMaxVpt = kTPR;                 // velocities per row are bounded by the lanes of a row
 constexpr int kMomPerPass = 4;                // moments reduced per LDS pass
 constexpr int kCellThreads = 256;             // threads per block of the per-cell kernel
+static_assert(kCellThreads == kPlanCellThreads, "block size of the per-cell kernel's work list");
 constexpr int kMaxCellLanes = 16;             // lanes per cell of the per-cell kernel (4, 8 or 16)
 
 // auxiliary half-range Gauss rule used to project the Maxwellian on the half-range Hermite

@@ -658,9 +658,10 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
 
 // ---- per-cell kernel --------------------------------------------------------------------------
 // A block of kCellThreads threads serves kCellThreads / L cells with L = cell_lanes lanes per cell
-// (4, 8 or 16, by the size of the velocity set): the lanes of a cell split the sums of the moment
+// (1 to 16; 2 unless the plan says otherwise): the lanes of a cell split the sums of the moment
 // partials over velocity groups, the auxiliary-rule sums of g_x and the output nodes of g_x and
-// g_y, and combine their partial sums by an xor butterfly (identical bits in every lane).
+// g_y, and combine their partial sums by an xor butterfly (identical bits in every lane).  Two more
+// blocks per instance each reduce the leaving fluxes through one wall, beside the cell blocks.
 
 // leaving fluxes through one wall (eq. diffuse_nw): block-wide sums over the leaving directions of
 // p_x F and p_x p_y F, F the wall face value of the current state; fixed-order reduction
@@ -695,6 +696,39 @@ __device__ void wall_sums(const InstDesc& D, const T* f, bool right, double& flu
         mom += red[w][1];
     }
     __syncthreads();  // red may be reused by a second call in the same block
+}
+
+// the left wall of the current state (eq. diffuse_nw: n_w and the momentum flux; none in the half
+// channel), and the count of a completed step; block-wide
+template <typename T>
+__device__ __forceinline__ void wall_left(const InstDesc& D, const T* fcur, int flags)
+{
+    if (!D.half) {
+        double fl, ml;
+        wall_sums<T>(D, fcur, false, fl, ml);
+        if (threadIdx.x == 0) {
+            const double nwl = -fl / D.den_l;
+            D.dyn[DY_NWL] = nwl;
+            D.dyn[DY_SHEAR_L] = ml + nwl * D.mom_l;
+        }
+    }
+    if (threadIdx.x == 0 && (flags & FLAG_STEP_DONE)) {
+        D.dyn[DY_STEP] += 1.0;
+        if (D.dyn[DY_AVG_ON] != 0.0) D.dyn[DY_AVG_STEPS] += 1.0;
+    }
+}
+
+// the right wall of the current state; block-wide
+template <typename T>
+__device__ __forceinline__ void wall_right(const InstDesc& D, const T* fcur)
+{
+    double fr, mr;
+    wall_sums<T>(D, fcur, true, fr, mr);
+    if (threadIdx.x == 0) {
+        const double nwr = -fr / D.den_r;
+        D.dyn[DY_NWR] = nwr;
+        D.dyn[DY_SHEAR_R] = mr + nwr * D.mom_r;
+    }
 }
 
 __device__ __forceinline__ double lane_sum(double x, int lanes)
@@ -828,6 +862,14 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     const CellRef cr = cells[blockIdx.x];
     const InstDesc& D = descs[cr.inst];
     const int nx = D.nx;
+    const T* fcur = (const T*)D.f[buf];
+    if (cr.cell0 < 0) {  // a wall block (uniform per block)
+        if (cr.cell0 == kWallLeft)
+            wall_left<T>(D, fcur, flags);
+        else
+            wall_right<T>(D, fcur);
+        return;
+    }
     const int LN = D.cell_lanes;
     const int q = threadIdx.x & (LN - 1);
     const int s = cr.cell0 + threadIdx.x / LN;
@@ -865,31 +907,11 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     const double* s_hz = ktab + lay.hz;
     const double* s_he = ktab + lay.he;
 
-    // walls: the block holding cell 0 does the left wall, the one holding cell nx-1 the right wall
-    const T* fcur = (const T*)D.f[buf];
-    if (cr.cell0 == 0) {
-        if (!D.half) {  // the half channel has no wall at x = 0
-            double fl, ml;
-            wall_sums<T>(D, fcur, false, fl, ml);
-            if (threadIdx.x == 0) {
-                const double nwl = -fl / D.den_l;
-                D.dyn[DY_NWL] = nwl;
-                D.dyn[DY_SHEAR_L] = ml + nwl * D.mom_l;
-            }
-        }
-        if (threadIdx.x == 0 && (flags & FLAG_STEP_DONE)) {
-            D.dyn[DY_STEP] += 1.0;
-            if (D.dyn[DY_AVG_ON] != 0.0) D.dyn[DY_AVG_STEPS] += 1.0;
-        }
-    }
-    if (cr.cell0 + kCellThreads / LN >= nx) {
-        double fr, mr;
-        wall_sums<T>(D, fcur, true, fr, mr);
-        if (threadIdx.x == 0) {
-            const double nwr = -fr / D.den_r;
-            D.dyn[DY_NWR] = nwr;
-            D.dyn[DY_SHEAR_R] = mr + nwr * D.mom_r;
-        }
+    if (!wall_blocks_of_their_own(D.qx, D.qy)) {
+        // walls done by the edge blocks: the block holding cell 0 the left wall, the one holding
+        // cell nx-1 the right wall
+        if (cr.cell0 == 0) wall_left<T>(D, fcur, flags);
+        if (cr.cell0 + kCellThreads / LN >= nx) wall_right<T>(D, fcur);
     }
 
 #pragma unroll

@@ -18,8 +18,37 @@ struct TileRef {   // one block-sized unit of the stage kernel
 
 struct CellRef {   // one block of the per-cell kernel
     int inst;
-    int cell0;
+    int cell0;     // first cell, or kWallLeft / kWallRight for a block that only does that wall
 };
+constexpr int kWallLeft = -1, kWallRight = -2;
+constexpr int kPlanCellThreads = 256;  // threads per block of the per-cell kernel
+
+// The leaving fluxes through a wall are a block-wide reduction over the qx*qy leaving velocities.
+// When that takes more than one pass of a block, each wall gets a block of its own, which runs
+// beside the cell blocks instead of after the cell work of the edge block; otherwise the edge
+// blocks do it (extra blocks for the many small instances of a batch cost more than they save).
+// Both give the same bits.
+constexpr bool wall_blocks_of_their_own(int qx, int qy) { return qx * qy > kPlanCellThreads; }
+
+// Blocks of the per-cell kernel for a list of instances: the wall blocks first, then the cell
+// blocks, cells_per_block[i] cells each.
+inline std::vector<CellRef> plan_cell_blocks(const std::vector<int>& ncells, const std::vector<int>& cells_per_block,
+                                             const std::vector<char>& own_walls)
+{
+    std::vector<CellRef> out;
+    for (int i = 0; i < (int)ncells.size(); ++i)
+        if (own_walls[i]) {
+            out.push_back(CellRef{i, kWallLeft});
+            out.push_back(CellRef{i, kWallRight});
+        }
+    for (int i = 0; i < (int)ncells.size(); ++i)
+        for (int c0 = 0; c0 < ncells[i]; c0 += cells_per_block[i]) out.push_back(CellRef{i, c0});
+    return out;
+}
+inline int cell_block_count(int ncells, int cells_per_block, bool own_walls)
+{
+    return (own_walls ? 2 : 0) + (ncells + cells_per_block - 1) / cells_per_block;
+}
 
 struct PlanShape {  // what the tile list needs to know about one instance
     int nctiles, ngroups, vpt, ncells;

@@ -1,7 +1,9 @@
 // CPU check of the stage kernel's work lists (hrlb_plan.h): for many random ragged batches and
 // single cases, every natural tile appears exactly once, padding records are the only extras,
 // position p of a list belongs to the chunk of XCD p % 8 (chunks contiguous in the natural order),
-// and the validator accepts the list at its own length and rejects it one record shorter.
+// and the validator accepts the list at its own length and rejects it one record shorter.  The
+// per-cell kernel's block list covers every cell of every instance once and holds two wall blocks
+// for each instance that asks for them (none for the others), all of them ahead of the cell blocks.
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -58,6 +60,34 @@ static void check_list(const std::vector<TileRef>& tiles, const std::vector<Plan
     }
 }
 
+static void check_cell_blocks(const std::vector<int>& ncells, const std::vector<int>& cpb, const std::vector<char>& own)
+{
+    const std::vector<CellRef> b = plan_cell_blocks(ncells, cpb, own);
+    size_t expect = 0;
+    for (size_t i = 0; i < ncells.size(); ++i) expect += cell_block_count(ncells[i], cpb[i], own[i]);
+    CHECK(b.size() == expect);
+    std::vector<int> walls_l(ncells.size(), 0), walls_r(ncells.size(), 0);
+    std::vector<std::vector<int>> covered(ncells.size());
+    for (size_t i = 0; i < ncells.size(); ++i) covered[i].assign(ncells[i], 0);
+    bool seen_cells = false;
+    for (const CellRef& r : b) {
+        CHECK(r.inst >= 0 && r.inst < (int)ncells.size());
+        if (r.cell0 < 0) {
+            CHECK(!seen_cells);
+            CHECK(r.cell0 == kWallLeft || r.cell0 == kWallRight);
+            (r.cell0 == kWallLeft ? walls_l : walls_r)[r.inst]++;
+            continue;
+        }
+        seen_cells = true;
+        CHECK(r.cell0 < ncells[r.inst]);
+        for (int s = r.cell0; s < r.cell0 + cpb[r.inst] && s < ncells[r.inst]; ++s) covered[r.inst][s]++;
+    }
+    for (size_t i = 0; i < ncells.size(); ++i) {
+        CHECK(walls_l[i] == (own[i] ? 1 : 0) && walls_r[i] == walls_l[i]);
+        for (int c : covered[i]) CHECK(c == 1);
+    }
+}
+
 int main()
 {
     std::srand(12345);
@@ -70,6 +100,14 @@ int main()
             shapes.push_back(PlanShape{nct, 1 + std::rand() % 60, 1 + std::rand() % 8, ncells});
         }
         check_list(plan_batch_tiles(shapes), shapes);
+        std::vector<int> nc, cpb;
+        std::vector<char> own;
+        for (const PlanShape& s : shapes) {
+            nc.push_back(s.ncells);
+            cpb.push_back(256 >> (std::rand() % 5));  // 1 to 16 lanes per cell
+            own.push_back((char)(std::rand() % 2));
+        }
+        check_cell_blocks(nc, cpb, own);
         const PlanShape& s = shapes[0];
         std::vector<PlanShape> one{s};
         check_list(case_tiles(s.nctiles, s.ngroups), one);
