@@ -698,6 +698,30 @@ __device__ void wall_sums(const InstDesc& D, const T* f, bool right, double& flu
     __syncthreads();  // red may be reused by a second call in the same block
 }
 
+// entry k of the per-cell kernel's LDS table copy (layout of cell_lds): the value from the tables of
+// the instance, 0 in the padding rows and beyond the end
+__device__ __forceinline__ double ktab_source(const InstDesc& D, const CellLds& lay, int k)
+{
+    const double* src;
+    int r, lim;
+    if (k < lay.wy) {
+        src = D.wx; r = k - lay.wx; lim = D.qx;
+    } else if (k < lay.az) {
+        src = D.wy; r = k - lay.wy; lim = D.qy;
+    } else if (k < lay.aw) {
+        src = D.auxZ; r = k - lay.az; lim = kAux;
+    } else if (k < lay.hZ) {
+        src = D.auxW; r = k - lay.aw; lim = kAux;
+    } else if (k < lay.hz) {
+        src = D.hZ; r = k - lay.hZ; lim = (D.nxo + 1) * kAux;
+    } else if (k < lay.he) {
+        src = D.hz; r = k - lay.hz; lim = (D.nxo + 1) * D.qx;
+    } else {
+        src = D.he; r = k - lay.he; lim = k < lay.total ? (D.nyo + 1) * D.qy : 0;
+    }
+    return r < lim ? src[r] : 0.0;
+}
+
 // the left wall of the current state (eq. diffuse_nw: n_w and the momentum flux; none in the half
 // channel), and the count of a completed step; block-wide
 template <typename T>
@@ -885,19 +909,22 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
         for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + sc];
 
-    // quadrature tables in LDS, rows of h and He padded with zeros to the unrolled counts
+    // quadrature tables in LDS, rows of h and He padded with zeros to the unrolled counts: every
+    // thread issues up to 8 loads before its first LDS write, so the copy takes one or two memory
+    // round trips instead of one per table row block
     const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
     const CellLds lay = cell_lds(qxn, nqy, nxb, nyb, nyo);
-    for (int k = threadIdx.x; k < qxn; k += blockDim.x) ktab[lay.wx + k] = D.wx[k];
-    for (int k = threadIdx.x; k < nqy; k += blockDim.x) ktab[lay.wy + k] = D.wy[k];
-    for (int k = threadIdx.x; k < kAux; k += blockDim.x) {
-        ktab[lay.az + k] = D.auxZ[k];
-        ktab[lay.aw + k] = D.auxW[k];
+    constexpr int kStageBatch = 8;
+    for (int base = 0; base < lay.total; base += kStageBatch * kCellThreads) {
+        double v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) v[u] = ktab_source(D, lay, base + u * kCellThreads + (int)threadIdx.x);
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int k = base + u * kCellThreads + (int)threadIdx.x;
+            if (k < lay.total) ktab[k] = v[u];
+        }
     }
-    for (int k = threadIdx.x; k < nxb * kAux; k += blockDim.x) ktab[lay.hZ + k] = k < (nxo + 1) * kAux ? D.hZ[k] : 0.0;
-    for (int k = threadIdx.x; k < nxb * qxn; k += blockDim.x) ktab[lay.hz + k] = k < (nxo + 1) * qxn ? D.hz[k] : 0.0;
-    const int herows = nyb > 0 ? nyb : nyo + 1;
-    for (int k = threadIdx.x; k < herows * nqy; k += blockDim.x) ktab[lay.he + k] = k < (nyo + 1) * nqy ? D.he[k] : 0.0;
     __syncthreads();
     const double* s_wx = ktab + lay.wx;
     const double* s_wy = ktab + lay.wy;
