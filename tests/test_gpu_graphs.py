@@ -41,3 +41,23 @@ def test_batch_graph_replays_match_direct_launches():
     for x, y in zip(sets[0][0], sets[1][0]):
         np.testing.assert_array_equal(x.get_state(), y.get_state())
     np.testing.assert_array_equal(sets[0][1][0], sets[1][1][0])
+
+
+def test_graph_replays_with_local_time_steps_match_direct_launches():
+    # checked steps of a local-step case also capture the mass rescaling and the re-analysis
+    from paper_1810_07803_amd import hrlb
+
+    say("[graphs] local time steps, checks inside the captured blocks")
+    q = hrlb.Quadrature(8, 4)
+    kw = dict(delta=0.5, uw=0.4, ncell=64, stretch_A=0.98, half_channel=1, local_dt_cap=32.0, precision=1, rounding=1,
+              seed=4)
+    a = hrlb.Case(q, hrlb.make_params(**kw))
+    b = hrlb.Case(q, hrlb.make_params(**kw))
+    a.set_graph_steps(0)
+    b.set_graph_steps(10)
+    for _ in range(3):  # replays after the program's own work and synchronisations
+        sa, ia = a.run_to_steady(1e-300, 40, 10)
+        sb, ib = b.run_to_steady(1e-300, 40, 10)
+        assert ia.residual == ib.residual and ia.mass_drift == ib.mass_drift
+        np.testing.assert_array_equal(a.get_state(), b.get_state())
+        np.testing.assert_array_equal(a.moments()[0], b.moments()[0])
