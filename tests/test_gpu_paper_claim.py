@@ -1,0 +1,42 @@
+"""The quadrature-convergence statement of Sec. IV (tests/golden/paper_quadrature_convergence.json):
+the paper's production models give Pi within 0.1% of HHLB(10;50) x HLB(6;7) on 48 nodes.  The helium
+transport tables are not available; mu ~ T^0.66 stands in for them.  Local time steps (same steady
+state, R18) and autotuned plans keep the solves to seconds; delta = 0.1 runs in the bench workload
+couette_paper_convergence (its reference solve alone takes about 20 s)."""
+import json
+import os
+
+import pytest
+
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_quadrature_convergence.json")
+
+
+def _pi(model, setup, delta):
+    from paper_1810_07803_amd import hrlb
+
+    q = hrlb.Quadrature(model["Qx"], model["Qy"], model["Nx"], model["Ny"])
+    kw = dict(delta=delta, uw=setup["u_w"], ncell=model["S"], stretch_A=setup["stretch_A"], Tw=setup["T_w"],
+              Pr=setup["Pr"], omega=0.66, half_channel=1, local_dt_cap=64.0)
+    vpt, lanes, _ = hrlb.tune_plan(q, hrlb.make_params(**kw), n_steps=10)
+    c = hrlb.Case(q, hrlb.make_params(tile_vpt=vpt, cell_lanes=lanes, **kw))
+    st, info = c.run_to_steady(1e-7, 400000, 2000, hrlb.HRLB_STOP_PXY)
+    assert st == 0, info.pxy_drift
+    pi = c.moments()[2]
+    say(f"   HHLB({model['Nx']};{model['Qx']}) S={model['S']} delta={delta}: Pi {pi:.9f} after {info.steps} steps")
+    return pi
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_production_quadratures_within_a_tenth_of_a_percent_of_the_reference(k):
+    g = json.load(open(GOLDEN))
+    prod = g["production"][k]
+    say(f"[paper claim] delta={prod['delta']}")
+    p = _pi(prod, g["setup"], prod["delta"])
+    r = _pi(g["reference"], g["setup"], prod["delta"])
+    err = p / r - 1.0
+    say(f"   Pi_prod / Pi_ref - 1 = {err:.3e}")
+    assert abs(err) < g["relative_tolerance"]
