@@ -91,6 +91,16 @@ extern "C" hrlb_status hrlb_init_quadrature(int Qx, int Nx_order, int Qy, int Ny
         orthonormal_values(hr, Nx_order, an[k], hv.data());
         for (int l = 0; l <= Nx_order; ++l) q->hZ[(size_t)l * kAux + k] = (double)hv[l];
     }
+    gauss_from_recurrence(hr, kAux2, an, aw);
+    q->auxZ2.resize(kAux2);
+    q->auxW2.resize(kAux2);
+    q->hZ2.assign((size_t)(Nx_order + 1) * kAux2, 0.0);
+    for (int k = 0; k < kAux2; ++k) {
+        q->auxZ2[k] = (double)an[k];
+        q->auxW2[k] = (double)aw[k];
+        orthonormal_values(hr, Nx_order, an[k], hv.data());
+        for (int l = 0; l <= Nx_order; ++l) q->hZ2[(size_t)l * kAux2 + k] = (double)hv[l];
+    }
     Recurrence fr = hermite_recurrence(Qy + 1);
     std::vector<long double> yn, yw;
     gauss_from_recurrence(fr, Qy, yn, yw);
@@ -239,6 +249,9 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     L.t_vPr = t; t += nt;
     L.t_dts = t; t += nx;
     L.t_jres = t; t += nx;
+    L.t_az2 = t; t += kAux2;
+    L.t_aw2 = t; t += kAux2;
+    L.t_hZ2 = t; t += (size_t)(q->nxo + 1) * kAux2;
     L.t_n = t;
     off = align256(off + sizeof(double) * t);
     for (int k = 0; k < 3; ++k) {
@@ -440,6 +453,9 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     std::copy(q->auxZ.begin(), q->auxZ.end(), tab.begin() + L.t_az);
     std::copy(q->auxW.begin(), q->auxW.end(), tab.begin() + L.t_aw);
     std::copy(q->hZ.begin(), q->hZ.end(), tab.begin() + L.t_hZ);
+    std::copy(q->auxZ2.begin(), q->auxZ2.end(), tab.begin() + L.t_az2);
+    std::copy(q->auxW2.begin(), q->auxW2.end(), tab.begin() + L.t_aw2);
+    std::copy(q->hZ2.begin(), q->hZ2.end(), tab.begin() + L.t_hZ2);
     std::copy(q->he.begin(), q->he.end(), tab.begin() + L.t_he);
     for (int s = 0; s < nx; ++s) {
         tab[L.t_ijd + s] = 1.0 / c->jdeta[s];
@@ -530,7 +546,7 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.seed = p->seed;
     D.nxb = gx_rows(q->nxo);
     D.nyb = gy_rows(q->nyo);
-    D.ktab_n = cell_lds(qx, qy, D.nxb, D.nyb, q->nyo).total;
+    D.ktab_n = cell_lds(qx, qy, D.nxb, D.nyb, q->nyo, uses_aux2(L.cell_lanes)).total;
     D.cell_lanes = L.cell_lanes;
     D.half = p->half_channel;
     D.lts = p->local_dt_cap > 1.0;
@@ -570,6 +586,9 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.auxZ = tb + L.t_az;
     D.auxW = tb + L.t_aw;
     D.hZ = tb + L.t_hZ;
+    D.auxZ2 = tb + L.t_az2;
+    D.auxW2 = tb + L.t_aw2;
+    D.hZ2 = tb + L.t_hZ2;
     D.he = tb + L.t_he;
     D.inv_jdeta = tb + L.t_ijd;
     D.jdeta = tb + L.t_jd;

@@ -29,6 +29,12 @@ constexpr int kMaxCellLanes = 16;             // lanes per cell of the per-cell 
 // auxiliary half-range Gauss rule used to project the Maxwellian on the half-range Hermite
 // basis (well-conditioned replacement of the monomial-moment form of eq. gx)
 constexpr int kAux = 48;
+// A second, 24-node rule serves the cells near the wall equilibrium, where it is as accurate: its
+// projections of g/omega on h_0..h_10 differ from the exact integrals by at most 3.3e-16 relative
+// for 0.7 <= T <= 1.1 and |u| <= 1 (2e-14 at T = 1.25, u = 1; 9e-10 at T = 1.6, u = 0.5, where the
+// 48-node rule stays below 2e-15 up to T = 2), so it is used for 0.7 <= T <= 1.15, |u_x| <= 0.75.
+constexpr int kAux2 = 24;
+constexpr double kAux2Tlo = 0.7, kAux2Thi = 1.15, kAux2Umax = 0.75;
 
 constexpr int kMaxQx = 128, kMaxNx = 16, kMaxQy = 64;
 constexpr int kMaxViscTable = 256;  // rows of a tabulated transport law
@@ -98,6 +104,9 @@ struct InstDesc {
     const double* auxZ;  // [kAux]
     const double* auxW;  // [kAux]
     const double* hZ;    // [(nxo+1)][kAux] the same polynomials at the auxiliary nodes
+    const double* auxZ2; // [kAux2] the smaller auxiliary rule
+    const double* auxW2; // [kAux2]
+    const double* hZ2;   // [(nxo+1)][kAux2]
     const double* he;    // [(nyo+1)][qy]   probabilists' Hermite polynomials at the y nodes
     const double* inv_jdeta; // [nx]
     const double* jdeta;     // [nx]
@@ -125,10 +134,13 @@ __host__ __device__ constexpr int gy_rows(int nyo)
          : nyo + 1 <= 32 ? 32 : 0;
 }
 // LDS layout (doubles): wx[qx] wy[qy] auxZ[kAux] auxW[kAux] hZ[nxb][kAux] hz[nxb][qx] he[rows][qy]
+// auxZ2[kAux2] auxW2[kAux2] hZ2[nxb][kAux2], the last three only for plans that use the 24-node rule
+// (at most 8 lanes per cell; uses_aux2)
 struct CellLds {
-    int wx, wy, az, aw, hZ, hz, he, total;
+    int wx, wy, az, aw, hZ, hz, he, az2, aw2, hZ2, total;
 };
-__host__ __device__ inline CellLds cell_lds(int qx, int qy, int nxb, int nyb, int nyo)
+__host__ __device__ constexpr bool uses_aux2(int cell_lanes) { return cell_lanes <= 8; }
+__host__ __device__ inline CellLds cell_lds(int qx, int qy, int nxb, int nyb, int nyo, bool aux2)
 {
     CellLds o;
     o.wx = 0;
@@ -138,7 +150,10 @@ __host__ __device__ inline CellLds cell_lds(int qx, int qy, int nxb, int nyb, in
     o.hZ = o.aw + kAux;
     o.hz = o.hZ + nxb * kAux;
     o.he = o.hz + nxb * qx;
-    o.total = o.he + (nyb > 0 ? nyb : nyo + 1) * qy;
+    o.az2 = o.he + (nyb > 0 ? nyb : nyo + 1) * qy;
+    o.aw2 = o.az2 + (aux2 ? kAux2 : 0);
+    o.hZ2 = o.aw2 + (aux2 ? kAux2 : 0);
+    o.total = o.hZ2 + (aux2 ? nxb * kAux2 : 0);
     return o;
 }
 

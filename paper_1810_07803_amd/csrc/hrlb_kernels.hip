@@ -716,8 +716,14 @@ __device__ __forceinline__ double ktab_source(const InstDesc& D, const CellLds& 
         src = D.hZ; r = k - lay.hZ; lim = (D.nxo + 1) * kAux;
     } else if (k < lay.he) {
         src = D.hz; r = k - lay.hz; lim = (D.nxo + 1) * D.qx;
+    } else if (k < lay.az2) {
+        src = D.he; r = k - lay.he; lim = (D.nyo + 1) * D.qy;
+    } else if (k < lay.aw2) {
+        src = D.auxZ2; r = k - lay.az2; lim = kAux2;
+    } else if (k < lay.hZ2) {
+        src = D.auxW2; r = k - lay.aw2; lim = kAux2;
     } else {
-        src = D.he; r = k - lay.he; lim = k < lay.total ? (D.nyo + 1) * D.qy : 0;
+        src = D.hZ2; r = k - lay.hZ2; lim = k < lay.total ? (D.nxo + 1) * kAux2 : 0;
     }
     return r < lim ? src[r] : 0.0;
 }
@@ -766,7 +772,7 @@ __device__ __forceinline__ double lane_sum(double x, int lanes)
 // independent exponential chains in flight (one node per iteration for the largest row count, whose
 // accumulators already fill the register budget).  Partial sums in k order, then an xor butterfly.
 template <int NB>
-__device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, double ux, const double* s_az,
+__device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, double ux, int K, const double* s_az,
                                            const double* s_aw, const double* s_hZ, double (&Ip)[NB],
                                            double (&Im)[NB])
 {
@@ -776,7 +782,7 @@ __device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, do
     const double rsT = 1.0 / sqrt(Tm);
     const double c0 = (Tm - 1.0) * inv2T, c1 = ux * (2.0 * inv2T), c2 = ux * ux * inv2T;
     int k = q;
-    for (; NB <= 11 && k + LN < kAux; k += 2 * LN) {
+    for (; NB <= 11 && k + LN < K; k += 2 * LN) {
         const double Z0 = s_az[k], Z1 = s_az[k + LN];
         const double a0 = Z0 * Z0 * c0 - c2, a1 = Z1 * Z1 * c0 - c2;
         const double b0 = Z0 * c1, b1 = Z1 * c1;
@@ -785,21 +791,21 @@ __device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, do
         const double em0 = w0 * exp(a0 - b0), em1 = w1 * exp(a1 - b1);
 #pragma unroll
         for (int l = 0; l < NB; ++l) {
-            const double h0 = s_hZ[l * kAux + k], h1 = s_hZ[l * kAux + k + LN];
+            const double h0 = s_hZ[l * K + k], h1 = s_hZ[l * K + k + LN];
             Ip[l] += ep0 * h0;
             Im[l] += em0 * h0;
             Ip[l] += ep1 * h1;
             Im[l] += em1 * h1;
         }
     }
-    for (; k < kAux; k += LN) {
+    for (; k < K; k += LN) {
         const double Z = s_az[k];
         const double a = Z * Z * c0 - c2, bb = Z * c1;
         const double wk = s_aw[k] * rsT;
         const double ep = wk * exp(a + bb), em = wk * exp(a - bb);
 #pragma unroll
         for (int l = 0; l < NB; ++l) {
-            const double h = s_hZ[l * kAux + k];
+            const double h = s_hZ[l * K + k];
             Ip[l] += ep * h;
             Im[l] += em * h;
         }
@@ -812,14 +818,22 @@ __device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, do
         }
 }
 
-// g_x at the 2 Q_x nodes from the projections: n w_i sum_l I_l h_l(z_i)
+// g_x at the 2 Q_x nodes from the projections: n w_i sum_l I_l h_l(z_i); the 24-node auxiliary rule
+// (ktab at s_az2) where it is as accurate as the 48-node one, the latter elsewhere (the same choice in
+// every lane of a cell).  With 16 lanes per cell the 24 nodes would split unevenly over the lanes
+// (pairs on 8 of them, single nodes on the others: both paths in every wave, no faster than the
+// 48-node split), so such plans keep the 48-node rule.
 template <typename T, int NB>
 __device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, double Tm, double ux, bool on, int s,
                                          int nx, int qxn, const double* s_wx, const double* s_az, const double* s_aw,
-                                         const double* s_hZ, const double* s_hz, T* cell)
+                                         const double* s_hZ, const double* s_az2, const double* s_hz, T* cell)
 {
     double Ip[NB], Im[NB];
-    gx_project<NB>(q, LN, nxo, Tm, ux, s_az, s_aw, s_hZ, Ip, Im);
+    const bool small = uses_aux2(LN) && Tm >= kAux2Tlo && Tm <= kAux2Thi && fabs(ux) <= kAux2Umax;
+    if (small)
+        gx_project<NB>(q, LN, nxo, Tm, ux, kAux2, s_az2, s_az2 + kAux2, s_az2 + 2 * kAux2, Ip, Im);
+    else
+        gx_project<NB>(q, LN, nxo, Tm, ux, kAux, s_az, s_aw, s_hZ, Ip, Im);
     for (int i = q; i < qxn; i += LN) {
         double ap = 0.0, am = 0.0;
 #pragma unroll
@@ -910,10 +924,11 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
         for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + sc];
 
     // quadrature tables in LDS, rows of h and He padded with zeros to the unrolled counts: every
-    // thread issues up to 8 loads before its first LDS write, so the copy takes one or two memory
-    // round trips instead of one per table row block
+    // thread issues up to 8 loads before its first LDS write, so the copy takes one memory round
+    // trip (up to 2048 doubles: every velocity set up to Qx = 80, Nx = 10) instead of one per table
+    // row block
     const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
-    const CellLds lay = cell_lds(qxn, nqy, nxb, nyb, nyo);
+    const CellLds lay = cell_lds(qxn, nqy, nxb, nyb, nyo, uses_aux2(D.cell_lanes));
     constexpr int kStageBatch = 8;
     for (int base = 0; base < lay.total; base += kStageBatch * kCellThreads) {
         double v[kStageBatch];
@@ -933,6 +948,7 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     const double* s_hZ = ktab + lay.hZ;
     const double* s_hz = ktab + lay.hz;
     const double* s_he = ktab + lay.he;
+    const double* s_az2 = ktab + lay.az2;
 
     if (!wall_blocks_of_their_own(D.qx, D.qy)) {
         // walls done by the edge blocks: the block holding cell 0 the left wall, the one holding
@@ -1013,10 +1029,10 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     // g_x (eq. gx) and g_y (eq. gy) with the loops over the expansion order unrolled for the case's
     // padded row count (uniform over the block)
     switch (nxb) {
-        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
-        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
-        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
-        default: gx_nodes<T, 17>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_hz, cell); break;
+        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        default: gx_nodes<T, 17>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
     }
     switch (nyb) {
         case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;

@@ -98,7 +98,7 @@ struct Layout {
     size_t desc, dyn, tables, f[3], cell, fields, avg, mom, res, tiles, cells, ctr, total;
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_vT, t_vMu, t_vOm,
-        t_vPr, t_dts, t_jres, t_n;
+        t_vPr, t_dts, t_jres, t_az2, t_aw2, t_hZ2, t_n;
     int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
     int ntile_list;  // records in the case's tile list (XCD-aware order, padded)
 };
@@ -113,6 +113,8 @@ struct hrlb_quad {
     std::vector<double> hz;            // [(nxo+1)][qx]
     std::vector<double> auxZ, auxW;    // [kAux]
     std::vector<double> hZ;            // [(nxo+1)][kAux]
+    std::vector<double> auxZ2, auxW2;  // [kAux2]
+    std::vector<double> hZ2;           // [(nxo+1)][kAux2]
     std::vector<double> he;            // [(nyo+1)][qy]
 };
 

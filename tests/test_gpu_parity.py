@@ -166,3 +166,28 @@ def test_full_size_parity_nx2048_q80x20_in_the_tuned_plan(precision, rounding, t
     say(f"   state err {e_state:.3e}  field errs {np.array2string(e_fields, precision=2)}")
     assert e_state < tol
     assert np.all(e_fields < tol)
+
+
+@pytest.mark.parametrize("precision,rounding,tol", [(0, 0, FP64_TOL), (1, 1, FP32_TOL)])
+def test_parity_across_a_temperature_profile_on_both_auxiliary_rules(precision, rounding, tol):
+    # the per-cell kernel projects g_x with a 24-node auxiliary rule for 0.7 <= T <= 1.15, |u_x| <= 0.75
+    # and with the 48-node rule elsewhere: a local equilibrium with T from 0.8 to 1.6 across the channel
+    # (and a small u_x) puts cells on both sides of the switch
+    say(f"[parity] T profile 0.8..1.6, Q8x8 nx64, precision={precision}")
+    case, orc = make_pair(8, 8, 64, delta=2.0, uw=0.3, stretch_A=0.9, precision=precision, rounding=rounding)
+    Ts = np.linspace(0.8, 1.6, orc.ncell)
+    ux = 0.05 * np.sin(np.linspace(0, np.pi, orc.ncell))
+    phi = np.zeros((orc.nv, orc.ncell))
+    for s, (T, u) in enumerate(zip(Ts, ux)):
+        phi[:, s] = np.outer(orc.gx(u, T), orc.gy(0.0, T)).reshape(-1)
+    chi = phi * Ts[None, :]
+    case.set_state(np.stack([phi, chi]))
+    case.step(10)
+    orc.step(phi, chi, 10)
+    st = case.get_state()
+    f_gpu, f_orc = case.moments()[0], orc.moments(phi, chi)
+    e = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
+    ef = field_errs(f_gpu, f_orc)
+    say(f"   T after 10 steps in [{f_orc[3].min():.3f}, {f_orc[3].max():.3f}]: state err {e:.3e}, field err max {ef.max():.2e}")
+    assert f_orc[3].min() < 1.1 and f_orc[3].max() > 1.3
+    assert e < tol and np.all(ef < tol)
