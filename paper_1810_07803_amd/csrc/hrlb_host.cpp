@@ -338,7 +338,7 @@ hrlb_status enqueue_eager(const Launcher& L, long n_steps, bool check_last, hipS
             // instances of the launch already hold)
             HIP_TRY(hrlbk_renorm(L.fp32, L.descs, L.ninst, st));
             HIP_TRY(hrlbk_stage(L.fp32, L.descs, L.tiles, L.ntiles, L.ctr, -1, 0, L.qy_max, st));
-            HIP_TRY(hrlbk_cell(L.fp32, L.descs, L.cells, L.ncellblocks, 0, 0, L.shmem, st));
+            HIP_TRY(hrlbk_cell(L.fp32, L.descs, L.cells, L.ncellblocks, 0, FLAG_FIELDS, L.shmem, st));
         }
     }
     return HRLB_OK;
@@ -380,7 +380,7 @@ hrlb_status analyze_case(hrlb_case* c)
 {
     const int fp32 = c->p.precision == HRLB_FP32_STORE_FP64_MOM;
     HIP_TRY(hrlbk_stage(fp32, c->d_desc, c->d_tiles, c->ntiles, c->d_ctr, -1, 0, c->q->qy, c->stream));
-    HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, 0, c->shmem, c->stream));
+    HIP_TRY(hrlbk_cell(fp32, c->d_desc, c->d_cells, c->L.ncellblocks, 0, FLAG_FIELDS, c->shmem, c->stream));
     HIP_TRY(hrlbk_finalize(c->d_desc, 1, 0, c->stream));
     c->needs_analyze = false;
     return HRLB_OK;
@@ -1162,7 +1162,7 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
         if (st != HRLB_OK) return st;
         const hrlb_batch_part& P = *b->parts[0];
         HIP_TRY(hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, P.d_ctr, -1, 0, b->qy_max, b->stream));
-        HIP_TRY(hrlbk_cell(b->fp32, P.d_descs, P.d_cells, P.ncellblocks, 0, 0, b->shmem, b->stream));
+        HIP_TRY(hrlbk_cell(b->fp32, P.d_descs, P.d_cells, P.ncellblocks, 0, FLAG_FIELDS, b->shmem, b->stream));
         HIP_TRY(hrlbk_finalize(P.d_descs, (int)P.idx.size(), 0, b->stream));
     }
     // two parts on two streams for large batches: one part's per-cell kernel overlaps the other's

@@ -28,7 +28,9 @@
 
 namespace hrlb {
 
-enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2 };
+// FLAG_FIELDS: the per-cell kernel also stores the FP64 fields (always at the end of a step, with
+// FLAG_STEP_DONE; analysis passes ask for them; the stages inside a step do not need them)
+enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2, FLAG_FIELDS = 4 };
 
 // Loads and stores through the global address space (the pointers live in descriptors, so the
 // compiler would otherwise emit flat instructions).
@@ -990,17 +992,19 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
         if (D.collisionless) invtau = 0.0;
         const double As = (1.0 - pr) / (n * Tm * Tm);
-        double* F = D.fields;
-        F[F_N * nx + s] = n;
-        F[F_UX * nx + s] = ux;
-        F[F_UY * nx + s] = uy;
-        F[F_T * nx + s] = Tm;
-        F[F_PXX * nx + s] = pxx;
-        F[F_PXY * nx + s] = pxy;
-        F[F_PYY * nx + s] = pyy;
-        F[F_TZZ * nx + s] = tzz;
-        F[F_QX * nx + s] = qx;
-        F[F_QY * nx + s] = qy;
+        if (flags & (FLAG_STEP_DONE | FLAG_FIELDS)) {
+            double* F = D.fields;
+            F[F_N * nx + s] = n;
+            F[F_UX * nx + s] = ux;
+            F[F_UY * nx + s] = uy;
+            F[F_T * nx + s] = Tm;
+            F[F_PXX * nx + s] = pxx;
+            F[F_PXY * nx + s] = pxy;
+            F[F_PYY * nx + s] = pyy;
+            F[F_TZZ * nx + s] = tzz;
+            F[F_QX * nx + s] = qx;
+            F[F_QY * nx + s] = qy;
+        }
         cell[SC_UX * nx + s] = (T)ux;
         cell[SC_UY * nx + s] = (T)uy;
         cell[SC_T * nx + s] = (T)Tm;

@@ -23,7 +23,9 @@ extern "C" hipError_t hrlbk_average(const hrlb::InstDesc* desc, int start, int n
 
 namespace hrlb {
 
-enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2 };
+// FLAG_FIELDS: the per-cell kernel also stores the FP64 fields (always at the end of a step, with
+// FLAG_STEP_DONE; analysis passes ask for them; the stages inside a step do not need them)
+enum : int { FLAG_RESID = 1, FLAG_STEP_DONE = 2, FLAG_FIELDS = 4 };
 
 hrlb_status fail(hrlb_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 
