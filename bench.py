@@ -28,6 +28,9 @@ WORKLOADS = {
     "couette_batch512_ragged_fp32": dict(kind="batch", precision=1, rounding=1),
     "couette_batch512_ragged_fp64": dict(kind="batch", precision=0, rounding=0),
     "couette_nx512_q16x8_fp64": dict(kind="single", name="couette_nx512_q16x8", precision=0, rounding=0),
+    # the plain method in FP64, one instance, run to a residual below 1e-10: time to steady
+    "couette_nx32_q4x4_fp64_steady": dict(kind="steady", name="couette_nx32_q4x4_fp64", precision=0, rounding=0,
+                                          tol=1e-10, check_every=100, max_steps=1000000),
     "couette_nx512_q16x8_fp32": dict(kind="single", name="couette_nx512_q16x8", precision=1, rounding=1),
     "couette_nx2048_q80x20_fp32": dict(kind="single", name="couette_nx2048_q80x20", precision=1, rounding=1),
     "couette_nx2048_q80x20_fp64": dict(kind="single", name="couette_nx2048_q80x20", precision=0, rounding=0),
@@ -238,6 +241,43 @@ def _study_main(args, spec):
     return 0
 
 
+def _steady_main(args, spec):
+    """One instance run to steady state with hrlb_run_to_steady (residual rule), timed end to end."""
+    from hrlb_inputs import case
+    from paper_1810_07803_amd import hrlb
+
+    d = case(spec["name"])
+    q = hrlb.Quadrature(d["Qx"], d["Qy"])
+    params = hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
+                              omega=d["omega"], precision=spec["precision"], rounding=spec["rounding"])
+    # warm-up: kernel loading and one short run on a separate case
+    hrlb.Case(q, params).step(10)
+    c = hrlb.Case(q, params)
+    t0 = time.perf_counter()
+    st, info = c.run_to_steady(spec["tol"], spec["max_steps"], spec["check_every"])
+    wall = time.perf_counter() - t0
+    f, x, pi, shear = c.moments()
+    units = c.nv * c.ncell * info.steps
+    out = {
+        "metric": "cell·velocity updates/s",
+        "value": units / wall,
+        "unit": "cell·velocity updates/s",
+        "n_gpus": 1, "steps": int(info.steps), "warmup": 10, "ms_per_step": wall / max(1, info.steps) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if spec["precision"] == 0 else "f32", "moments_dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "case": d, "stop": {"rule": "residual", "tol": spec["tol"],
+                                                                  "check_every": spec["check_every"]},
+                   "parallelism": "single GPU, one instance"},
+        "steady": {"status": int(st), "steps": int(info.steps), "residual": info.residual,
+                   "time_to_steady_s": wall, "solves_per_s": 1.0 / wall, "Pi": pi, "mass_drift": info.mass_drift,
+                   "wall_shear": [float(shear[0]), float(shear[1])]},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -277,6 +317,8 @@ def main(argv=None):
         return _serve_main(args, spec)
     if spec["kind"] == "study":
         return _study_main(args, spec)
+    if spec["kind"] == "steady":
+        return _steady_main(args, spec)
     insts = _instances(spec)
     print(f"# building {len(insts)} instance(s) of {args.workload}", file=sys.stderr, flush=True)
     quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune, tile_vpt=args.tile_vpt,
