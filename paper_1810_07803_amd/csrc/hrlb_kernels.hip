@@ -301,8 +301,10 @@ enum : int { kModeAnalyze = 0, kModeStep = 1, kModeResid = 2 };
 // the next position x + 8 k of its XCD's part of the tile list from the counter ctr[x] until the
 // list is exhausted, so heavy and light tiles balance dynamically.  The last block to finish
 // (counter ctr[8]) clears the counters for the next launch.
+// At least 2 waves per SIMD: without the bound the FP64 variant is allocated past 256 registers
+// (1 wave per SIMD); the FP32 variants fit 3 waves either way.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restrict__ descs,
+__global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __restrict__ descs,
                                                          const TileRef* __restrict__ tiles, int ntiles,
                                                          int stage, unsigned* __restrict__ ctr)
 {
@@ -465,10 +467,23 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                         bld4(rfn, rowoff + oC, fnp);
                         bld4(rfn, chi_off + rowoff + oC, fnc);
                     }
-                    const T phiwl = (T)(nwl * D.gw_l[v]), phiwr = (T)(nwr * D.gw_r[v]);
-                    const T chiwl = (T)(Tw * nwl * D.gw_l[v]), chiwr = (T)(Tw * nwr * D.gw_r[v]);
+                    // wall populations (eq. diffuse) of this velocity: only the strips next to a wall read them
+                    T phiwl = T(0), chiwl = T(0), phiwr = T(0), chiwr = T(0);
+                    if (first) {
+                        const double g = D.gw_l[v];
+                        phiwl = (T)(nwl * g);
+                        chiwl = (T)(Tw * nwl * g);
+                    }
+                    if (last) {
+                        const double g = D.gw_r[v];
+                        phiwr = (T)(nwr * g);
+                        chiwr = (T)(Tw * nwr * g);
+                    }
                     // ghosts: entering directions take the wall populations, leaving ones the
-                    // quadratic extrapolation of the three cells next to the wall
+                    // quadratic extrapolation of the three cells next to the wall.  A leaving face at
+                    // a wall is then the window's own face: its five cells and its operations are
+                    // those of wall_face_left / wall_face_right, so it has the same bits as the wall
+                    // fluxes the per-cell kernel forms.  An entering face is the wall population.
                     T Fp[5], Fc[5];
                     if (px > T(0)) {
                         if (first) {
@@ -500,17 +515,7 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(const InstDesc* __restr
                         }
                         P.faces_neg(Fp);
                         X.faces_neg(Fc);
-                        if (first) {
-                            Fp[0] = wall_face_left(P.w[4], P.w[5], P.w[6]);
-                            Fc[0] = wall_face_left(X.w[4], X.w[5], X.w[6]);
-                        }
-                    }
-                    // right face: from the thread's own window, or the wall face at the end of the channel
-                    if (last) {
-                        if (px > T(0)) {
-                            Fp[4] = wall_face_right(P.w[5], P.w[6], P.w[7]);
-                            Fc[4] = wall_face_right(X.w[5], X.w[6], X.w[7]);
-                        } else {
+                        if (last) {
                             Fp[4] = phiwr;
                             Fc[4] = chiwr;
                         }
