@@ -24,9 +24,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+# Batch workloads run the long-row plan: each instance asks for rows of tile_vpt = the largest
+# divisor of Q_y up to 16 that still fills a group's 16 rows (the library's default rows hold at most
+# 8 velocities).  With ~4,450 tiles per launch the longer rows spread the per-tile work over more
+# velocities; the serving loop's smaller batches keep the default, which fills the GPU with more tiles.
 WORKLOADS = {
-    "couette_batch512_ragged_fp32": dict(kind="batch", precision=1, rounding=1),
-    "couette_batch512_ragged_fp64": dict(kind="batch", precision=0, rounding=0),
+    "couette_batch512_ragged_fp32": dict(kind="batch", precision=1, rounding=1, rows="long"),
+    "couette_batch512_ragged_fp64": dict(kind="batch", precision=0, rounding=0, rows="long"),
     "couette_nx512_q16x8_fp64": dict(kind="single", name="couette_nx512_q16x8", precision=0, rounding=0),
     # the plain method in FP64, one instance, run to a residual below 1e-10: time to steady
     "couette_nx32_q4x4_fp64_steady": dict(kind="steady", name="couette_nx32_q4x4_fp64", precision=0, rounding=0,
@@ -36,7 +40,7 @@ WORKLOADS = {
     "couette_nx2048_q80x20_fp64": dict(kind="single", name="couette_nx2048_q80x20", precision=0, rounding=0),
     # the same flows as their right halves (point symmetry of Sec. II): n_cells/2 cells per instance,
     # one diffuse wall, half the updates per step
-    "couette_batch512_ragged_half_fp32": dict(kind="batch", precision=1, rounding=1, half=True),
+    "couette_batch512_ragged_half_fp32": dict(kind="batch", precision=1, rounding=1, half=True, rows="long"),
     "couette_nx512_q16x8_half_fp32": dict(kind="single", name="couette_nx512_q16x8", precision=1, rounding=1,
                                           half=True),
     # serving: 64 solves drawn like the ragged batch with Nx up to 2048 (seed 1), Poisson arrivals at
@@ -72,9 +76,16 @@ def _instances(spec):
     return [d]
 
 
-def _build(spec, insts, tune: bool, tile_vpt: int = 0, cell_lanes: int = 0):
+def long_row_vpt(Qx: int, Qy: int) -> int:
+    """Velocities per stage-kernel row of the long-row plan: the largest divisor of Qy up to 16 that
+    leaves at least 16 rows (2 Qx Qy / vpt >= 16)."""
+    return max(d for d in range(1, min(Qy, 16) + 1) if Qy % d == 0 and 2 * Qx * Qy // d >= 16)
+
+
+def _build(spec, insts, tune: bool, tile_vpt: int = 0, cell_lanes: int = 0, rows: str = "default"):
     """Cases of the workload; a single instance gets its stage-kernel tiling from the autotuner.
-    tile_vpt / cell_lanes > 0 impose a plan on every instance (where admissible)."""
+    tile_vpt / cell_lanes > 0 impose a plan on every instance (where admissible); rows="long" asks
+    every instance for the long-row plan."""
     from paper_1810_07803_amd import hrlb
 
     quads, cases, tuned = {}, [], None
@@ -91,6 +102,8 @@ def _build(spec, insts, tune: bool, tile_vpt: int = 0, cell_lanes: int = 0):
             kw["cell_lanes"] = cell_lanes
         if tile_vpt > 0 and d["Qy"] % tile_vpt == 0:
             kw["tile_vpt"] = tile_vpt
+        elif rows == "long":
+            kw["tile_vpt"] = long_row_vpt(d["Qx"], d["Qy"])
         if tune and len(insts) == 1:
             tuned = hrlb.tune_plan(quads[key], hrlb.make_params(**kw), n_steps=10)
             kw["tile_vpt"], kw["cell_lanes"] = tuned[0], tuned[1]
@@ -298,6 +311,9 @@ def main(argv=None):
                     "instance (0 = each instance's automatic choice)")
     ap.add_argument("--tile-vpt", type=int, default=0, help="velocities per stage-kernel row for every instance "
                     "whose Qy it divides (0 = automatic)")
+    ap.add_argument("--rows", choices=("default", "long"), default=None,
+                    help="stage-kernel rows of every instance: the library default (at most 8 velocities) or the "
+                    "long-row plan (up to 16); default: the workload's own choice")
     ap.add_argument("--arena-mib", type=int, default=4096, help="serving: device arena for resident solves")
     ap.add_argument("--serve-wall-s", type=float, default=240.0, help="serving: wall-clock limit of the trace")
     args = ap.parse_args(argv)
@@ -321,8 +337,9 @@ def main(argv=None):
         return _steady_main(args, spec)
     insts = _instances(spec)
     print(f"# building {len(insts)} instance(s) of {args.workload}", file=sys.stderr, flush=True)
+    rows = args.rows or spec.get("rows", "default")
     quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune, tile_vpt=args.tile_vpt,
-                                        cell_lanes=args.cell_lanes)
+                                        cell_lanes=args.cell_lanes, rows=rows)
     units = sum(c.nv * c.ncell for c in cases)
     batch.set_graph_steps(args.graph_steps)
     batch.set_streams(args.streams)
@@ -391,7 +408,8 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": args.workload, "instances": len(cases), "units_per_step": units,
                    "half_channel": bool(spec.get("half")),
-                   "graph_steps": args.graph_steps, "streams": args.streams, "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
+                   "graph_steps": args.graph_steps, "streams": args.streams, "rows": rows,
+                   "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
                    "parallelism": "single GPU, instances batched per launch"},
         "wall_s_timed": wall,
         "roofline": roofline,

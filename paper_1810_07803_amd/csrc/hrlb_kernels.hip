@@ -23,6 +23,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 
@@ -193,42 +194,43 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, ui
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, kBufDword3);
 }
-// four consecutive values at a byte offset (16-byte aligned for float, two 16-byte loads for double)
-__device__ __forceinline__ void bld4(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[4])
+// four consecutive values at byte offset off + soff (16-byte aligned for float, two 16-byte loads for
+// double); soff is the wave-uniform part of the offset, which the instruction adds from a scalar register
+__device__ __forceinline__ void bld4(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[4], uint32_t soff = 0)
 {
-    const f4v v = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+    const f4v v = __builtin_bit_cast(f4v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, 0));
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
     o[3] = v.w;
 }
-__device__ __forceinline__ void bld4(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&o)[4])
+__device__ __forceinline__ void bld4(__amdgpu_buffer_rsrc_t r, uint32_t off, double (&o)[4], uint32_t soff = 0)
 {
-    const d2v a = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
-    const d2v b = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off + 16, 0, 0));
+    const d2v a = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, (int)soff, 0));
+    const d2v b = __builtin_bit_cast(d2v, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off + 16, (int)soff, 0));
     o[0] = a.x;
     o[1] = a.y;
     o[2] = b.x;
     o[3] = b.y;
 }
-__device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&o)[4])
+__device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, uint32_t off, const float (&o)[4], uint32_t soff = 0)
 {
     f4v v;
     v.x = o[0];
     v.y = o[1];
     v.z = o[2];
     v.w = o[3];
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, v), r, (int)off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, v), r, (int)off, (int)soff, 0);
 }
-__device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, uint32_t off, const double (&o)[4])
+__device__ __forceinline__ void bst4(__amdgpu_buffer_rsrc_t r, uint32_t off, const double (&o)[4], uint32_t soff = 0)
 {
     d2v a, b;
     a.x = o[0];
     a.y = o[1];
     b.x = o[2];
     b.y = o[3];
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, a), r, (int)off, 0, 0);
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, b), r, (int)off + 16, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, a), r, (int)off, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i4v, b), r, (int)off + 16, (int)soff, 0);
 }
 template <typename T>
 __device__ __forceinline__ T bld1(__amdgpu_buffer_rsrc_t r, uint32_t off);
@@ -242,6 +244,55 @@ __device__ __forceinline__ double bld1<double>(__amdgpu_buffer_rsrc_t r, uint32_
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
+
+// ---- prefetch through LDS (FP32 stage kernel) ----------------------------------------------------
+// The buffer unit writes a velocity's 16-byte loads of a wave straight into that wave's LDS buffer:
+// slot i of lane l lands at buf + i kPfLoad + 16 l.  Slots: the windows of phi (cells s0-4.., s0..,
+// s0+4..) and of chi, then the previous stage's values f^n of phi and chi at cells s0...  The loads
+// of the next velocity are in flight while the wave computes the current one, and they hold no
+// registers meanwhile.  The velocity loop issues no other vector-memory load, so the only waits on
+// the memory counter are the ones below.
+constexpr int kPfSlots = 8;
+constexpr int kPfLoad = 64 * 16;                   // bytes of one slot of a wave
+constexpr int kPfWave = kPfSlots * kPfLoad;        // bytes of a wave's buffer
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+__device__ __forceinline__ void dma16(__amdgpu_buffer_rsrc_t r, unsigned char* slot, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)slot, 16, voff, soff, 0, 0);
+}
+
+// Reads slots 0..N-1 of the lane (LDS byte address la) once at most W vector-memory operations of
+// the wave are outstanding; the memory counter retires in issue order.  The reads are complete when
+// the statement ends (their results are not used before).
+template <int W, int N>
+__device__ __forceinline__ void read_slots(uint32_t la, f4v (&t)[kPfSlots])
+{
+    static_assert((W == 0 || W == 2) && (N == 6 || N == 8), "read_slots: W in {0, 2}, N in {6, 8}");
+#define HRLB_RD6                                                                                      \
+    "ds_read_b128 %0, %8\n\tds_read_b128 %1, %8 offset:1024\n\tds_read_b128 %2, %8 offset:2048\n\t"      \
+    "ds_read_b128 %3, %8 offset:3072\n\tds_read_b128 %4, %8 offset:4096\n\tds_read_b128 %5, %8 offset:5120\n\t"
+#define HRLB_RD8 HRLB_RD6 "ds_read_b128 %6, %8 offset:6144\n\tds_read_b128 %7, %8 offset:7168\n\t"
+#define HRLB_OUTS                                                                                     \
+    "=&v"(t[0]), "=&v"(t[1]), "=&v"(t[2]), "=&v"(t[3]), "=&v"(t[4]), "=&v"(t[5]), "=&v"(t[6]), "=&v"(t[7])
+    if constexpr (W == 0 && N == 6)
+        __asm__ volatile("s_waitcnt vmcnt(0)\n\t" HRLB_RD6 "s_waitcnt lgkmcnt(0)" : HRLB_OUTS : "v"(la));
+    else if constexpr (W == 2 && N == 6)
+        __asm__ volatile("s_waitcnt vmcnt(2)\n\t" HRLB_RD6 "s_waitcnt lgkmcnt(0)" : HRLB_OUTS : "v"(la));
+    else if constexpr (W == 0 && N == 8)
+        __asm__ volatile("s_waitcnt vmcnt(0)\n\t" HRLB_RD8 "s_waitcnt lgkmcnt(0)" : HRLB_OUTS : "v"(la));
+    else
+        __asm__ volatile("s_waitcnt vmcnt(2)\n\t" HRLB_RD8 "s_waitcnt lgkmcnt(0)" : HRLB_OUTS : "v"(la));
+#undef HRLB_RD6
+#undef HRLB_RD8
+#undef HRLB_OUTS
+}
+// Wait until no vector-memory operation of the wave is outstanding.
+__device__ __forceinline__ void vm_drain() { __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// moments reduced per LDS pass of the stage kernel's epilogue: 2 for FP32 storage (the prefetch
+// buffers take the rest of the LDS share of a block), 4 for FP64
+__host__ __device__ constexpr int moments_per_pass(size_t elem) { return elem == 4 ? 2 : kMomPerPass; }
 
 // The window of a thread owning cells s0..s0+3 is w[m] = cell s0 - 4 + m, m = 0..11; its faces
 // f = 0..4 lie between cells s0+f-1 and s0+f (face 4 is also the next thread's face 0: both are
@@ -309,9 +360,17 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                                                          int stage, unsigned* __restrict__ ctr)
 {
     constexpr bool ANALYZE = MODE == kModeAnalyze;
+    constexpr bool kDma = std::is_same<T, float>::value && !ANALYZE;  // windows prefetched through LDS
     // dynamic LDS: [union of (cell tables of the tile) and (moment reduction)] + boundary faces
     extern __shared__ __align__(16) unsigned char smem[];
     double(*lds_mom)[kRows][kTileCells] = reinterpret_cast<double(*)[kRows][kTileCells]>(smem);
+    // the window prefetch buffers of the FP32 kernels: an LDS object of their own, so that the
+    // compiler tells them apart from the cell tables (no wait for the prefetch before table reads)
+    unsigned char* pfbuf = nullptr;
+    if constexpr (kDma) {
+        __shared__ __align__(16) unsigned char s_pf[(kThreads / 64) * kPfWave];
+        pfbuf = s_pf;
+    }
     T* lds_cell = reinterpret_cast<T*>(smem);
     __shared__ double lds_red[kThreads / 64][2];
 
@@ -351,6 +410,52 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
         const double nwl = D.dyn[DY_NWL], nwr = D.dyn[DY_NWR];
         const double Tw = D.Tw;
         const int nslot = cell_lds_slots(qy);
+        // window offsets of the lane: cells s0-4.., s0.., s0+4.. (idle lanes read cells 0..3)
+        const int sc = active ? s0 : 0;
+        const bool last = s0 + kStrip == nx;
+        const uint32_t oL = (uint32_t)(active && s0 != 0 ? s0 - 4 : sc) * es;
+        const uint32_t oC = (uint32_t)sc * es;
+        const uint32_t oR = (uint32_t)(active && !last ? s0 + 4 : sc) * es;
+        const uint32_t rowstep = (uint32_t)nx * es;
+        const uint32_t chi_off = (uint32_t)nv * rowstep;
+        // offset of velocity vbase + k: the lane's rowoff plus the wave-uniform k rowstep
+        const uint32_t rowoff = (uint32_t)vbase * rowstep;
+        // this wave's prefetch buffer and the lane's LDS byte address in it
+        unsigned char* const pf = pfbuf + __builtin_amdgcn_readfirstlane(tid / 64) * kPfWave;  // wave-uniform
+        const uint32_t pf_la = (uint32_t)(uintptr_t)(lds_ptr)pf + (uint32_t)(tid % 64) * 16u;
+        // the strip at cell 0: the left wall closure (full channel) or the mirrored ghosts (half channel)
+        const bool first = s0 == 0 && !D.half, mirror = s0 == 0 && D.half;
+        // rows of the mirrored velocities (-p_x, -p_y): the other sign of the half-range node, the
+        // full-range node of opposite sign (nodes symmetric about 0, ascending)
+        const int hmir = hi < qx ? hi + qx : hi - qx;
+        const int jbase = vbase - hi * qy;  // j of the row's first velocity
+        const __amdgpu_buffer_rsrc_t rfn = make_rsrc(D.f[0], state_bytes);
+        // the prefetch of velocity k: windows, f^n (stages 2 and 3), and for the strip at cell 0 of
+        // a half channel the mirrored cells in place of the left windows
+        auto prefetch = [&](int k) {
+            const uint32_t ks = (uint32_t)k * rowstep;
+            dma16(rin, pf + 0 * kPfLoad, rowoff + oL, ks);
+            dma16(rin, pf + 1 * kPfLoad, rowoff + oC, ks);
+            dma16(rin, pf + 2 * kPfLoad, rowoff + oR, ks);
+            dma16(rin, pf + 3 * kPfLoad, chi_off + rowoff + oL, ks);
+            dma16(rin, pf + 4 * kPfLoad, chi_off + rowoff + oC, ks);
+            dma16(rin, pf + 5 * kPfLoad, chi_off + rowoff + oR, ks);
+            if (stage > 0) {
+                dma16(rfn, pf + 6 * kPfLoad, rowoff + oC, ks);
+                dma16(rfn, pf + 7 * kPfLoad, chi_off + rowoff + oC, ks);
+            }
+            if (mirror) {
+                const uint32_t moff = (uint32_t)(hmir * qy + (qy - 1 - (jbase + k))) * rowstep;
+                dma16(rin, pf + 0 * kPfLoad, moff, 0u);
+                dma16(rin, pf + 3 * kPfLoad, chi_off + moff, 0u);
+            }
+        };
+        // the first velocity's loads travel while the cell tables are staged
+        if constexpr (kDma)
+            if (row_on) prefetch(0);
+        // per-tile copies of p_y (all j) and of the wall populations of the tile's velocities
+        double* const lds_py = reinterpret_cast<double*>(smem + (size_t)nslot * kLdsSlot * es);
+        double* const lds_gw = lds_py + qy;  // [left, right][row][k]
 
         if (!ANALYZE) {
             // stage the tile's cell tables: scalars, g_y (all j), g_x of each row's node
@@ -373,6 +478,20 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
 #pragma unroll
                 for (int c = 0; c < 4; ++c) lds_cell[slot * kLdsSlot + c * kTPR + q4] = v4[c];
             }
+            if constexpr (kDma) {
+                for (int i = tid; i < qy; i += kThreads) lds_py[i] = D.py[i];
+                for (int i = tid; i < kRows * vpt; i += kThreads) {
+                    const int r = i / vpt, kk = i - r * vpt, sg = tr.group * kRows + r;
+                    double gl = 0.0, gr = 0.0;
+                    if (sg < D.nseg) {
+                        const int h = sg / D.segs_per_line, vv = h * qy + (sg - h * D.segs_per_line) * vpt + kk;
+                        gl = D.gw_l[vv];
+                        gr = D.gw_r[vv];
+                    }
+                    lds_gw[i] = gl;
+                    lds_gw[kRows * vpt + i] = gr;
+                }
+            }
             __syncthreads();
         }
 
@@ -384,21 +503,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
         double rnum = 0, rden = 0;
 
         if (row_on) {
-            const __amdgpu_buffer_rsrc_t rfn = make_rsrc(D.f[0], state_bytes);
             const __amdgpu_buffer_rsrc_t rout = make_rsrc(D.f[out_idx], state_bytes);
-            const int sc = active ? s0 : 0;  // idle lanes read cells 0..3
-            const bool last = s0 + kStrip == nx;
-            // the strip at cell 0: the left wall closure (full channel) or the mirrored ghosts (half channel)
-            const bool first = s0 == 0 && !D.half, mirror = s0 == 0 && D.half;
-            // rows of the mirrored velocities (-p_x, -p_y): the other sign of the half-range node, the
-            // full-range node of opposite sign (nodes symmetric about 0, ascending)
-            const int hmir = hi < qx ? hi + qx : hi - qx;
-            const uint32_t oL = (uint32_t)(active && s0 != 0 ? s0 - 4 : sc) * es;
-            const uint32_t oC = (uint32_t)sc * es;
-            const uint32_t oR = (uint32_t)(active && !last ? s0 + 4 : sc) * es;
-            const uint32_t rowstep = (uint32_t)nx * es;
-            const uint32_t chi_off = (uint32_t)nv * rowstep;
-            uint32_t rowoff = (uint32_t)vbase * rowstep;
             // residual weights: J_s deta for ||f_old||, J_s deta (dt/dt_s)^2 for ||f_new - f_old|| / dt
             double jw[kStrip] = {0, 0, 0, 0}, jr[kStrip] = {0, 0, 0, 0};
             if (want_res && active)
@@ -415,44 +520,106 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                 const uint32_t stepc = (uint32_t)D.dyn[DY_STEP];
                 rkey = hash32(D.seed ^ hash32(stepc * 3u + (uint32_t)stage + 0x9e3779b9u));
             }
-            for (int k = 0; k < vpt; ++k, rowoff += rowstep) {
+            const int rounding = ANALYZE ? 0 : D.rounding;
+            if constexpr (kDma) {
+                // the loads above have completed before the loop: inside it the memory counter also
+                // counts the prefetch, and a wait for one of them would wait for the prefetch too
+                __asm__ volatile("" ::"v"(dtc[0]), "v"(dtc[1]), "v"(dtc[2]), "v"(dtc[3]), "v"(px), "v"(pxd));
+                if constexpr (want_res)
+                    __asm__ volatile("" ::"v"(jw[0]), "v"(jw[1]), "v"(jw[2]), "v"(jw[3]), "v"(jr[0]), "v"(jr[1]),
+                                     "v"(jr[2]), "v"(jr[3]));
+            }
+            uint32_t kstep = 0;
+            for (int k = 0; k < vpt; ++k, kstep += rowstep) {
+                Win<T> P, X;
+                T fnp[4] = {T(0), T(0), T(0), T(0)}, fnc[4] = {T(0), T(0), T(0), T(0)};
                 const int v = vbase + k;
                 const int j = v - hi * qy;
-                const double pyd = D.py[j];
-                const T py = (T)pyd;
-                Win<T> P, X;
-                {
+                double pyd, gl = 0.0, gr = 0.0;
+                if constexpr (kDma) {
+                    // velocity k is in the buffer once every operation but the last two (the previous
+                    // velocity's output stores) has retired
+                    f4v t[kPfSlots];
+                    if (k == 0) {
+                        if (stage > 0) read_slots<0, 8>(pf_la, t); else read_slots<0, 6>(pf_la, t);
+                    } else {
+                        if (stage > 0) read_slots<2, 8>(pf_la, t); else read_slots<2, 6>(pf_la, t);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        P.w[c] = t[0][c];
+                        X.w[c] = t[3][c];
+                        P.w[4 + c] = t[1][c];
+                        P.w[8 + c] = t[2][c];
+                        X.w[4 + c] = t[4][c];
+                        X.w[8 + c] = t[5][c];
+                        if (stage > 0) {
+                            fnp[c] = t[6][c];
+                            fnc[c] = t[7][c];
+                        }
+                    }
+                    if (mirror)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            // point symmetry of Sec. II about x = 0 (half channel, strip at cell 0): ghost
+                            // cells -1..-4 of (p_x, p_y) hold the values of (-p_x, -p_y) in cells 0..3
+                            P.w[c] = t[0][3 - c];
+                            X.w[c] = t[3][3 - c];
+                        }
+                    pyd = lds_py[j];
+                    gl = lds_gw[row * vpt + k];
+                    gr = lds_gw[(kRows + row) * vpt + k];
+                    // the next velocity (the last one loads its own again, which nothing reads)
+                    prefetch(k + 1 < vpt ? k + 1 : k);
+                } else {
                     T tmp[4];
-                    bld4(rin, rowoff + oL, tmp);
+                    bld4(rin, rowoff + oL, tmp, kstep);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) P.w[c] = tmp[c];
-                    bld4(rin, rowoff + oC, tmp);
+                    bld4(rin, rowoff + oC, tmp, kstep);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) P.w[4 + c] = tmp[c];
-                    bld4(rin, rowoff + oR, tmp);
+                    bld4(rin, rowoff + oR, tmp, kstep);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) P.w[8 + c] = tmp[c];
-                    bld4(rin, chi_off + rowoff + oL, tmp);
+                    bld4(rin, chi_off + rowoff + oL, tmp, kstep);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) X.w[c] = tmp[c];
-                    bld4(rin, chi_off + rowoff + oC, tmp);
+                    bld4(rin, chi_off + rowoff + oC, tmp, kstep);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) X.w[4 + c] = tmp[c];
-                    bld4(rin, chi_off + rowoff + oR, tmp);
+                    bld4(rin, chi_off + rowoff + oR, tmp, kstep);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) X.w[8 + c] = tmp[c];
+                    pyd = D.py[j];
+                    if (!ANALYZE && mirror) {
+                        // point symmetry of Sec. II about x = 0: ghost cells -1..-4 of (p_x, p_y) hold
+                        // the values of (-p_x, -p_y) in cells 0..3
+                        const uint32_t moff = (uint32_t)(hmir * qy + (qy - 1 - j)) * rowstep;
+                        bld4(rin, moff, tmp);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) P.w[3 - c] = tmp[c];
+                        bld4(rin, chi_off + moff, tmp);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) X.w[3 - c] = tmp[c];
+                    }
+                    if (!ANALYZE && stage > 0) {
+                        bld4(rfn, rowoff + oC, fnp, kstep);
+                        bld4(rfn, chi_off + rowoff + oC, fnc, kstep);
+                    }
+                    if (!ANALYZE && first) gl = D.gw_l[v];
+                    if (!ANALYZE && last) gr = D.gw_r[v];
                 }
-                if (!ANALYZE && mirror) {
-                    // point symmetry of Sec. II about x = 0: ghost cells -1..-4 of (p_x, p_y) hold
-                    // the values of (-p_x, -p_y) in cells 0..3
-                    const uint32_t moff = (uint32_t)(hmir * qy + (qy - 1 - j)) * rowstep;
-                    T tmp[4];
-                    bld4(rin, moff, tmp);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) P.w[3 - c] = tmp[c];
-                    bld4(rin, chi_off + moff, tmp);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) X.w[3 - c] = tmp[c];
+                const T py = (T)pyd;
+                // wall populations (eq. diffuse) of this velocity: only the strips next to a wall use them
+                T phiwl = T(0), chiwl = T(0), phiwr = T(0), chiwr = T(0);
+                if (!ANALYZE && first) {
+                    phiwl = (T)(nwl * gl);
+                    chiwl = (T)(Tw * nwl * gl);
+                }
+                if (!ANALYZE && last) {
+                    phiwr = (T)(nwr * gr);
+                    chiwr = (T)(Tw * nwr * gr);
                 }
                 T op[kStrip], oc[kStrip];
                 if (ANALYZE) {
@@ -462,23 +629,6 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                         oc[c] = X.w[4 + c];
                     }
                 } else {
-                    T fnp[4] = {T(0), T(0), T(0), T(0)}, fnc[4] = {T(0), T(0), T(0), T(0)};
-                    if (stage > 0) {
-                        bld4(rfn, rowoff + oC, fnp);
-                        bld4(rfn, chi_off + rowoff + oC, fnc);
-                    }
-                    // wall populations (eq. diffuse) of this velocity: only the strips next to a wall read them
-                    T phiwl = T(0), chiwl = T(0), phiwr = T(0), chiwr = T(0);
-                    if (first) {
-                        const double g = D.gw_l[v];
-                        phiwl = (T)(nwl * g);
-                        chiwl = (T)(Tw * nwl * g);
-                    }
-                    if (last) {
-                        const double g = D.gw_r[v];
-                        phiwr = (T)(nwr * g);
-                        chiwr = (T)(Tw * nwr * g);
-                    }
                     // ghosts: entering directions take the wall populations, leaving ones the
                     // quadratic extrapolation of the three cells next to the wall.  A leaving face at
                     // a wall is then the window's own face: its five cells and its operations are
@@ -520,8 +670,15 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                             Fc[4] = chiwr;
                         }
                     }
+                    if constexpr (kDma) {
+                        // the previous stage's values are first needed by the combine: their loads
+                        // overlap the face computation
+#pragma unroll
+                        for (int c = 0; c < kStrip; ++c)
+                            __asm__ volatile("" : "+v"(fnp[c]), "+v"(fnc[c]) : "v"(Fp[kStrip]), "v"(Fc[kStrip]));
+                    }
                     uint32_t rbits[kStrip] = {0, 0, 0, 0};
-                    if (D.rounding) {
+                    if (rounding) {
                         const uint32_t base = rkey ^ ((uint32_t)v * 0x85ebca6bu) ^ ((uint32_t)s0 * 0xc2b2ae35u);
 #pragma unroll
                         for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : xorshift32(rbits[c - 1]);
@@ -556,8 +713,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                         const double fnpd = (double)fnp[c], fncd = (double)fnc[c];
                         const double ope = ca * fnpd + cb * ((double)p + dtc[c] * (double)Lp);
                         const double oce = ca * fncd + cb * ((double)x + dtc[c] * (double)Lx);
-                        op[c] = store_round<T>(ope, D.rounding, rbits[c]);
-                        oc[c] = store_round<T>(oce, D.rounding, rbits[c] >> 16);
+                        op[c] = store_round<T>(ope, rounding, rbits[c]);
+                        oc[c] = store_round<T>(oce, rounding, rbits[c] >> 16);
                         if (want_res) {
                             const double dp = ope - fnpd, dc = oce - fncd;
                             rnum += jr[c] * (dp * dp + dc * dc);
@@ -565,8 +722,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                         }
                     }
                     if (active) {
-                        bst4(rout, rowoff + oC, op);
-                        bst4(rout, chi_off + rowoff + oC, oc);
+                        bst4(rout, rowoff + oC, op, kstep);
+                        bst4(rout, chi_off + rowoff + oC, oc, kstep);
                     }
                 }
                 if (active) {
@@ -585,6 +742,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                 }
             }
         }
+        // the last prefetch has landed before its LDS becomes part of the moment sums
+        if constexpr (kDma) vm_drain();
         if (!ANALYZE) __syncthreads();  // the LDS region switches from cell tables to moment sums
 
         // ---- moments: combine the row sums with the powers of p_x, reduce rows in LDS ----------
@@ -608,11 +767,12 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                 m11[10][c] = B1;
             }
         }
+        constexpr int kMpp = moments_per_pass(sizeof(T));
 #pragma unroll
-        for (int pass = 0; pass < (kNMom + kMomPerPass - 1) / kMomPerPass; ++pass) {
+        for (int pass = 0; pass < (kNMom + kMpp - 1) / kMpp; ++pass) {
 #pragma unroll
-            for (int mm = 0; mm < kMomPerPass; ++mm) {
-                const int m = pass * kMomPerPass + mm;
+            for (int mm = 0; mm < kMpp; ++mm) {
+                const int m = pass * kMpp + mm;
                 if (m < kNMom) {
                     // position c * 16 + strip: the 16 lanes of a row write 16 consecutive words
 #pragma unroll
@@ -623,9 +783,9 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
             {
                 // lane l of the reading wave takes position l: cell 4 (l % 16) + l / 16 of the tile
                 const int mm = tid / kTileCells, pos = tid % kTileCells;
-                const int m = pass * kMomPerPass + mm;
+                const int m = pass * kMpp + mm;
                 const int cellx = c0 + (pos % kTPR) * kStrip + pos / kTPR;
-                if (m < kNMom && cellx < nx) {
+                if (mm < kMpp && m < kNMom && cellx < nx) {
                     double s = 0.0;
 #pragma unroll
                     for (int r = 0; r < kRows; ++r) s += lds_mom[mm][r][pos];
@@ -1147,8 +1307,10 @@ using namespace hrlb;
 extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_stage_lds(int fp32, int qy_max)
 {
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
-    const size_t cells = (size_t)cell_lds_slots(qy_max) * kLdsSlot * es;
-    const size_t moms = sizeof(double) * kMomPerPass * kRows * kTileCells;
+    // FP32: the cell tables are followed by p_y and the wall populations of the tile's velocities
+    const size_t vel = fp32 ? sizeof(double) * (size_t)(qy_max + 2 * kRows * std::min(qy_max, kMaxVpt)) : 0;
+    const size_t cells = (size_t)cell_lds_slots(qy_max) * kLdsSlot * es + vel;
+    const size_t moms = sizeof(double) * moments_per_pass(fp32 ? sizeof(float) : sizeof(double)) * kRows * kTileCells;
     return cells > moms ? cells : moms;
 }
 
