@@ -767,7 +767,12 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                 m11[10][c] = B1;
             }
         }
-        constexpr int kMpp = moments_per_pass(sizeof(T));
+        // the FP32 step kernels reduce in the drained prefetch buffers (4 moments per pass, like FP64)
+        constexpr int kMpp = kDma ? kMomPerPass : moments_per_pass(sizeof(T));
+        static_assert(!kDma || sizeof(double) * kMomPerPass * kRows * kTileCells <= (kThreads / 64) * kPfWave,
+                      "moment passes fit the prefetch buffers");
+        double(*const lds_red_mom)[kRows][kTileCells] =
+            kDma ? reinterpret_cast<double(*)[kRows][kTileCells]>(pfbuf) : lds_mom;
 #pragma unroll
         for (int pass = 0; pass < (kNMom + kMpp - 1) / kMpp; ++pass) {
 #pragma unroll
@@ -776,7 +781,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                 if (m < kNMom) {
                     // position c * 16 + strip: the 16 lanes of a row write 16 consecutive words
 #pragma unroll
-                    for (int c = 0; c < kStrip; ++c) lds_mom[mm][row][c * kTPR + strip] = m11[m][c];
+                    for (int c = 0; c < kStrip; ++c) lds_red_mom[mm][row][c * kTPR + strip] = m11[m][c];
                 }
             }
             __syncthreads();
@@ -788,7 +793,7 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                 if (mm < kMpp && m < kNMom && cellx < nx) {
                     double s = 0.0;
 #pragma unroll
-                    for (int r = 0; r < kRows; ++r) s += lds_mom[mm][r][pos];
+                    for (int r = 0; r < kRows; ++r) s += lds_red_mom[mm][r][pos];
                     D.mom_part[((size_t)tr.group * kNMom + m) * nx + cellx] = s;
                 }
             }
