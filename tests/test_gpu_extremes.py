@@ -10,7 +10,7 @@ from tests.gpu_helpers import field_errs, make_pair, rel_state_err, say
 pytestmark = pytest.mark.gpu
 
 
-def _parity(Qx, Qy, nx, steps, *, precision=0, rounding=0, Nx=None, half=False, **kw):
+def _parity(Qx, Qy, nx, steps, *, precision=0, rounding=0, Nx=None, half=False, tile_vpt=0, **kw):
     from oracle.oracle import OracleProblem
     from paper_1810_07803_amd import hrlb
 
@@ -18,7 +18,7 @@ def _parity(Qx, Qy, nx, steps, *, precision=0, rounding=0, Nx=None, half=False, 
     q = hrlb.Quadrature(Qx, Qy, orc.Nx, orc.Ny)
     case = hrlb.Case(q, hrlb.make_params(delta=kw["delta"], uw=kw["uw"], ncell=nx, stretch_A=kw.get("stretch_A", 0.0),
                                          precision=precision, rounding=rounding, dt=orc.dt, seed=5,
-                                         half_channel=int(half)))
+                                         half_channel=int(half), tile_vpt=tile_vpt))
     case._quad_ref = q
     phi, chi = orc.init_state()
     phi, chi = perturb(phi, 0.05, 61), perturb(chi, 0.05, 62)
@@ -42,10 +42,24 @@ def test_smallest_grid_and_velocity_set(precision, rounding, tol, half):
     assert e < tol and np.all(ef < tol)
 
 
-def test_largest_velocity_set():
+@pytest.mark.parametrize("precision,rounding,tol", [(0, 0, 1e-12), (1, 1, 1e-5)])
+def test_largest_velocity_set(precision, rounding, tol):
+    # FP32 storage: the stage kernel's LDS (cell tables of 64 g_y rows, the per-tile velocity
+    # tables, the window prefetch buffers) is at its largest here
     say("[extremes] HHLB(10;128) x HLB(63;64): 16384 velocities, 8 cells")
-    e, ef = _parity(128, 64, 8, 3, delta=1.0, uw=0.3, stretch_A=0.9)
-    assert e < 1e-12 and np.all(ef < 1e-12)
+    e, ef = _parity(128, 64, 8, 3, precision=precision, rounding=rounding, delta=1.0, uw=0.3, stretch_A=0.9)
+    assert e < tol and np.all(ef < tol)
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_longest_rows_fp32(half):
+    # rows of 16 velocities (the most a row holds): the prefetch walks 16 velocities per tile and the
+    # per-tile copies of p_y and the wall populations are at their largest; 96 cells = one full tile
+    # and a ragged one
+    say(f"[extremes] rows of 16 velocities, HHLB(7;8) x HLB(15;16), 96 cells, half={half}")
+    e, ef = _parity(8, 16, 96, 12, precision=1, rounding=1, half=half, tile_vpt=16, delta=0.5, uw=0.3,
+                    stretch_A=0.9)
+    assert e < 1e-5 and np.all(ef < 1e-5)
 
 
 def test_highest_expansion_order_of_gx():
