@@ -8,24 +8,27 @@ from tests.gpu_helpers import field_errs, make_pair, rel_state_err, say
 pytestmark = pytest.mark.gpu
 
 
-def test_every_tiling_matches_the_oracle():
+@pytest.mark.parametrize("precision,rounding,tol", [(0, 0, 1e-12), (1, 1, 1e-5)])
+def test_every_tiling_matches_the_oracle(precision, rounding, tol):
+    # FP32 storage runs the stage kernel's LDS prefetch, whose per-row velocity walk (1 to 12
+    # velocities here, the last one loading itself again) each plan exercises
     from paper_1810_07803_amd import hrlb
 
     Qx, Qy, nx = 8, 12, 100
-    say(f"[tiling] Qx={Qx} Qy={Qy} nx={nx}, tile_vpt in divisors of Qy")
+    say(f"[tiling] Qx={Qx} Qy={Qy} nx={nx} precision={precision}, tile_vpt in divisors of Qy")
     _, orc = make_pair(Qx, Qy, nx, delta=0.7, uw=0.25, stretch_A=0.9)
     phi, chi = orc.init_state()
     orc.step(phi, chi, 12)
     q = hrlb.Quadrature(Qx, Qy)
     for vpt, lanes in ((1, 1), (2, 2), (3, 4), (4, 8), (6, 16), (12, 0)):
         c = hrlb.Case(q, hrlb.make_params(delta=0.7, uw=0.25, ncell=nx, stretch_A=0.9, dt=orc.dt, tile_vpt=vpt,
-                                          cell_lanes=lanes))
+                                          cell_lanes=lanes, precision=precision, rounding=rounding, seed=3))
         c.step(12)
         st = c.get_state()
         e = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
         ef = field_errs(c.moments()[0], orc.moments(phi, chi))
         say(f"   vpt={vpt} lanes={lanes}: state err {e:.2e}, field err {ef.max():.2e}")
-        assert e < 1e-12 and np.all(ef < 1e-12)
+        assert e < tol and np.all(ef < tol)
 
 
 def test_autotuner_returns_an_admissible_tiling():
