@@ -305,8 +305,9 @@ def main(argv=None):
                     help="steps per captured HIP graph (0 launches every kernel directly)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
-    ap.add_argument("--streams", type=int, default=2,
-                    help="parts of the batch advanced on separate streams (1-4)")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="parts of the batch advanced on separate streams (1-4; 3 is the library's default for "
+                    "batches of at least 2e7 units)")
     ap.add_argument("--cell-lanes", type=int, default=0, help="lanes per cell of the per-cell kernel for every "
                     "instance (0 = each instance's automatic choice)")
     ap.add_argument("--tile-vpt", type=int, default=0, help="velocities per stage-kernel row for every instance "

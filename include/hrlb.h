@@ -196,8 +196,8 @@ const char *hrlb_last_error(void);
  * kernel launches.  The cases are split into parts of about equal work (velocities x cells); each
  * part is advanced by one persistent launch per stage and kernel on a stream of its own, forked
  * from and joined back into the cases' stream, so that one part's per-cell kernel overlaps another
- * part's stage kernel.  Two parts by default for batches of at least 3e7 cell-velocity units, one
- * part below (measured faster on MI355X).  Each case keeps its own
+ * part's stage kernel.  Three parts by default for batches of at least 2e7 cell-velocity units,
+ * one part below (measured faster on MI355X).  Each case keeps its own
  * workspace and results; a case's numbers are the same alone, in any batch and in any split.  All
  * cases must share one stream and one precision.  The batch needs its own device workspace for
  * descriptors and tile lists (sized for any split into 1 to 4 parts). */

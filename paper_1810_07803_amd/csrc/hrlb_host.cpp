@@ -952,7 +952,8 @@ extern "C" hrlb_status hrlb_set_state(hrlb_case* c, const double* host_state)
 // batches
 namespace {
 constexpr int kMaxBatchParts = 4;
-constexpr double kSplitUnits = 3e7;  // cell-velocity units from which a batch is split over two streams
+constexpr double kSplitUnits = 2e7;  // cell-velocity units from which a batch is split over kSplitParts streams
+constexpr int kSplitParts = 3;
 
 // cases of a batch split into n parts of about equal work (units = velocities x cells): largest first
 // onto the least loaded part; each part keeps its cases in ascending order
@@ -1165,12 +1166,14 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
         HIP_TRY(hrlbk_cell(b->fp32, P.d_descs, P.d_cells, P.ncellblocks, 0, FLAG_FIELDS, b->shmem, b->stream));
         HIP_TRY(hrlbk_finalize(P.d_descs, (int)P.idx.size(), 0, b->stream));
     }
-    // two parts on two streams for large batches: one part's per-cell kernel overlaps the other's
-    // stage kernel.  Measured on MI355X: +8% at 5.2e7 units, -16% at 1e7 units (the parts' launches
-    // then compete for the chip), hence one part below kSplitUnits
+    // three parts on three streams for large batches: one part's per-cell kernel overlaps another's
+    // stage kernel.  Measured on MI355X (512-instance FP32 batches, one box): 1 / 2 / 3 / 4 parts
+    // give 4.91 / 5.18 / 5.30 / 5.15e10 updates/s at 5.2e7 units and 4.23 / 4.33 / 4.75 / 4.72e10
+    // at 2.6e7 units (half channel); at 1e7 units two parts were 16% slower than one (the parts'
+    // launches then compete for the chip), hence one part below kSplitUnits
     double units = 0.0;
     for (int i = 0; i < n_cases; ++i) units += (double)cases[i]->nv * cases[i]->p.n_cells;
-    st = batch_build_parts(b.get(), (n_cases >= 2 && units >= kSplitUnits) ? 2 : 1);
+    st = batch_build_parts(b.get(), units >= kSplitUnits ? std::min(kSplitParts, n_cases) : 1);
     if (st != HRLB_OK) return st;
     for (int i = 0; i < n_cases; ++i) cases[i]->needs_analyze = false;
     *out = b.release();
