@@ -24,13 +24,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
-# Batch workloads run the long-row plan: each instance asks for rows of tile_vpt = the largest
-# divisor of Q_y up to 16 that still fills a group's 16 rows (the library's default rows hold at most
-# 8 velocities).  With ~4,450 tiles per launch the longer rows spread the per-tile work over more
-# velocities; the serving loop's smaller batches keep the default, which fills the GPU with more tiles.
+# Batch workloads run the batch plan: each instance asks for rows of tile_vpt = the largest divisor
+# of Q_y up to 16 that still fills a group's 16 rows (the library's default rows hold at most 8
+# velocities), and for one lane per cell in the per-cell kernel (the default is two).  With
+# thousands of tiles and hundreds of thousands of cells per launch, longer rows spread the per-tile
+# work over more velocities and single lanes halve the per-cell blocks; the serving loop's smaller
+# batches keep the defaults, which fill the GPU with more tiles and blocks.
 WORKLOADS = {
-    "couette_batch512_ragged_fp32": dict(kind="batch", precision=1, rounding=1, rows="long"),
-    "couette_batch512_ragged_fp64": dict(kind="batch", precision=0, rounding=0, rows="long"),
+    "couette_batch512_ragged_fp32": dict(kind="batch", precision=1, rounding=1, rows="long", lanes=1),
+    "couette_batch512_ragged_fp64": dict(kind="batch", precision=0, rounding=0, rows="long", lanes=1),
     "couette_nx512_q16x8_fp64": dict(kind="single", name="couette_nx512_q16x8", precision=0, rounding=0),
     # the plain method in FP64, one instance, run to a residual below 1e-10: time to steady
     "couette_nx32_q4x4_fp64_steady": dict(kind="steady", name="couette_nx32_q4x4_fp64", precision=0, rounding=0,
@@ -40,7 +42,8 @@ WORKLOADS = {
     "couette_nx2048_q80x20_fp64": dict(kind="single", name="couette_nx2048_q80x20", precision=0, rounding=0),
     # the same flows as their right halves (point symmetry of Sec. II): n_cells/2 cells per instance,
     # one diffuse wall, half the updates per step
-    "couette_batch512_ragged_half_fp32": dict(kind="batch", precision=1, rounding=1, half=True, rows="long"),
+    "couette_batch512_ragged_half_fp32": dict(kind="batch", precision=1, rounding=1, half=True, rows="long",
+                                              lanes=1),
     "couette_nx512_q16x8_half_fp32": dict(kind="single", name="couette_nx512_q16x8", precision=1, rounding=1,
                                           half=True),
     # serving: 64 solves drawn like the ragged batch with Nx up to 2048 (seed 1), Poisson arrivals at
@@ -309,7 +312,7 @@ def main(argv=None):
                     help="parts of the batch advanced on separate streams (1-4; 3 is the library's default for "
                     "batches of at least 2e7 units)")
     ap.add_argument("--cell-lanes", type=int, default=0, help="lanes per cell of the per-cell kernel for every "
-                    "instance (0 = each instance's automatic choice)")
+                    "instance (0 = the workload's plan: 1 for the batches, else each instance's automatic choice)")
     ap.add_argument("--tile-vpt", type=int, default=0, help="velocities per stage-kernel row for every instance "
                     "whose Qy it divides (0 = automatic)")
     ap.add_argument("--rows", choices=("default", "long"), default=None,
@@ -339,8 +342,9 @@ def main(argv=None):
     insts = _instances(spec)
     print(f"# building {len(insts)} instance(s) of {args.workload}", file=sys.stderr, flush=True)
     rows = args.rows or spec.get("rows", "default")
+    lanes = args.cell_lanes if args.cell_lanes > 0 else spec.get("lanes", 0)
     quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune, tile_vpt=args.tile_vpt,
-                                        cell_lanes=args.cell_lanes, rows=rows)
+                                        cell_lanes=lanes, rows=rows)
     units = sum(c.nv * c.ncell for c in cases)
     batch.set_graph_steps(args.graph_steps)
     batch.set_streams(args.streams)
@@ -409,7 +413,7 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": args.workload, "instances": len(cases), "units_per_step": units,
                    "half_channel": bool(spec.get("half")),
-                   "graph_steps": args.graph_steps, "streams": args.streams, "rows": rows,
+                   "graph_steps": args.graph_steps, "streams": args.streams, "rows": rows, "cell_lanes": lanes,
                    "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
                    "parallelism": "single GPU, instances batched per launch"},
         "wall_s_timed": wall,
