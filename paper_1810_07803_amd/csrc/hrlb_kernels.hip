@@ -18,7 +18,9 @@
 // one velocity and reconstructs their 5 faces from a 12-cell window (the right face is also the
 // next thread's left face; recomputing it costs less than fetching it: a per-tile pre-pass that
 // read the tile-edge cells once more cost 20% extra HBM reads).  A block covers 64 cells x 16
-// velocity rows; the tile's cell tables (moments, equilibria) are staged in LDS.
+// velocity rows; the tile's cell tables (moments, equilibria) are staged in LDS.  With FP32 storage
+// each wave's loads for its next velocity go straight from the buffer unit into LDS while it
+// computes the current one.
 #include "hrlb_internal.h"
 
 #include <map>
@@ -290,8 +292,9 @@ __device__ __forceinline__ void read_slots(uint32_t la, f4v (&t)[kPfSlots])
 // Wait until no vector-memory operation of the wave is outstanding.
 __device__ __forceinline__ void vm_drain() { __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// moments reduced per LDS pass of the stage kernel's epilogue: 2 for FP32 storage (the prefetch
-// buffers take the rest of the LDS share of a block), 4 for FP64
+// moments reduced per pass of the stage kernel's epilogue in the dynamic LDS: 2 for FP32 storage
+// (the block's LDS share also holds the prefetch buffers; only the analysis kernel reduces there,
+// the step kernels reduce 4 per pass in their drained prefetch buffers), 4 for FP64
 __host__ __device__ constexpr int moments_per_pass(size_t elem) { return elem == 4 ? 2 : kMomPerPass; }
 
 // The window of a thread owning cells s0..s0+3 is w[m] = cell s0 - 4 + m, m = 0..11; its faces
