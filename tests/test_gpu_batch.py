@@ -21,6 +21,37 @@ def _cases(precision, rounding):
 
 
 @pytest.mark.parametrize("precision,rounding", [(0, 0), (1, 1)])
+def test_batch_plan_equals_alone_bitwise(precision, rounding):
+    # the benchmark batches' plan (rows of the largest divisor of Q_y up to 16, one lane per cell),
+    # requested per case: each case keeps its bits alone and in a batch split over three streams
+    import bench
+    from paper_1810_07803_amd import hrlb
+
+    def cases():
+        out = []
+        for k, (Qx, Qy, nx, delta, uw) in enumerate(SHAPES):
+            q = hrlb.Quadrature(Qx, Qy)
+            c = hrlb.Case(q, hrlb.make_params(delta=delta, uw=uw, ncell=nx, stretch_A=0.9, precision=precision,
+                                              rounding=rounding, seed=200 + k, tile_vpt=bench.long_row_vpt(Qx, Qy),
+                                              cell_lanes=1))
+            c._quad_ref = q
+            out.append(c)
+        return out
+
+    say(f"[batch] batch plan alone vs mix, precision={precision} rounding={rounding}")
+    alone = cases()
+    for c in alone:
+        c.step(25)
+    mixed = cases()
+    b = hrlb.Batch(mixed)
+    b.set_streams(3)
+    b.step(25)
+    for a, m in zip(alone, mixed):
+        np.testing.assert_array_equal(a.get_state(), m.get_state())
+        np.testing.assert_array_equal(a.moments()[0], m.moments()[0])
+
+
+@pytest.mark.parametrize("precision,rounding", [(0, 0), (1, 1)])
 def test_batch_equals_alone_bitwise(precision, rounding):
     from paper_1810_07803_amd import hrlb
 
@@ -83,8 +114,10 @@ def test_batch_poll_reports_residual_and_pxy():
 
 @pytest.mark.parametrize("precision,rounding,tol", [(1, 1, 1e-5), (0, 0, 1e-12)])
 def test_full_ragged_batch_sampled_against_oracle(precision, rounding, tol):
-    """The 512-instance ragged workload (seed 0), launched as one batch; three sampled instances are
-    re-run alone by the oracle from the same state and compared element by element."""
+    """The 512-instance ragged workload (seed 0), launched as one batch in the benchmark's
+    configuration (its batch plan: long rows and one lane per cell; three streams); three sampled
+    instances are re-run alone by the oracle from the same state and compared element by element."""
+    import bench
     from paper_1810_07803_amd import hrlb
 
     draws = batch_draws(512, seed=0)
@@ -93,7 +126,8 @@ def test_full_ragged_batch_sampled_against_oracle(precision, rounding, tol):
     for d in draws:
         q = hrlb.Quadrature(d["Qx"], d["Qy"])
         p = hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
-                             omega=d["omega"], precision=precision, rounding=rounding, seed=d["seed"])
+                             omega=d["omega"], precision=precision, rounding=rounding, seed=d["seed"],
+                             tile_vpt=bench.long_row_vpt(d["Qx"], d["Qy"]), cell_lanes=1)
         c = hrlb.Case(q, p)
         c._quad_ref = q
         cases.append(c)
