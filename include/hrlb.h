@@ -47,8 +47,14 @@ typedef enum {
     HRLB_E_INVALID = -1,    /* an argument is out of range or inconsistent             */
     HRLB_E_NOMEM = -2,      /* workspace too small, or host allocation failed          */
     HRLB_E_DEVICE = -3,     /* a HIP runtime call failed                               */
-    HRLB_E_DIVERGED = -4    /* NaN/Inf in the residual; the state is not meaningful      */
+    HRLB_E_DIVERGED = -4,   /* NaN/Inf in the residual; the state is not meaningful      */
+    HRLB_E_RANGE = -5       /* a cell left the band in which the truncated equilibrium of eq. (gx) is
+                             * evaluated to 2e-13 (0.3 <= T/T_w <= 2.4, |u_x| <= sqrt(T_w)); the state
+                             * stays readable, but its accuracy is no longer the stated one        */
 } hrlb_status;
+
+/* bits of hrlb_case_flags */
+enum { HRLB_FLAG_NONFINITE = 1u, HRLB_FLAG_RANGE = 2u };
 
 enum { HRLB_FP64 = 0, HRLB_FP32_STORE_FP64_MOM = 1 };
 enum { HRLB_ROUND_NEAREST = 0, HRLB_ROUND_STOCHASTIC = 1 };
@@ -73,8 +79,11 @@ hrlb_status hrlb_quadrature_nodes(const hrlb_quad *q, double *px, double *wx, do
 
 typedef struct {
     double delta;     /* rarefaction parameter, eq. (delta); 0 selects collisionless flow      */
-    double u_w;       /* wall speed along y (left wall -u_w, right wall +u_w), |u_w| <= 2     */
-    double T_w;       /* wall temperature (> 0); the units assume T_w = 1 but any value works  */
+    double u_w;       /* wall speed along y (left wall -u_w, right wall +u_w), |u_w| <= 2 sqrt(T_w) */
+    double T_w;       /* wall temperature (> 0) in the units of p0^2/(m K_B): the velocity set is  */
+                      /* fixed by p0 = 1, and eq. (gx) is evaluated with an auxiliary rule scaled */
+                      /* to T_w, verified for cells with 0.3 <= T/T_w <= 2.4 and |u_x| <= sqrt(T_w) */
+                      /* (HRLB_E_RANGE / HRLB_FLAG_RANGE outside)                                  */
     double Pr;        /* Prandtl number of the Shakhov model, > 0                             */
     double omega;     /* viscosity index of eq. (mu): mu ~ T^omega                             */
     int n_cells;      /* cells across the channel (its right half when half_channel is set):    */
@@ -155,8 +164,9 @@ hrlb_status hrlb_tune_plan(const hrlb_quad *q, const hrlb_case_params *p, void *
 
 /* Runs blocks of check_every steps until the stop criterion drops below tol
  * (HRLB_STOP_RESIDUAL: the residual above; HRLB_STOP_PXY: the relative drift rate of the
- * J-weighted mean P_xy between checks), NaN/Inf appears (HRLB_E_DIVERGED) or max_steps is
- * reached (HRLB_NOT_CONVERGED).  Synchronous: returns when the decision is made. */
+ * J-weighted mean P_xy between checks), NaN/Inf appears (HRLB_E_DIVERGED), a cell leaves the
+ * verified band of eq. (gx) (HRLB_E_RANGE, checked at every check) or max_steps is reached
+ * (HRLB_NOT_CONVERGED).  Synchronous: returns when the decision is made. */
 hrlb_status hrlb_run_to_steady(hrlb_case *c, double tol, long max_steps, int check_every, int stop_rule,
                                hrlb_steady_info *info);
 
@@ -184,6 +194,12 @@ hrlb_status hrlb_average_read(hrlb_case *c, double *fields, double *Pi, long *st
  * resumes from a checkpoint or starts from a given state. */
 hrlb_status hrlb_get_state(hrlb_case *c, double *host_state);
 hrlb_status hrlb_set_state(hrlb_case *c, const double *host_state);
+
+/* Synchronous: the sticky condition bits of the case (HRLB_FLAG_NONFINITE: a non-finite value met at
+ * a check; HRLB_FLAG_RANGE: since its creation some cell's temperature or normal velocity left the
+ * band 0.3 <= T/T_w <= 2.4, |u_x| <= sqrt(T_w) in which eq. (gx) is evaluated to 2e-13; the per-cell
+ * kernel sets it at every stage, so it covers steps taken with hrlb_step too). */
+hrlb_status hrlb_case_flags(hrlb_case *c, unsigned *flags);
 
 /* Time step in use and the number of velocities / cells of the case. */
 hrlb_status hrlb_case_info(const hrlb_case *c, double *dt, int *n_vel, int *n_cells, long *steps_done);
@@ -262,7 +278,7 @@ enum { HRLB_REQ_WAITING = 0, HRLB_REQ_ACTIVE = 1, HRLB_REQ_DONE = 2, HRLB_REQ_FA
 typedef struct {
     int state;          /* HRLB_REQ_*                                                         */
     int status;         /* DONE: HRLB_OK (stop rule met) or HRLB_NOT_CONVERGED (max_steps);    */
-                        /* FAILED: the error (HRLB_E_DIVERGED, HRLB_E_DEVICE, ...)            */
+                        /* FAILED: the error (HRLB_E_DIVERGED, HRLB_E_RANGE, HRLB_E_DEVICE...) */
     long steps;         /* steps taken                                                         */
     double residual, pxy_drift, Pi, sim_time, mass_drift;  /* as hrlb_steady_info/hrlb_moments */
     double t_arrival, t_admit, t_done;                      /* server clock; -1 if not reached */

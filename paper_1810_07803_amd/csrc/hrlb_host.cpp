@@ -82,6 +82,9 @@ extern "C" hrlb_status hrlb_init_quadrature(int Qx, int Nx_order, int Qy, int Ny
     }
     std::vector<long double> an, aw;
     gauss_from_recurrence(hr, kAux, an, aw);
+    q->hr = hr;
+    q->auxZl = an;
+    q->auxWl = aw;
     q->auxZ.resize(kAux);
     q->auxW.resize(kAux);
     q->hZ.assign((size_t)(Nx_order + 1) * kAux, 0.0);
@@ -92,6 +95,8 @@ extern "C" hrlb_status hrlb_init_quadrature(int Qx, int Nx_order, int Qy, int Ny
         for (int l = 0; l <= Nx_order; ++l) q->hZ[(size_t)l * kAux + k] = (double)hv[l];
     }
     gauss_from_recurrence(hr, kAux2, an, aw);
+    q->auxZ2l = an;
+    q->auxW2l = aw;
     q->auxZ2.resize(kAux2);
     q->auxW2.resize(kAux2);
     q->hZ2.assign((size_t)(Nx_order + 1) * kAux2, 0.0);
@@ -146,7 +151,10 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
     if (!(p->delta >= 0.0) || !std::isfinite(p->delta)) return fail(HRLB_E_INVALID, "delta must be >= 0");
     if (!(p->T_w > 0.0) || !std::isfinite(p->T_w)) return fail(HRLB_E_INVALID, "T_w must be > 0");
     if (!(p->Pr > 0.0) || !std::isfinite(p->Pr)) return fail(HRLB_E_INVALID, "Pr must be > 0");
-    if (!std::isfinite(p->u_w) || std::fabs(p->u_w) > 2.0) return fail(HRLB_E_INVALID, "|u_w| must be <= 2");
+    // |u_w| <= 2 sqrt(T_w): the viscous heating of Couette flow stays below the collisionless value
+    // T/T_w = 1 + u_w^2/(3 T_w) <= 2.33, inside the band where eq. (gx) is evaluated to 2e-13
+    if (!std::isfinite(p->u_w) || std::fabs(p->u_w) > 2.0 * std::sqrt(p->T_w))
+        return fail(HRLB_E_INVALID, "|u_w| must be <= 2 sqrt(T_w)");
     if (!std::isfinite(p->omega) || p->omega < 0.0 || p->omega > 2.0) return fail(HRLB_E_INVALID, "omega outside [0,2]");
     if (p->n_cells < 8 || p->n_cells > 65536 || p->n_cells % kStrip != 0)
         return fail(HRLB_E_INVALID, "n_cells=%d must be a multiple of %d in [8, 65536]", p->n_cells, kStrip);
@@ -258,8 +266,9 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
         L.f[k] = off;
         off = align256(off + es * 2 * (size_t)nv * nx);
     }
-    L.cell = off;
-    off = align256(off + es * (size_t)(kNSc + 2 * qx + qy) * nx);
+    L.cell = off;  // FP64 scalars [kNSc][nx], then the storage-precision table [g_slots][nx]
+    L.cell_g = align256(sizeof(double) * kNSc * nx);
+    off = align256(off + L.cell_g + es * (size_t)g_slots(qx, qy) * nx);
     L.fields = off;
     off = align256(off + sizeof(double) * kNFields * nx);
     L.avg = off;
@@ -450,12 +459,25 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     std::copy(q->wx.begin(), q->wx.end(), tab.begin() + L.t_wx);
     std::copy(q->wy.begin(), q->wy.end(), tab.begin() + L.t_wy);
     std::copy(q->hz.begin(), q->hz.end(), tab.begin() + L.t_hz);
-    std::copy(q->auxZ.begin(), q->auxZ.end(), tab.begin() + L.t_az);
-    std::copy(q->auxW.begin(), q->auxW.end(), tab.begin() + L.t_aw);
-    std::copy(q->hZ.begin(), q->hZ.end(), tab.begin() + L.t_hZ);
-    std::copy(q->auxZ2.begin(), q->auxZ2.end(), tab.begin() + L.t_az2);
-    std::copy(q->auxW2.begin(), q->auxW2.end(), tab.begin() + L.t_aw2);
-    std::copy(q->hZ2.begin(), q->hZ2.end(), tab.begin() + L.t_hZ2);
+    // auxiliary rules of eq. (gx) scaled to the wall temperature: nodes and weights times sqrt(T_w), the
+    // orthonormal h_l at the scaled nodes (extended precision, rounded once)
+    {
+        const long double sw = std::sqrt((long double)p->T_w);
+        std::vector<long double> hv(q->nxo + 1);
+        auto scaled = [&](const std::vector<long double>& Z, const std::vector<long double>& W, size_t tz, size_t tw,
+                          size_t th) {
+            const int K = (int)Z.size();
+            for (int k = 0; k < K; ++k) {
+                const long double z = sw * Z[k];
+                tab[tz + k] = (double)z;
+                tab[tw + k] = (double)(sw * W[k]);
+                orthonormal_values(q->hr, q->nxo, z, hv.data());
+                for (int l = 0; l <= q->nxo; ++l) tab[th + (size_t)l * K + k] = (double)hv[l];
+            }
+        };
+        scaled(q->auxZl, q->auxWl, L.t_az, L.t_aw, L.t_hZ);
+        scaled(q->auxZ2l, q->auxW2l, L.t_az2, L.t_aw2, L.t_hZ2);
+    }
     std::copy(q->he.begin(), q->he.end(), tab.begin() + L.t_he);
     for (int s = 0; s < nx; ++s) {
         tab[L.t_ijd + s] = 1.0 / c->jdeta[s];
@@ -471,8 +493,8 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
             tab[L.t_vOm + k] = std::log(p->visc_mu[k + 1] / p->visc_mu[k]) / std::log(p->visc_T[k + 1] / p->visc_T[k]);
     }
     std::vector<double> gxw(2 * qx), gyl(qy), gyr(qy), gy0(qy);
-    eval_gx(qx, q->nxo, q->wx.data(), q->hz.data(), q->auxZ.data(), q->auxW.data(), q->hZ.data(), 0.0, p->T_w,
-            gxw.data());
+    eval_gx(qx, q->nxo, q->wx.data(), q->hz.data(), tab.data() + L.t_az, tab.data() + L.t_aw, tab.data() + L.t_hZ,
+            p->T_w, 0.0, p->T_w, gxw.data());
     eval_gy(qy, q->nyo, q->wy.data(), q->he.data(), -p->u_w, p->T_w, gyl.data());
     eval_gy(qy, q->nyo, q->wy.data(), q->he.data(), +p->u_w, p->T_w, gyr.data());
     eval_gy(qy, q->nyo, q->wy.data(), q->he.data(), 0.0, p->T_w, gy0.data());
@@ -571,7 +593,8 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     for (int s = 0; s < nx; ++s) D.jsum += c->jdeta[s];
     char* ws = c->ws;
     for (int k = 0; k < 3; ++k) D.f[k] = ws + L.f[k];
-    D.cell = ws + L.cell;
+    D.sc = (double*)(ws + L.cell);
+    D.cell = ws + L.cell + L.cell_g;
     D.fields = (double*)(ws + L.fields);
     D.avg = (double*)(ws + L.avg);
     D.mom_part = (double*)(ws + L.mom);
@@ -662,6 +685,23 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
 }
 
 extern "C" void hrlb_free_case(hrlb_case* c) { delete c; }
+
+void hrlb::range_message(long steps)
+{
+    fail(HRLB_E_RANGE,
+         "a cell left %.1f <= T/T_w <= %.1f, |u_x| <= %.1f sqrt(T_w), where eq. (gx) is evaluated to 2e-13 "
+         "(after %ld steps)", kAuxTlo, kAuxThi, kAuxUmax, steps);
+}
+
+extern "C" hrlb_status hrlb_case_flags(hrlb_case* c, unsigned* flags)
+{
+    if (!c || !flags) return fail(HRLB_E_INVALID, "NULL argument");
+    double dy[kNDyn];
+    HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *flags = (dy[DY_FLAGS] != 0.0 ? HRLB_FLAG_NONFINITE : 0u) | (dy[DY_RANGE] != 0.0 ? HRLB_FLAG_RANGE : 0u);
+    return HRLB_OK;
+}
 
 extern "C" hrlb_status hrlb_case_info(const hrlb_case* c, double* dt, int* n_vel, int* n_cells, long* steps_done)
 {
@@ -779,6 +819,7 @@ hrlb_status hrlb::steady_update(SteadyTrack& t, const double* dy, long n, double
     t.res = std::sqrt(dy[DY_RES_NUM]) / (dt * std::sqrt(dy[DY_RES_DEN]));
     const double pxy = dy[DY_PXY_MEAN];
     if (!std::isfinite(t.res) || !std::isfinite(pxy) || dy[DY_FLAGS] != 0.0) return HRLB_E_DIVERGED;
+    if (dy[DY_RANGE] != 0.0) return HRLB_E_RANGE;
     if (t.have_prev) t.drift = std::fabs(pxy - t.pxy_prev) / (n * dt * std::max(std::fabs(pxy), 1e-300));
     t.have_prev = true;
     t.pxy_prev = pxy;
@@ -813,6 +854,7 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         if (v != HRLB_NOT_CONVERGED) {
             verdict = v;
             if (v == HRLB_E_DIVERGED) fail(HRLB_E_DIVERGED, "non-finite residual after %ld steps", c->steps_done);
+            if (v == HRLB_E_RANGE) range_message(c->steps_done);
             break;
         }
     }

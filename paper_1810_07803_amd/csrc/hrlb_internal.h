@@ -27,12 +27,19 @@ static_assert(kCellThreads == kPlanCellThreads, "block size of the per-cell kern
 constexpr int kMaxCellLanes = 16;             // lanes per cell of the per-cell kernel (4, 8 or 16)
 
 // auxiliary half-range Gauss rule used to project the Maxwellian on the half-range Hermite
-// basis (well-conditioned replacement of the monomial-moment form of eq. gx)
+// basis (well-conditioned replacement of the monomial-moment form of eq. gx).  The rule of a case is
+// the standard one scaled to the wall temperature: nodes sqrt(T_w) Z_k, weights sqrt(T_w) W_k, i.e.
+// the Gauss rule of the weight exp(-p^2/(2 T_w)), so that its accuracy depends on T/T_w and
+// u/sqrt(T_w) only.  Measured against the binary128 form of eq. gx (N_x = 10, Q_x = 16 and 80,
+// T_w = 1 and 3), relative to max_i |g_x,i|: at most 4e-15 for 0.3 <= T/T_w <= 2 and
+// |u_x| <= 2 sqrt(T_w); 2e-13 at T/T_w = 2.4 with |u_x| <= sqrt(T_w); 4e-11 at T/T_w = 3.
 constexpr int kAux = 48;
-// A second, 24-node rule serves the cells near the wall equilibrium, where it is as accurate: its
-// projections of g/omega on h_0..h_10 differ from the exact integrals by at most 3.3e-16 relative
-// for 0.7 <= T <= 1.1 and |u| <= 1 (2e-14 at T = 1.25, u = 1; 9e-10 at T = 1.6, u = 0.5, where the
-// 48-node rule stays below 2e-15 up to T = 2), so it is used for 0.7 <= T <= 1.15, |u_x| <= 0.75.
+// the band in which the 48-node projection is verified to 2e-13: a cell outside it raises DY_RANGE
+constexpr double kAuxTlo = 0.3, kAuxThi = 2.4, kAuxUmax = 1.0;
+// A second, 24-node rule (scaled the same way) serves the cells near the wall equilibrium, where it
+// is as accurate: measured the same way, at most 3e-15 for 0.7 <= T/T_w <= 1.15 and
+// |u_x| <= 0.75 sqrt(T_w) (T_w = 1 and 3), but 3e-13 at T/T_w = 1.5, u = 0 and 1e-9 at T/T_w = 1.5,
+// u = sqrt(T_w); so it is used for 0.7 <= T/T_w <= 1.15, |u_x| <= 0.75 sqrt(T_w).
 constexpr int kAux2 = 24;
 constexpr double kAux2Tlo = 0.7, kAux2Thi = 1.15, kAux2Umax = 0.75;
 
@@ -40,8 +47,13 @@ constexpr int kMaxQx = 128, kMaxNx = 16, kMaxQy = 64;
 constexpr int kMaxViscTable = 256;  // rows of a tabulated transport law
 constexpr int kNMom = 11;  // raw moment accumulators per cell
 
-// per-cell scalars stored in the storage precision, slot-major [slot][nx]
-enum : int { SC_UX = 0, SC_UY, SC_T, SC_INVTAU, SC_AS, SC_AS5T, SC_QX, SC_QY, SC_IJD, kNSc };
+// per-cell scalars of the collision, FP64 for both storage precisions (the Shakhov factor's
+// temperature and heat-flux terms are evaluated in FP64), slot-major [slot][nx]
+enum : int { SC_UX = 0, SC_UY, SC_T, SC_INVTAU, SC_AS, SC_AS5T, SC_QX, SC_QY, kNSc };
+// per-cell table in the storage precision, slot-major [slot][nx]: 1/(J_s deta), then g_x at the
+// 2 Q_x nodes, then g_y at the Q_y nodes
+constexpr int kGIjd = 0, kGx0 = 1;
+__host__ __device__ constexpr int g_slots(int qx, int qy) { return 1 + 2 * qx + qy; }
 // FP64 output fields [field][nx]
 enum : int { F_N = 0, F_UX, F_UY, F_T, F_PXX, F_PXY, F_PYY, F_TZZ, F_QX, F_QY, kNFields };
 // mutable per-instance FP64 scalars
@@ -58,6 +70,7 @@ enum : int {
     DY_FLAGS,     // nonzero if a non-finite value was met
     DY_AVG_ON,    // nonzero: every completed step adds the fields to the running sums
     DY_AVG_STEPS, // steps summed since the last start
+    DY_RANGE,     // nonzero once a cell's T/T_w or u_x/sqrt(T_w) left the verified band of eq. gx
     kNDyn = 16
 };
 
@@ -90,7 +103,8 @@ struct InstDesc {
     double jsum;         // sum_s J_s deta (channel width in x)
     // device pointers (all inside the case workspace)
     void* f[3];          // state buffers, each [2][nv][nx] in the storage precision
-    void* cell;          // [kNSc + 2 qx + qy][nx] storage precision
+    double* sc;          // [kNSc][nx] FP64 per-cell scalars of the collision
+    void* cell;          // [g_slots(qx, qy)][nx] storage precision: 1/(J deta), g_x, g_y
     double* fields;      // [kNFields][nx]
     double* avg;         // [kNFields][nx] running sums of the fields over completed steps
     double* mom_part;    // [ngroups][kNMom][nx]
@@ -101,8 +115,8 @@ struct InstDesc {
     const double* wx;    // [qx]
     const double* wy;    // [qy]
     const double* hz;    // [(nxo+1)][qx]   orthonormal half-range polynomials at the nodes
-    const double* auxZ;  // [kAux]
-    const double* auxW;  // [kAux]
+    const double* auxZ;  // [kAux]  nodes of the auxiliary rule, scaled by sqrt(T_w)
+    const double* auxW;  // [kAux]  its weights, scaled by sqrt(T_w)
     const double* hZ;    // [(nxo+1)][kAux] the same polynomials at the auxiliary nodes
     const double* auxZ2; // [kAux2] the smaller auxiliary rule
     const double* auxW2; // [kAux2]
@@ -179,11 +193,12 @@ __host__ __device__ inline void visc_lookup(const double* T, const double* mu, c
 
 // ---- equilibrium truncations (host and device) ------------------------------------------
 // g_{x,i}(u,T), i < 2 qx, following eq. gx as a projection: g_{x,i} = w_i sum_l h_l(z_i) I_l with
-// I_l = int_0^inf g(p; sigma_i u, T) h_l(p) dp evaluated with the auxiliary half-range rule,
-// where g/omega = exp(p^2/2 - (p-u)^2/(2T))/sqrt(T).
+// I_l = int_0^inf g(p; sigma_i u, T) h_l(p) dp evaluated with the auxiliary half-range rule scaled to
+// T_w (nodes Z, weights W of the weight exp(-p^2/(2 T_w))/sqrt(2 pi)), on which
+// g/omega_w = exp(p^2/(2 T_w) - (p-u)^2/(2T))/sqrt(T).
 __host__ __device__ inline void eval_gx(int qx, int nxo, const double* wx, const double* hz,
                                         const double* auxZ, const double* auxW, const double* hZ,
-                                        double u, double T, double* out)
+                                        double Tw, double u, double T, double* out)
 {
     const double inv2T = 0.5 / T;
     const double rsT = 1.0 / sqrt(T);
@@ -193,7 +208,7 @@ __host__ __device__ inline void eval_gx(int qx, int nxo, const double* wx, const
         for (int l = 0; l <= nxo; ++l) I[l] = 0.0;
         for (int k = 0; k < kAux; ++k) {
             const double Z = auxZ[k];
-            const double e = (Z * Z * (T - 1.0) + 2.0 * Z * us - us * us) * inv2T;
+            const double e = (Z * Z * ((T - Tw) / Tw) + 2.0 * Z * us - us * us) * inv2T;
             const double wk = auxW[k] * exp(e) * rsT;
             for (int l = 0; l <= nxo; ++l) I[l] += wk * hZ[l * kAux + k];
         }

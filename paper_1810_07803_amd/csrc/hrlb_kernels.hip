@@ -339,13 +339,17 @@ struct Win {
     }
 };
 
-// Per-tile staging of the cell tables in LDS: the per-cell scalars, then g_y for every j of the
-// instance, then g_x of the block's 16 rows.  Inside a slot the 64 cells are stored as
-// [4 cells of a thread][16 threads of a row], so that the 16 lanes of a row read 16 consecutive
-// words; slots are kLdsSlot elements apart, which puts the 4 rows of a wave (reading slots one
-// apart for g_x) on disjoint bank ranges.
-__host__ __device__ constexpr int cell_lds_slots(int qy) { return kNSc + qy + kRows; }
+// Per-tile staging of the cell tables in LDS: the FP64 per-cell scalars, then (storage precision)
+// 1/(J deta), g_y for every j of the instance, and g_x of the block's 16 rows.  Inside a slot the 64
+// cells are stored as [4 cells of a thread][16 threads of a row], so that the 16 lanes of a row read
+// 16 consecutive words; slots are kLdsSlot elements apart, which puts the 4 rows of a wave (reading
+// slots one apart for g_x) on disjoint bank ranges.
+__host__ __device__ constexpr int g_lds_slots(int qy) { return 1 + qy + kRows; }
 constexpr int kLdsSlot = kTileCells + kTPR;
+__host__ __device__ constexpr size_t cell_lds_bytes(int qy, size_t es)
+{
+    return sizeof(double) * kNSc * kLdsSlot + es * (size_t)g_lds_slots(qy) * kLdsSlot;
+}
 
 // MODE: kModeAnalyze (no update; partials of the current state f[0], used after set-up or a state
 // upload), kModeStep, kModeResid (a step whose stage 3 also forms the residual partials)
@@ -355,10 +359,12 @@ enum : int { kModeAnalyze = 0, kModeStep = 1, kModeResid = 2 };
 // the next position x + 8 k of its XCD's part of the tile list from the counter ctr[x] until the
 // list is exhausted, so heavy and light tiles balance dynamically.  The last block to finish
 // (counter ctr[8]) clears the counters for the next launch.
-// At least 2 waves per SIMD: without the bound the FP64 variant is allocated past 256 registers
-// (1 wave per SIMD); the FP32 variants fit 3 waves either way.
+// Waves per SIMD: at least 2 (without the bound the FP64 variant is allocated past 256 registers,
+// 1 wave per SIMD); 3 for the FP32 step variant (168 registers, no spill; it needs 172 unbounded, so
+// the FP64 collision would otherwise cost a third of its occupancy).  The residual variant, which
+// runs on checked steps only, keeps 2 rather than spill.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __restrict__ descs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MODE == 1 ? 3 : 2))) void stage_kernel(const InstDesc* __restrict__ descs,
                                                          const TileRef* __restrict__ tiles, int ntiles,
                                                          int stage, unsigned* __restrict__ ctr)
 {
@@ -374,7 +380,8 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
         __shared__ __align__(16) unsigned char s_pf[(kThreads / 64) * kPfWave];
         pfbuf = s_pf;
     }
-    T* lds_cell = reinterpret_cast<T*>(smem);
+    double* const lds_sc = reinterpret_cast<double*>(smem);
+    T* const lds_g = reinterpret_cast<T*>(smem + sizeof(double) * kNSc * kLdsSlot);
     __shared__ double lds_red[kThreads / 64][2];
 
     const int tid = threadIdx.x;
@@ -412,7 +419,6 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
         const __amdgpu_buffer_rsrc_t rin = make_rsrc(D.f[in_idx], state_bytes);
         const double nwl = D.dyn[DY_NWL], nwr = D.dyn[DY_NWR];
         const double Tw = D.Tw;
-        const int nslot = cell_lds_slots(qy);
         // window offsets of the lane: cells s0-4.., s0.., s0+4.. (idle lanes read cells 0..3)
         const int sc = active ? s0 : 0;
         const bool last = s0 + kStrip == nx;
@@ -457,29 +463,40 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
         if constexpr (kDma)
             if (row_on) prefetch(0);
         // per-tile copies of p_y (all j) and of the wall populations of the tile's velocities
-        double* const lds_py = reinterpret_cast<double*>(smem + (size_t)nslot * kLdsSlot * es);
+        double* const lds_py = reinterpret_cast<double*>(smem + cell_lds_bytes(qy, es));
         double* const lds_gw = lds_py + qy;  // [left, right][row][k]
 
         if (!ANALYZE) {
-            // stage the tile's cell tables: scalars, g_y (all j), g_x of each row's node
-            const __amdgpu_buffer_rsrc_t rcell =
-                make_rsrc(D.cell, (uint32_t)(kNSc + 2 * qx + qy) * (uint32_t)nx * es);
-            for (int ch = tid; ch < nslot * (kTileCells / 4); ch += kThreads) {
+            // stage the tile's cell tables: the FP64 scalars; 1/(J deta), g_y (all j) and g_x of each
+            // row's node in the storage precision
+            const __amdgpu_buffer_rsrc_t rsc = make_rsrc(D.sc, (uint32_t)kNSc * (uint32_t)nx * 8u);
+            const __amdgpu_buffer_rsrc_t rg = make_rsrc(D.cell, (uint32_t)g_slots(qx, qy) * (uint32_t)nx * es);
+            const int nsl = kNSc + g_lds_slots(qy);
+            for (int ch = tid; ch < nsl * (kTileCells / 4); ch += kThreads) {
                 const int slot = ch / (kTileCells / 4), q4 = ch % (kTileCells / 4);
-                int src;
-                if (slot < kNSc)
-                    src = slot;
-                else if (slot < kNSc + qy)
-                    src = kNSc + 2 * qx + (slot - kNSc);
-                else {
-                    const int r = slot - kNSc - qy, sg = tr.group * kRows + r;
-                    src = kNSc + (sg < D.nseg ? sg / D.segs_per_line : 0);
-                }
-                T v4[4];
                 const int cell = c0 + 4 * q4;
-                bld4(rcell, ((uint32_t)src * nx + (uint32_t)(cell < nx ? cell : 0)) * es, v4);
+                const uint32_t cc = (uint32_t)(cell < nx ? cell : 0);
+                if (slot < kNSc) {
+                    double v4[4];
+                    bld4(rsc, ((uint32_t)slot * nx + cc) * 8u, v4);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) lds_cell[slot * kLdsSlot + c * kTPR + q4] = v4[c];
+                    for (int c = 0; c < 4; ++c) lds_sc[slot * kLdsSlot + c * kTPR + q4] = v4[c];
+                } else {
+                    const int gs = slot - kNSc;
+                    int src;
+                    if (gs == 0)
+                        src = kGIjd;
+                    else if (gs <= qy)
+                        src = kGx0 + 2 * qx + (gs - 1);
+                    else {
+                        const int r = gs - 1 - qy, sg = tr.group * kRows + r;
+                        src = kGx0 + (sg < D.nseg ? sg / D.segs_per_line : 0);
+                    }
+                    T v4[4];
+                    bld4(rg, ((uint32_t)src * nx + cc) * es, v4);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) lds_g[gs * kLdsSlot + c * kTPR + q4] = v4[c];
+                }
             }
             if constexpr (kDma) {
                 for (int i = tid; i < qy; i += kThreads) lds_py[i] = D.py[i];
@@ -613,7 +630,6 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                     if (!ANALYZE && first) gl = D.gw_l[v];
                     if (!ANALYZE && last) gr = D.gw_r[v];
                 }
-                const T py = (T)pyd;
                 // wall populations (eq. diffuse) of this velocity: only the strips next to a wall use them
                 T phiwl = T(0), chiwl = T(0), phiwr = T(0), chiwr = T(0);
                 if (!ANALYZE && first) {
@@ -690,32 +706,38 @@ __global__ __launch_bounds__(kThreads, 2) void stage_kernel(const InstDesc* __re
                     // an opaque column index keeps the compiler from hoisting the per-cell terms out of
                     // the velocity loop into registers (they stay in LDS; occupancy 3 instead of 2)
                     __asm__ volatile("" : "+v"(lcol));
-                    const T* Lc = lds_cell + lcol;
+                    const double* Ls = lds_sc + lcol;
+                    const T* Lg = lds_g + lcol;
 #pragma unroll
                     for (int c = 0; c < kStrip; ++c) {
                         const T p = P.w[4 + c], x = X.w[4 + c];
-                        const T ux = Lc[SC_UX * kLdsSlot + c * kTPR], uy = Lc[SC_UY * kLdsSlot + c * kTPR];
-                        const T Tt = Lc[SC_T * kLdsSlot + c * kTPR], itau = Lc[SC_INVTAU * kLdsSlot + c * kTPR];
-                        const T AS = Lc[SC_AS * kLdsSlot + c * kTPR], A5 = Lc[SC_AS5T * kLdsSlot + c * kTPR];
-                        const T qxv = Lc[SC_QX * kLdsSlot + c * kTPR], qyv = Lc[SC_QY * kLdsSlot + c * kTPR];
-                        const T ijd = Lc[SC_IJD * kLdsSlot + c * kTPR];
-                        const T gy = Lc[(kNSc + j) * kLdsSlot + c * kTPR];
-                        const T gx = Lc[(kNSc + qy + row) * kLdsSlot + c * kTPR];
-                        // reduced Shakhov collision, Sec. II
-                        const T xx = px - ux, xy = py - uy;
-                        const T x2 = xx * xx + xy * xy;
-                        const T qxi = qxv * xx + qyv * xy;
-                        const T sp = qxi * (A5 * x2 - T(0.8) * AS);
-                        const T sch = qxi * (A5 * x2 - T(0.4) * AS);
-                        const T feq = gx * gy;
-                        const T tp = feq + feq * sp;
-                        const T tc = Tt * (feq + feq * sch);
-                        const T Lp = -px * (Fp[c + 1] - Fp[c]) * ijd + (tp - p) * itau;
-                        const T Lx = -px * (Fc[c + 1] - Fc[c]) * ijd + (tc - x) * itau;
+                        const double ux = Ls[SC_UX * kLdsSlot + c * kTPR], uy = Ls[SC_UY * kLdsSlot + c * kTPR];
+                        const double Tt = Ls[SC_T * kLdsSlot + c * kTPR], itau = Ls[SC_INVTAU * kLdsSlot + c * kTPR];
+                        const double AS = Ls[SC_AS * kLdsSlot + c * kTPR], A5 = Ls[SC_AS5T * kLdsSlot + c * kTPR];
+                        const double qxv = Ls[SC_QX * kLdsSlot + c * kTPR], qyv = Ls[SC_QY * kLdsSlot + c * kTPR];
+                        const T ijd = Lg[kGIjd * kLdsSlot + c * kTPR];
+                        const T gy = Lg[(1 + j) * kLdsSlot + c * kTPR];
+                        const T gx = Lg[(1 + qy + row) * kLdsSlot + c * kTPR];
+                        // reduced Shakhov collision, Sec. II, in FP64: the Shakhov factors S_phi, S_chi
+                        // (temperature and heat-flux terms), the targets phi_eq (1 + S_phi), chi_eq (1 + S_chi)
+                        // (the product of the truncated equilibria is exact in FP64) and their relaxation
+                        const double xx = pxd - ux, xy = pyd - uy;
+                        const double x2 = xx * xx + xy * xy;
+                        const double qxi = qxv * xx + qyv * xy;
+                        const double sp = qxi * (A5 * x2 - 0.8 * AS);
+                        const double sch = qxi * (A5 * x2 - 0.4 * AS);
+                        const double feq = (double)gx * (double)gy;
+                        const double tp = feq + feq * sp;
+                        const double tc = Tt * (feq + feq * sch);
+                        // x-advection in the storage precision: -p_x (F_{s+1/2} - F_{s-1/2}) / (J_s deta)
+                        const T ap = -px * (Fp[c + 1] - Fp[c]) * ijd;
+                        const T ax = -px * (Fc[c + 1] - Fc[c]) * ijd;
+                        const double Lp = (double)ap + (tp - (double)p) * itau;
+                        const double Lx = (double)ax + (tc - (double)x) * itau;
                         // SSP-RK3 stage: out = a f^n + b (f_in + dt L(f_in)), combined in FP64
                         const double fnpd = (double)fnp[c], fncd = (double)fnc[c];
-                        const double ope = ca * fnpd + cb * ((double)p + dtc[c] * (double)Lp);
-                        const double oce = ca * fncd + cb * ((double)x + dtc[c] * (double)Lx);
+                        const double ope = ca * fnpd + cb * ((double)p + dtc[c] * Lp);
+                        const double oce = ca * fncd + cb * ((double)x + dtc[c] * Lx);
                         op[c] = store_round<T>(ope, rounding, rbits[c]);
                         oc[c] = store_round<T>(oce, rounding, rbits[c] >> 16);
                         if (want_res) {
@@ -946,16 +968,18 @@ __device__ __forceinline__ double lane_sum(double x, int lanes)
 // auxiliary rule: lane q of the cell takes nodes k = q, q + L, ...; two nodes per iteration keep two
 // independent exponential chains in flight (one node per iteration for the largest row count, whose
 // accumulators already fill the register budget).  Partial sums in k order, then an xor butterfly.
+// The rule is scaled to T_w (nodes Z of the weight exp(-p^2/(2 T_w))), on which the integrand is
+// exp(Z^2 (T/T_w - 1)/(2T) + Z u/T - u^2/(2T))/sqrt(T) h_l(Z).
 template <int NB>
-__device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, double ux, int K, const double* s_az,
-                                           const double* s_aw, const double* s_hZ, double (&Ip)[NB],
-                                           double (&Im)[NB])
+__device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, double Tw, double ux, int K,
+                                           const double* s_az, const double* s_aw, const double* s_hZ,
+                                           double (&Ip)[NB], double (&Im)[NB])
 {
 #pragma unroll
     for (int l = 0; l < NB; ++l) Ip[l] = Im[l] = 0.0;
     const double inv2T = 0.5 / Tm;
     const double rsT = 1.0 / sqrt(Tm);
-    const double c0 = (Tm - 1.0) * inv2T, c1 = ux * (2.0 * inv2T), c2 = ux * ux * inv2T;
+    const double c0 = ((Tm - Tw) / Tw) * inv2T, c1 = ux * (2.0 * inv2T), c2 = ux * ux * inv2T;
     int k = q;
     for (; NB <= 11 && k + LN < K; k += 2 * LN) {
         const double Z0 = s_az[k], Z1 = s_az[k + LN];
@@ -999,16 +1023,18 @@ __device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, do
 // (pairs on 8 of them, single nodes on the others: both paths in every wave, no faster than the
 // 48-node split), so such plans keep the 48-node rule.
 template <typename T, int NB>
-__device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, double Tm, double ux, bool on, int s,
-                                         int nx, int qxn, const double* s_wx, const double* s_az, const double* s_aw,
-                                         const double* s_hZ, const double* s_az2, const double* s_hz, T* cell)
+__device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, double Tm, double Tw, double ux, bool on,
+                                         int s, int nx, int qxn, const double* s_wx, const double* s_az,
+                                         const double* s_aw, const double* s_hZ, const double* s_az2,
+                                         const double* s_hz, T* cell)
 {
     double Ip[NB], Im[NB];
-    const bool small = uses_aux2(LN) && Tm >= kAux2Tlo && Tm <= kAux2Thi && fabs(ux) <= kAux2Umax;
+    const bool small = uses_aux2(LN) && Tm >= kAux2Tlo * Tw && Tm <= kAux2Thi * Tw &&
+                       fabs(ux) <= kAux2Umax * sqrt(Tw);
     if (small)
-        gx_project<NB>(q, LN, nxo, Tm, ux, kAux2, s_az2, s_az2 + kAux2, s_az2 + 2 * kAux2, Ip, Im);
+        gx_project<NB>(q, LN, nxo, Tm, Tw, ux, kAux2, s_az2, s_az2 + kAux2, s_az2 + 2 * kAux2, Ip, Im);
     else
-        gx_project<NB>(q, LN, nxo, Tm, ux, kAux, s_az, s_aw, s_hZ, Ip, Im);
+        gx_project<NB>(q, LN, nxo, Tm, Tw, ux, kAux, s_az, s_aw, s_hZ, Ip, Im);
     for (int i = q; i < qxn; i += LN) {
         double ap = 0.0, am = 0.0;
 #pragma unroll
@@ -1019,8 +1045,8 @@ __device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, doubl
         }
         const double nw = n * s_wx[i];
         if (on) {
-            cell[(kNSc + i) * nx + s] = (T)(nw * ap);
-            cell[(kNSc + qxn + i) * nx + s] = (T)(nw * am);
+            cell[(kGx0 + i) * nx + s] = (T)(nw * ap);
+            cell[(kGx0 + qxn + i) * nx + s] = (T)(nw * am);
         }
     }
 }
@@ -1043,7 +1069,7 @@ __device__ __forceinline__ void gy_nodes(int q, int LN, int nyo, double uy, doub
         double acc = 0.0;
 #pragma unroll
         for (int l = 0; l < NB; ++l) acc += cl[l] * s_he[l * nqy + j];
-        if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
+        if (on) cell[(kGx0 + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
     }
 }
 
@@ -1062,7 +1088,7 @@ __device__ __forceinline__ void gy_nodes_long(int q, int LN, int nyo, double uy,
             c2 = c1;
             c1 = c;
         }
-        if (on) cell[(kNSc + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
+        if (on) cell[(kGx0 + 2 * qxn + j) * nx + s] = (T)(s_wy[j] * acc);
     }
 }
 
@@ -1178,15 +1204,20 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
             F[F_QX * nx + s] = qx;
             F[F_QY * nx + s] = qy;
         }
-        cell[SC_UX * nx + s] = (T)ux;
-        cell[SC_UY * nx + s] = (T)uy;
-        cell[SC_T * nx + s] = (T)Tm;
-        cell[SC_INVTAU * nx + s] = (T)invtau;
-        cell[SC_AS * nx + s] = (T)As;
-        cell[SC_AS5T * nx + s] = (T)(As / (5.0 * Tm));
-        cell[SC_QX * nx + s] = (T)qx;
-        cell[SC_QY * nx + s] = (T)qy;
-        cell[SC_IJD * nx + s] = (T)D.inv_jdeta[s];
+        double* sc = D.sc;
+        sc[SC_UX * nx + s] = ux;
+        sc[SC_UY * nx + s] = uy;
+        sc[SC_T * nx + s] = Tm;
+        sc[SC_INVTAU * nx + s] = invtau;
+        sc[SC_AS * nx + s] = As;
+        sc[SC_AS5T * nx + s] = As / (5.0 * Tm);
+        sc[SC_QX * nx + s] = qx;
+        sc[SC_QY * nx + s] = qy;
+        cell[kGIjd * nx + s] = (T)D.inv_jdeta[s];
+        // the band in which the projection of eq. (gx) is verified (a finite state outside it is
+        // flagged; non-finite values are caught by the residual check)
+        const double Tr = Tm / D.Tw;
+        if (Tr < kAuxTlo || Tr > kAuxThi || fabs(ux) > kAuxUmax * sqrt(D.Tw)) D.dyn[DY_RANGE] = 1.0;
         if ((flags & FLAG_STEP_DONE) && D.dyn[DY_AVG_ON] != 0.0) {
             // running sums of the fields at the end of every step (time averages, hrlb_average_*)
             double* A = D.avg;
@@ -1206,10 +1237,10 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     // g_x (eq. gx) and g_y (eq. gy) with the loops over the expansion order unrolled for the case's
     // padded row count (uniform over the block)
     switch (nxb) {
-        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        default: gx_nodes<T, 17>(q, LN, nxo, n, Tm, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        default: gx_nodes<T, 17>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
     }
     switch (nyb) {
         case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
@@ -1317,7 +1348,7 @@ extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_stage_lds(int fp32
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
     // FP32: the cell tables are followed by p_y and the wall populations of the tile's velocities
     const size_t vel = fp32 ? sizeof(double) * (size_t)(qy_max + 2 * kRows * std::min(qy_max, kMaxVpt)) : 0;
-    const size_t cells = (size_t)cell_lds_slots(qy_max) * kLdsSlot * es + vel;
+    const size_t cells = cell_lds_bytes(qy_max, es) + vel;
     const size_t moms = sizeof(double) * moments_per_pass(fp32 ? sizeof(float) : sizeof(double)) * kRows * kTileCells;
     return cells > moms ? cells : moms;
 }

@@ -11,6 +11,7 @@
 #include "../../include/hrlb.h"
 #include "hrlb_internal.h"
 #include "hrlb_plan.h"
+#include "hrlb_quadrature.h"
 
 extern "C" hipError_t hrlbk_stage(int fp32, const hrlb::InstDesc* descs, const hrlb::TileRef* tiles, int ntiles, unsigned* ctr,
                                   int stage, int flags, int qy_max, hipStream_t st);
@@ -94,10 +95,12 @@ struct SteadyTrack {
 // Returns HRLB_OK when the stop criterion is below tol, HRLB_NOT_CONVERGED to go on, and
 // HRLB_E_DIVERGED (with the message set) on a non-finite value.
 hrlb_status steady_update(SteadyTrack& t, const double* dy, long n, double dt, double tol, int stop_rule);
+// sets the thread's error message of HRLB_E_RANGE
+void range_message(long steps);
 
 // byte offsets of the regions of a case workspace
 struct Layout {
-    size_t desc, dyn, tables, f[3], cell, fields, avg, mom, res, tiles, cells, ctr, total;
+    size_t desc, dyn, tables, f[3], cell, cell_g, fields, avg, mom, res, tiles, cells, ctr, total;
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_vT, t_vMu, t_vOm,
         t_vPr, t_dts, t_jres, t_az2, t_aw2, t_hZ2, t_n;
@@ -109,6 +112,8 @@ struct Layout {
 
 struct hrlb_quad {
     int qx, nxo, qy, nyo;
+    hrlb::Recurrence hr;               // half-range recurrence (orthonormal h_l at any point)
+    std::vector<long double> auxZl, auxWl, auxZ2l, auxW2l;  // unscaled auxiliary rules, extended precision
     std::vector<double> zx, wx;        // [qx] positive nodes, weights
     std::vector<double> px, wx2;       // [2qx] h-major
     std::vector<double> zy, wy;        // [qy]

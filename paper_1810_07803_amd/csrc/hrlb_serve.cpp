@@ -288,6 +288,7 @@ extern "C" hrlb_status hrlb_server_pump(hrlb_server* s, hrlb_server_stats* stats
                 continue;
             }
             if (v == HRLB_E_DIVERGED) fail(HRLB_E_DIVERGED, "request %ld: non-finite residual", rq->id);
+            if (v == HRLB_E_RANGE) range_message(rq->c->steps_done);
             s->retire(rq, v, d);
             ++retired_n;
         }

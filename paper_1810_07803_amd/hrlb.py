@@ -16,7 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhrlb.so")
 
 HRLB_OK, HRLB_NOT_CONVERGED = 0, 1
-HRLB_E_INVALID, HRLB_E_NOMEM, HRLB_E_DEVICE, HRLB_E_DIVERGED = -1, -2, -3, -4
+HRLB_E_INVALID, HRLB_E_NOMEM, HRLB_E_DEVICE, HRLB_E_DIVERGED, HRLB_E_RANGE = -1, -2, -3, -4, -5
+HRLB_FLAG_NONFINITE, HRLB_FLAG_RANGE = 1, 2
 HRLB_FP64, HRLB_FP32_STORE_FP64_MOM = 0, 1
 HRLB_ROUND_NEAREST, HRLB_ROUND_STOCHASTIC = 0, 1
 HRLB_STOP_RESIDUAL, HRLB_STOP_PXY = 0, 1
@@ -26,7 +27,7 @@ FIELD_NAMES = ("n", "u_x", "u_y", "T", "P_xx", "P_xy", "P_yy", "T_zz", "q_x", "q
 EXPORTED = (
     "hrlb_init_quadrature", "hrlb_quadrature_nodes", "hrlb_case_workspace_bytes", "hrlb_init_case",
     "hrlb_step", "hrlb_run_to_steady", "hrlb_moments", "hrlb_get_state", "hrlb_set_state",
-    "hrlb_case_info", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
+    "hrlb_case_info", "hrlb_case_flags", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
     "hrlb_batch_workspace_bytes", "hrlb_batch_create", "hrlb_batch_step", "hrlb_batch_poll",
     "hrlb_batch_free", "hrlb_batch_profile", "hrlb_batch_set_streams", "hrlb_case_set_graph_steps",
     "hrlb_batch_set_graph_steps",
@@ -110,6 +111,7 @@ def load() -> C.CDLL:
                 "hrlb_get_state": [vp, dp],
                 "hrlb_set_state": [vp, dp],
                 "hrlb_case_info": [vp, dp, ip, ip, C.POINTER(C.c_long)],
+                "hrlb_case_flags": [vp, C.POINTER(C.c_uint)],
                 "hrlb_batch_workspace_bytes": [C.POINTER(vp), C.c_int, C.POINTER(C.c_size_t)],
                 "hrlb_batch_create": [C.POINTER(vp), C.c_int, vp, C.c_size_t, C.POINTER(vp)],
                 "hrlb_batch_step": [vp, C.c_long, C.c_int],
@@ -290,6 +292,12 @@ class Case:
         pi, n = C.c_double(), C.c_long()
         _check(load().hrlb_average_read(self.handle, _dptr(f), C.byref(pi), C.byref(n)))
         return f, pi.value, n.value
+
+    def flags(self) -> int:
+        """Sticky condition bits (HRLB_FLAG_NONFINITE, HRLB_FLAG_RANGE)."""
+        f = C.c_uint()
+        _check(load().hrlb_case_flags(self.handle, C.byref(f)))
+        return f.value
 
     def steps_done(self) -> int:
         sd = C.c_long()

@@ -1,8 +1,9 @@
 """The quadrature-convergence statement of Sec. IV (tests/golden/paper_quadrature_convergence.json):
 the paper's production models give Pi within 0.1% of HHLB(10;50) x HLB(6;7) on 48 nodes.  The helium
 transport tables are not available; mu ~ T^0.66 stands in for them.  Local time steps (same steady
-state, R18) and autotuned plans keep the solves to seconds; delta = 0.1 runs in the bench workload
-couette_paper_convergence (its reference solve alone takes about 20 s)."""
+state as the global step) and autotuned plans keep the solves to seconds (the delta = 0.1 reference
+solve takes the longest, about 20 s).  The GPU's numbers in this set-up are compared with the oracle
+element by element in test_gpu_temperature.py."""
 import json
 import os
 
@@ -30,7 +31,7 @@ def _pi(model, setup, delta):
     return pi
 
 
-@pytest.mark.parametrize("k", [0, 1])
+@pytest.mark.parametrize("k", [0, 1, 2])
 def test_production_quadratures_within_a_tenth_of_a_percent_of_the_reference(k):
     g = json.load(open(GOLDEN))
     prod = g["production"][k]

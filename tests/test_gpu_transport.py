@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from hrlb_inputs import perturb
-from tests.gpu_helpers import field_errs, make_pair, pxy_err, rel_state_err, say
+from tests.gpu_helpers import parity, say
 
 pytestmark = pytest.mark.gpu
 
@@ -41,13 +41,10 @@ def _pair(Qx, Qy, nx, steps, *, precision=0, rounding=0, table, **kw):
     case.set_state(np.stack([phi, chi]))
     case.step(steps)
     orc.step(phi, chi, steps)
-    st = case.get_state()
-    f_gpu = case.moments()[0]
     f_orc = orc.moments(phi, chi)
-    T = f_orc[3]
-    e_state = max(rel_state_err(st[0], phi), rel_state_err(st[1], chi))
-    e_fields = np.append(field_errs(f_gpu, f_orc), pxy_err(f_gpu, f_orc))
-    return e_state, e_fields, T
+    tol = FP64_TOL if precision == 0 else FP32_TOL
+    ok = parity(case.get_state(), phi, chi, case.moments()[0], f_orc, tol)
+    return ok, f_orc[3]
 
 
 @pytest.mark.parametrize("Qx,Qy,nx,steps,kw,min_intervals", [
@@ -57,21 +54,19 @@ def _pair(Qx, Qy, nx, steps, *, precision=0, rounding=0, table, **kw):
 def test_tabulated_law_fixed_step_parity_fp64(Qx, Qy, nx, steps, kw, min_intervals):
     table = _table(3)
     say(f"[table] Q{Qx}x{Qy} nx={nx} {steps} steps {kw}, {len(table)} rows")
-    e_state, e_fields, T = _pair(Qx, Qy, nx, steps, table=table, **kw)
+    ok, T = _pair(Qx, Qy, nx, steps, table=table, **kw)
     rows = np.array([r[0] for r in table])
     visited = np.unique(np.searchsorted(rows, T, side="right"))
-    say(f"   state err {e_state:.3e} field err max {e_fields.max():.2e}; T in [{T.min():.4f}, {T.max():.4f}], "
-        f"{len(visited)} intervals")
+    say(f"   T in [{T.min():.4f}, {T.max():.4f}], {len(visited)} intervals")
     assert len(visited) >= min_intervals
-    assert e_state < FP64_TOL and np.all(e_fields < FP64_TOL)
+    assert ok
 
 
 @pytest.mark.parametrize("rounding", [0, 1])
 def test_tabulated_law_fixed_step_parity_fp32(rounding):
-    e_state, e_fields, _ = _pair(8, 7, 132, 20, precision=1, rounding=rounding, table=_table(4), delta=0.5, uw=0.3,
-                                 stretch_A=0.9)
-    say(f"[table] fp32 rounding={rounding}: state err {e_state:.3e} field err max {e_fields.max():.2e}")
-    assert e_state < FP32_TOL and np.all(e_fields < FP32_TOL)
+    say(f"[table] fp32 rounding={rounding}")
+    ok, _ = _pair(8, 7, 132, 20, precision=1, rounding=rounding, table=_table(4), delta=0.5, uw=0.3, stretch_A=0.9)
+    assert ok
 
 
 def test_power_law_table_equals_the_power_law_on_gpu():
