@@ -40,6 +40,10 @@
  *     the WENO face value (with extrapolated ghosts) for leaving directions.
  *   - n_w uses the discrete sums over the velocity set of the leaving face values, which
  *     makes the discrete wall mass flux exactly zero.
+ *   - a second closure, selected by wall_closure = 1 and used only to check the first, drops the
+ *     WENO candidate stencils that reach beyond a wall (linear weights renormalised over the rest),
+ *     so that no ghost value is read; entering wall faces keep the wall population.  Both closures
+ *     are consistent, so their results must agree as the grid is refined.
  *   - WENO-5 is applied to phi and chi independently, eps = 1e-6, upwinded by sign(p_x).
  *   - initial state: rest equilibrium n = 1, u = 0, T = T_w.
  *   - local time steps (lts_cap > 1, a steady-state accelerator that is not in the paper): cell s
@@ -82,6 +86,8 @@ typedef struct {
     int ntab;                      /* 0: mu ~ T^omega and constant Pr; >= 2: the tabulated law      */
     const double *tabT, *tabMu, *tabPr; /* [ntab] T_n ascending, mu_n, Pr_n (= c_p mu_n / kappa_n)   */
     double lts_cap;                /* > 1: local time steps up to lts_cap * dt (steady states only)  */
+    int wall_closure;              /* 0: extrapolated ghosts (the solver's reading); 1: truncated      */
+                                   /* WENO stencils at the walls (a second consistent closure)         */
 } orc_problem;
 
 /* ----------------------------------------------------------------------------------------- */
@@ -346,20 +352,38 @@ int orc_collision_target(const orc_problem *P, const double *cell /* n,ux,uy,T,q
 /* ----------------------------------------------------------------------------------------- */
 /* WENO-5 (Jiang & Shu): face value from five values ordered along the upwind direction,       */
 /* a = f_{c-2}, b = f_{c-1}, c = f_c (upwind cell), d = f_{c+1}, e = f_{c+2}.                  */
+/* orc_weno5_sub keeps only the candidate stencils whose bit is set in mask (bit k: stencil k, */
+/* 0 = {a,b,c}, 1 = {b,c,d}, 2 = {c,d,e}), with their linear weights renormalised by dropping  */
+/* the others; the values of the dropped stencils are never read.  mask = 7 is plain WENO-5.   */
 /* ----------------------------------------------------------------------------------------- */
-double orc_weno5(double a, double b, double c, double d, double e)
+double orc_weno5_sub(double a, double b, double c, double d, double e, int mask)
 {
-    double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
-    double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
-    double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
-    double b0 = 13.0 / 12.0 * (a - 2.0 * b + c) * (a - 2.0 * b + c) + 0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
-    double b1 = 13.0 / 12.0 * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
-    double b2 = 13.0 / 12.0 * (c - 2.0 * d + e) * (c - 2.0 * d + e) + 0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
-    double a0 = 0.1 / ((ORC_EPS_WENO + b0) * (ORC_EPS_WENO + b0));
-    double a1 = 0.6 / ((ORC_EPS_WENO + b1) * (ORC_EPS_WENO + b1));
-    double a2 = 0.3 / ((ORC_EPS_WENO + b2) * (ORC_EPS_WENO + b2));
-    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+    double num = 0.0, den = 0.0;
+    if (mask & 1) {
+        double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+        double b0 = 13.0 / 12.0 * (a - 2.0 * b + c) * (a - 2.0 * b + c) + 0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
+        double a0 = 0.1 / ((ORC_EPS_WENO + b0) * (ORC_EPS_WENO + b0));
+        num += a0 * q0;
+        den += a0;
+    }
+    if (mask & 2) {
+        double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+        double b1 = 13.0 / 12.0 * (b - 2.0 * c + d) * (b - 2.0 * c + d) + 0.25 * (b - d) * (b - d);
+        double a1 = 0.6 / ((ORC_EPS_WENO + b1) * (ORC_EPS_WENO + b1));
+        num += a1 * q1;
+        den += a1;
+    }
+    if (mask & 4) {
+        double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+        double b2 = 13.0 / 12.0 * (c - 2.0 * d + e) * (c - 2.0 * d + e) + 0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
+        double a2 = 0.3 / ((ORC_EPS_WENO + b2) * (ORC_EPS_WENO + b2));
+        num += a2 * q2;
+        den += a2;
+    }
+    return num / den;
 }
+
+double orc_weno5(double a, double b, double c, double d, double e) { return orc_weno5_sub(a, b, c, d, e, 7); }
 
 /* Lagrange quadratic through (0,y0), (1,y1), (2,y2), evaluated at t */
 static double extrap_quadratic(double y0, double y1, double y2, double t)
@@ -395,12 +419,27 @@ static void fill_right_extrap(double *e, int N)
         e[NG + N + k] = extrap_quadratic(e[NG + N - 3], e[NG + N - 2], e[NG + N - 1], 3 + k);
 }
 
-/* face value at face f (between cells f-1 and f) for velocity sign sgn */
-static double face_value(const double *e, int f, double px)
+/* face value at face f (between cells f-1 and f) for the sign of px.  Extrapolated-ghost closure:
+ * plain WENO-5 over the extended row.  Truncated closure: the candidate stencils that reach a cell
+ * beyond a wall (below lo or above N-1) are dropped; lo = 0 at a wall, lo = -NG where the half
+ * channel's mirrored ghosts continue the row. */
+static double face_value_c(const orc_problem *P, const double *e, int N, int f, double px)
 {
     const double *c = e + NG;
-    if (px > 0) return orc_weno5(c[f - 3], c[f - 2], c[f - 1], c[f], c[f + 1]);
-    return orc_weno5(c[f + 2], c[f + 1], c[f], c[f - 1], c[f - 2]);
+    int mask = 7;
+    if (P->wall_closure == 1) {
+        int lo = P->half ? -NG : 0, hi = N - 1;
+        /* first cell of stencil k in upwind order: p_x > 0 reads cells f-3+k .. f-1+k; p_x < 0 reads
+         * cells f-k .. f+2-k */
+        mask = 0;
+        for (int k = 0; k < 3; ++k) {
+            int first = px > 0 ? f - 3 + k : f - k, last = first + 2;
+            if (first >= lo && last <= hi) mask |= 1 << k;
+        }
+        if (mask == 0) return 0.0; /* only wall faces of entering directions, whose value is overridden */
+    }
+    if (px > 0) return orc_weno5_sub(c[f - 3], c[f - 2], c[f - 1], c[f], c[f + 1], mask);
+    return orc_weno5_sub(c[f + 2], c[f + 1], c[f], c[f - 1], c[f - 2], mask);
 }
 
 typedef struct {
@@ -425,6 +464,38 @@ static void free_wall_tables(wall_tables *W)
     free(W->gxw);
     free(W->gyl);
     free(W->gyr);
+}
+
+/* The extended row of one velocity (cells -NG .. N+NG-1) as the right-hand side builds it: ghosts
+ * of directions leaving through a wall by quadratic extrapolation, of directions entering from a wall
+ * the wall population (wall_l at the left wall, wall_r at the right one); in the half channel the
+ * left ghosts hold the mirrored velocity's row fm.  Then the N+1 face values, the wall faces of
+ * entering directions being the wall population (diffuse reflection, equation (diffuse)). */
+int orc_row_faces(const orc_problem *P, double px, const double *f, double wall_l, double wall_r, const double *fm,
+                  double *e, double *F)
+{
+    int N = P->ncell;
+    fill_interior(f, N, e);
+    if (px > 0) {
+        for (int k = 1; k <= NG; ++k) e[NG - k] = wall_l;
+        fill_right_extrap(e, N);
+    } else {
+        fill_left_extrap(e);
+        for (int k = 0; k < NG; ++k) e[NG + N + k] = wall_r;
+    }
+    if (P->half) {
+        if (!fm) return -1;
+        fill_left_mirror(e, fm);
+    }
+    for (int fc = 0; fc <= N; ++fc) {
+        if (px > 0 && fc == 0 && !P->half)
+            F[fc] = wall_l;
+        else if (px < 0 && fc == N)
+            F[fc] = wall_r;
+        else
+            F[fc] = face_value_c(P, e, N, fc, px);
+    }
+    return 0;
 }
 
 /* ----------------------------------------------------------------------------------------- */
@@ -465,7 +536,7 @@ int orc_rhs(const orc_problem *P, const double *phi, const double *chi, double *
         inv_tau[s] = P->collisionless ? 0.0 : 1.0 / orc_tau(P, cell[0], cell[3]);
     }
 
-    /* leaving face values at both walls (extrapolated ghosts), equation (diffuse_nw) */
+    /* leaving face values at both walls (the closure's face values), equation (diffuse_nw) */
 #pragma omp parallel for schedule(static)
     for (int v = 0; v < V; ++v) {
         double *e = malloc(sizeof(double) * (N + 2 * NG));
@@ -473,8 +544,8 @@ int orc_rhs(const orc_problem *P, const double *phi, const double *chi, double *
         fill_interior(phi + (size_t)v * N, N, e);
         fill_left_extrap(e);
         fill_right_extrap(e, N);
-        out_face_l[v] = px < 0 ? face_value(e, 0, px) : 0.0;
-        out_face_r[v] = px > 0 ? face_value(e, N, px) : 0.0;
+        out_face_l[v] = px < 0 ? face_value_c(P, e, N, 0, px) : 0.0;
+        out_face_r[v] = px > 0 ? face_value_c(P, e, N, N, px) : 0.0;
         free(e);
     }
     double numl = 0, denl = 0, numr = 0, denr = 0;
@@ -506,23 +577,8 @@ int orc_rhs(const orc_problem *P, const double *phi, const double *chi, double *
             double *df = (dist == 0 ? dphi : dchi) + (size_t)v * N;
             const double *tg = (dist == 0 ? tphi : tchi) + (size_t)v * N;
             double wscale = dist == 0 ? 1.0 : P->Tw; /* chi_wall = K_B T_w phi_wall */
-            fill_interior(f, N, e);
-            if (px > 0) {
-                for (int k = 1; k <= NG; ++k) e[NG - k] = wscale * wl;
-                fill_right_extrap(e, N);
-            } else {
-                fill_left_extrap(e);
-                for (int k = 0; k < NG; ++k) e[NG + N + k] = wscale * wr;
-            }
-            if (P->half) fill_left_mirror(e, (dist == 0 ? phi : chi) + (size_t)vel_mirror(P, v) * N);
-            for (int fc = 0; fc <= N; ++fc) {
-                if (px > 0 && fc == 0 && !P->half)
-                    F[fc] = wscale * wl;
-                else if (px < 0 && fc == N)
-                    F[fc] = wscale * wr;
-                else
-                    F[fc] = face_value(e, fc, px);
-            }
+            const double *fm = P->half ? (dist == 0 ? phi : chi) + (size_t)vel_mirror(P, v) * N : NULL;
+            orc_row_faces(P, px, f, wscale * wl, wscale * wr, fm, e, F);
             for (int s = 0; s < N; ++s) {
                 double adv = -px * (F[s + 1] - F[s]) / (J[s] * deta);
                 double col = (tg[s] - f[s]) * inv_tau[s];

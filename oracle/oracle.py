@@ -52,7 +52,7 @@ class _Problem(C.Structure):
         ("delta", C.c_double), ("uw", C.c_double), ("Tw", C.c_double), ("Pr", C.c_double),
         ("omega", C.c_double), ("dt", C.c_double), ("collisionless", C.c_int), ("half", C.c_int),
         ("ntab", C.c_int), ("tabT", C.POINTER(C.c_double)), ("tabMu", C.POINTER(C.c_double)),
-        ("tabPr", C.POINTER(C.c_double)), ("lts_cap", C.c_double),
+        ("tabPr", C.POINTER(C.c_double)), ("lts_cap", C.c_double), ("wall_closure", C.c_int),
     ]
 
 
@@ -74,6 +74,9 @@ def _load():
             lib.orc_collision_target.argtypes = [pp, dp, dp, dp]
             lib.orc_weno5.argtypes = [C.c_double] * 5
             lib.orc_weno5.restype = C.c_double
+            lib.orc_weno5_sub.argtypes = [C.c_double] * 5 + [C.c_int]
+            lib.orc_weno5_sub.restype = C.c_double
+            lib.orc_row_faces.argtypes = [pp, C.c_double, dp, C.c_double, C.c_double, dp, dp, dp]
             lib.orc_rhs.argtypes = [pp, dp, dp, dp, dp, dp]
             lib.orc_init_state.argtypes = [pp, dp, dp]
             lib.orc_step.argtypes = [pp, dp, dp, C.c_long, C.c_int, C.c_double, dp]
@@ -93,6 +96,11 @@ def weno5(a, b, c, d, e) -> float:
     return _load().orc_weno5(a, b, c, d, e)
 
 
+def weno5_sub(a, b, c, d, e, mask: int) -> float:
+    """WENO-5 with only the candidate stencils of mask (bit k: stencil k) and renormalised linear weights."""
+    return _load().orc_weno5_sub(a, b, c, d, e, mask)
+
+
 def num_threads() -> int:
     return _load().orc_num_threads()
 
@@ -104,7 +112,7 @@ class OracleProblem:
                  stretch_A: float = 0.0, delta: float = 1.0, uw: float = 0.05, Tw: float = 1.0,
                  Pr: float = 2.0 / 3.0, omega: float = 0.7, dt: float | None = None, cfl: float = 0.5,
                  collisionless: bool = False, half_channel: bool = False, visc_table=None,
-                 local_dt_cap: float = 0.0):
+                 local_dt_cap: float = 0.0, wall_closure: int = 0):
         self.Qx, self.Qy = Qx, Qy
         self.Nx = min(Qx - 1, 10) if Nx is None else Nx
         self.Ny = Qy - 1 if Ny is None else Ny
@@ -139,7 +147,7 @@ class OracleProblem:
                            delta, uw, Tw, Pr, omega, self.dt, int(self.collisionless), int(self.half),
                            0 if self.table is None else self.table.shape[1],
                            *([None] * 3 if self.table is None else [_ptr(r) for r in self._tab]),
-                           float(local_dt_cap))
+                           float(local_dt_cap), int(wall_closure))
 
     # -- grid and time step ------------------------------------------------------------------
     def _grid(self):
@@ -198,6 +206,17 @@ class OracleProblem:
         tp, tc = np.zeros(self.nv), np.zeros(self.nv)
         _load().orc_collision_target(C.byref(self._p), _ptr(cell), _ptr(tp), _ptr(tc))
         return tp, tc
+
+    def row_faces(self, px: float, f: np.ndarray, wall_l: float = 0.0, wall_r: float = 0.0, fm=None):
+        """(extended row over cells -3 .. N+2, the N+1 face values) of one velocity's row f as the
+        right-hand side builds them: ghosts, wall populations wall_l / wall_r of entering directions,
+        the mirrored row fm of the half channel."""
+        f = np.ascontiguousarray(f, np.float64)
+        e, F = np.zeros(self.ncell + 6), np.zeros(self.ncell + 1)
+        fmp = None if fm is None else _ptr(np.ascontiguousarray(fm, np.float64))
+        if _load().orc_row_faces(C.byref(self._p), px, _ptr(f), wall_l, wall_r, fmp, _ptr(e), _ptr(F)) != 0:
+            raise ValueError("orc_row_faces failed")
+        return e, F
 
     def init_state(self):
         phi = np.zeros((self.nv, self.ncell))
