@@ -140,6 +140,24 @@ hrlb_status hrlb_case_workspace_bytes(const hrlb_quad *q, const hrlb_case_params
 hrlb_status hrlb_init_case(const hrlb_quad *q, const hrlb_case_params *p, void *dev_workspace,
                            size_t ws_bytes, void *hip_stream, hrlb_case **out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): a case like hrlb_init_case's whose caller passes device
+ * memory for the populations only.  dev_state (256-byte aligned, at least hrlb_case_state_bytes;
+ * caller-owned, untouched until the case is freed) holds the three state buffers f^0, f^1, f^2,
+ * each [2][Nv][n_cells] in the storage precision (phi then chi).  Everything else of the case -- its
+ * descriptor, tables, per-cell tables, fields, moment and residual partial sums, work lists and
+ * counters -- lives in the library's static scratch: one 32 MiB array per device, held until the
+ * process ends.  Allocates no device memory (no hipMalloc, hipFree or allocating routine; it uploads
+ * the tables and clears the counters in the scratch, which keeps the last contents otherwise).
+ * Every call on a device shares that device's scratch: one such case per device at a time.  Creating
+ * another one on the same device replaces the first, whose calls then return HRLB_E_INVALID; work of
+ * the first still in flight on a stream when the second is created races with the second's set-up.
+ * HRLB_E_INVALID also when the case's auxiliary data exceed the scratch (larger cases use
+ * hrlb_init_case).  The case works with every call that takes a case, batches included. */
+hrlb_status hrlb_case_state_bytes(const hrlb_quad *q, const hrlb_case_params *p, size_t *bytes);
+hrlb_status hrlb_init_case_static(const hrlb_quad *q, const hrlb_case_params *p, void *dev_state,
+                                  size_t state_bytes, void *hip_stream, hrlb_case **out);
+
 /* Enqueues n_steps >= 0 full SSP-RK3 steps (three stages each) on the case's stream. */
 hrlb_status hrlb_step(hrlb_case *c, long n_steps);
 

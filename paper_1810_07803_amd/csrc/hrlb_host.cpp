@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -262,10 +263,6 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     L.t_hZ2 = t; t += (size_t)(q->nxo + 1) * kAux2;
     L.t_n = t;
     off = align256(off + sizeof(double) * t);
-    for (int k = 0; k < 3; ++k) {
-        L.f[k] = off;
-        off = align256(off + es * 2 * (size_t)nv * nx);
-    }
     L.cell = off;  // FP64 scalars [kNSc][nx], then the storage-precision table [g_slots][nx]
     L.cell_g = align256(sizeof(double) * kNSc * nx);
     off = align256(off + L.cell_g + es * (size_t)g_slots(qx, qy) * nx);
@@ -284,7 +281,15 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     off = align256(off + sizeof(CellRef) * L.ncellblocks);
     L.ctr = off;
     off = align256(off + sizeof(unsigned) * (kXcds + 1));
-    L.total = off;
+    L.aux_total = off;
+    // the populations: three state buffers, offsets relative to the state region
+    size_t so = 0;
+    for (int k = 0; k < 3; ++k) {
+        L.f[k] = so;
+        so = align256(so + es * 2 * (size_t)nv * nx);
+    }
+    L.state_total = so;
+    L.total = L.aux_total + L.state_total;  // a workspace holds the auxiliary region, then the state
     return L;
 }
 
@@ -426,28 +431,25 @@ extern "C" hrlb_status hrlb_case_workspace_bytes(const hrlb_quad* q, const hrlb_
     return HRLB_OK;
 }
 
-extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params* p, void* dev_workspace,
-                                      size_t ws_bytes, void* hip_stream, hrlb_case** out)
+namespace {
+// A case whose auxiliary region (descriptor, tables, cell tables, moment and residual partials, work
+// lists, counters) starts at aux and whose three state buffers start at state; both device memory of
+// the caller (hrlb_init_case) or the state alone with aux in the library's static scratch
+// (hrlb_init_case_static).  Validated parameters and layout.
+hrlb_status init_case_in(const hrlb_quad* q, const hrlb_case_params* p, const Layout& L, char* aux, char* state,
+                         hipStream_t stream, int static_dev, hrlb_case** out)
 {
-    if (!out) return fail(HRLB_E_INVALID, "out is NULL");
-    *out = nullptr;
-    hrlb_status st = validate(q, p);
-    if (st != HRLB_OK) return st;
-    if (!dev_workspace) return fail(HRLB_E_INVALID, "device workspace is NULL");
-    if (((uintptr_t)dev_workspace) & 255) return fail(HRLB_E_INVALID, "device workspace must be 256-byte aligned");
-    Layout L = make_layout(q, p);
-    if (ws_bytes < L.total)
-        return fail(HRLB_E_NOMEM, "workspace of %zu bytes < %zu required", ws_bytes, L.total);
-
     hrlb_case* c = new (std::nothrow) hrlb_case;
     if (!c) return fail(HRLB_E_NOMEM, "host allocation failed");
     c->p = *p;
     c->q = q;
-    c->ws = (char*)dev_workspace;
-    c->ws_bytes = ws_bytes;
-    c->stream = (hipStream_t)hip_stream;
+    c->ws = aux;
+    c->ws_bytes = L.total;
+    c->stream = stream;
     c->L = L;
     c->steps_done = 0;
+    c->static_dev = static_dev;
+    c->static_gen = 0;
     const int nx = p->n_cells, qx = q->qx, qy = q->qy, nv = 2 * qx * qy;
     c->nv = nv;
     grid_of(p, c->x, c->jdeta);
@@ -591,8 +593,8 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     D.mom_r = mom_r;
     D.jsum = 0.0;
     for (int s = 0; s < nx; ++s) D.jsum += c->jdeta[s];
-    char* ws = c->ws;
-    for (int k = 0; k < 3; ++k) D.f[k] = ws + L.f[k];
+    char* ws = aux;
+    for (int k = 0; k < 3; ++k) D.f[k] = state + L.f[k];
     D.sc = (double*)(ws + L.cell);
     D.cell = ws + L.cell + L.cell_g;
     D.fields = (double*)(ws + L.fields);
@@ -684,6 +686,82 @@ extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params
     return HRLB_OK;
 }
 
+// generation of the static case last created on each device (0: none yet)
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+unsigned long g_static_gen[kMaxDevices] = {};
+}  // namespace
+
+// a case created by hrlb_init_case_static is live until the next one on its device replaces it
+hrlb_status hrlb::case_live(const hrlb_case* c)
+{
+    if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    if (c->static_dev < 0) return HRLB_OK;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_gen[c->static_dev] != c->static_gen)
+        return fail(HRLB_E_INVALID, "static case superseded by a later hrlb_init_case_static on device %d",
+                    c->static_dev);
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_init_case(const hrlb_quad* q, const hrlb_case_params* p, void* dev_workspace,
+                                      size_t ws_bytes, void* hip_stream, hrlb_case** out)
+{
+    if (!out) return fail(HRLB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hrlb_status st = validate(q, p);
+    if (st != HRLB_OK) return st;
+    if (!dev_workspace) return fail(HRLB_E_INVALID, "device workspace is NULL");
+    if (((uintptr_t)dev_workspace) & 255) return fail(HRLB_E_INVALID, "device workspace must be 256-byte aligned");
+    const Layout L = make_layout(q, p);
+    if (ws_bytes < L.total)
+        return fail(HRLB_E_NOMEM, "workspace of %zu bytes < %zu required", ws_bytes, L.total);
+    char* ws = (char*)dev_workspace;
+    return init_case_in(q, p, L, ws, ws + L.aux_total, (hipStream_t)hip_stream, -1, out);
+}
+
+extern "C" hrlb_status hrlb_case_state_bytes(const hrlb_quad* q, const hrlb_case_params* p, size_t* bytes)
+{
+    hrlb_status st = validate(q, p);
+    if (st != HRLB_OK) return st;
+    if (!bytes) return fail(HRLB_E_INVALID, "bytes is NULL");
+    *bytes = make_layout(q, p).state_total;
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_init_case_static(const hrlb_quad* q, const hrlb_case_params* p, void* dev_state,
+                                             size_t state_bytes, void* hip_stream, hrlb_case** out)
+{
+    if (!out) return fail(HRLB_E_INVALID, "out is NULL");
+    *out = nullptr;
+    hrlb_status st = validate(q, p);
+    if (st != HRLB_OK) return st;
+    if (!dev_state) return fail(HRLB_E_INVALID, "device state buffer is NULL");
+    if (((uintptr_t)dev_state) & 255) return fail(HRLB_E_INVALID, "device state buffer must be 256-byte aligned");
+    const Layout L = make_layout(q, p);
+    if (state_bytes < L.state_total)
+        return fail(HRLB_E_NOMEM, "state buffer of %zu bytes < %zu required", state_bytes, L.state_total);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HRLB_E_DEVICE, "device %d beyond the supported %d", dev, kMaxDevices);
+    void* scratch = nullptr;
+    size_t scratch_bytes = 0;
+    HIP_TRY(hrlbk_scratch(&scratch, &scratch_bytes));
+    if (L.aux_total > scratch_bytes)
+        return fail(HRLB_E_INVALID,
+                    "the case needs %zu bytes of tables and partial sums, beyond the %zu bytes of the static scratch",
+                    L.aux_total, scratch_bytes);
+    hrlb_case* c = nullptr;
+    st = init_case_in(q, p, L, (char*)scratch, (char*)dev_state, (hipStream_t)hip_stream, dev, &c);
+    if (st != HRLB_OK) return st;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        c->static_gen = ++g_static_gen[dev];
+    }
+    *out = c;
+    return HRLB_OK;
+}
+
 extern "C" void hrlb_free_case(hrlb_case* c) { delete c; }
 
 void hrlb::range_message(long steps)
@@ -696,6 +774,10 @@ void hrlb::range_message(long steps)
 extern "C" hrlb_status hrlb_case_flags(hrlb_case* c, unsigned* flags)
 {
     if (!c || !flags) return fail(HRLB_E_INVALID, "NULL argument");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     double dy[kNDyn];
     HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -706,6 +788,10 @@ extern "C" hrlb_status hrlb_case_flags(hrlb_case* c, unsigned* flags)
 extern "C" hrlb_status hrlb_case_info(const hrlb_case* c, double* dt, int* n_vel, int* n_cells, long* steps_done)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     if (dt) *dt = c->dt;
     if (n_vel) *n_vel = c->nv;
     if (n_cells) *n_cells = c->p.n_cells;
@@ -716,6 +802,10 @@ extern "C" hrlb_status hrlb_case_info(const hrlb_case* c, double* dt, int* n_vel
 extern "C" hrlb_status hrlb_step(hrlb_case* c, long n_steps)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     if (n_steps < 0) return fail(HRLB_E_INVALID, "n_steps < 0");
     hrlb_status st0 = ensure_analyzed(c);
     if (st0 != HRLB_OK) return st0;
@@ -831,6 +921,10 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
                                           hrlb_steady_info* info)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     if (check_every < 1 || max_steps < 0 || !(tol > 0.0)) return fail(HRLB_E_INVALID, "bad tol/max_steps/check_every");
     if (stop_rule != HRLB_STOP_RESIDUAL && stop_rule != HRLB_STOP_PXY) return fail(HRLB_E_INVALID, "bad stop rule");
     const auto t0 = std::chrono::steady_clock::now();
@@ -874,6 +968,10 @@ extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, dou
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
     {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
+    {
         hrlb_status sa = ensure_analyzed(c);
         if (sa != HRLB_OK) return sa;
     }
@@ -909,6 +1007,10 @@ extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, dou
 extern "C" hrlb_status hrlb_average_start(hrlb_case* c)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     HIP_TRY(hrlbk_average(c->d_desc, 1, c->p.n_cells, c->stream));
     return HRLB_OK;
 }
@@ -916,6 +1018,10 @@ extern "C" hrlb_status hrlb_average_start(hrlb_case* c)
 extern "C" hrlb_status hrlb_average_stop(hrlb_case* c)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     HIP_TRY(hrlbk_average(c->d_desc, 0, c->p.n_cells, c->stream));
     return HRLB_OK;
 }
@@ -923,6 +1029,10 @@ extern "C" hrlb_status hrlb_average_stop(hrlb_case* c)
 extern "C" hrlb_status hrlb_average_read(hrlb_case* c, double* fields, double* Pi, long* steps)
 {
     if (!c) return fail(HRLB_E_INVALID, "case is NULL");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     const int nx = c->p.n_cells;
     std::vector<double> a((size_t)kNFields * nx);
     double dy[kNDyn];
@@ -953,6 +1063,10 @@ extern "C" hrlb_status hrlb_average_read(hrlb_case* c, double* fields, double* P
 extern "C" hrlb_status hrlb_get_state(hrlb_case* c, double* host_state)
 {
     if (!c || !host_state) return fail(HRLB_E_INVALID, "NULL argument");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     const size_t n = 2 * (size_t)c->nv * c->p.n_cells;
     if (c->p.precision == HRLB_FP64) {
         HIP_TRY(hipMemcpyAsync(host_state, c->desc.f[0], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
@@ -969,6 +1083,10 @@ extern "C" hrlb_status hrlb_get_state(hrlb_case* c, double* host_state)
 extern "C" hrlb_status hrlb_set_state(hrlb_case* c, const double* host_state)
 {
     if (!c || !host_state) return fail(HRLB_E_INVALID, "NULL argument");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     const size_t n = 2 * (size_t)c->nv * c->p.n_cells;
     for (size_t k = 0; k < n; ++k)
         if (!std::isfinite(host_state[k])) return fail(HRLB_E_INVALID, "state holds a non-finite value at %zu", k);
@@ -1059,6 +1177,10 @@ hrlb_status batch_check(hrlb_case* const* cases, int n)
     if (!cases || n < 1) return fail(HRLB_E_INVALID, "empty batch");
     for (int i = 0; i < n; ++i) {
         if (!cases[i]) return fail(HRLB_E_INVALID, "case %d is NULL", i);
+        {
+            const hrlb_status sl = case_live(cases[i]);
+            if (sl != HRLB_OK) return sl;
+        }
         if (cases[i]->p.precision != cases[0]->p.precision) return fail(HRLB_E_INVALID, "mixed precisions in a batch");
         if (cases[i]->stream != cases[0]->stream) return fail(HRLB_E_INVALID, "cases of a batch must share a stream");
     }
@@ -1267,6 +1389,10 @@ extern "C" void hrlb_batch_free(hrlb_batch* b) { delete b; }
 extern "C" hrlb_status hrlb_case_set_graph_steps(hrlb_case* c, int steps_per_graph)
 {
     if (!c || steps_per_graph < 0) return fail(HRLB_E_INVALID, "NULL case or negative steps");
+    {
+        const hrlb_status sl = case_live(c);
+        if (sl != HRLB_OK) return sl;
+    }
     c->run.drop_graphs();
     c->run.graph_steps = steps_per_graph;
     return HRLB_OK;

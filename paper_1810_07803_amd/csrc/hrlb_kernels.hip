@@ -1339,6 +1339,38 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
 
 }  // namespace hrlb
 
+// ---- static scratch of the allocation-free case (hrlb_init_case_static) ---------------------------
+// The auxiliary region of one case (descriptor, tables, cell tables, fields, moment and residual
+// partials, work lists, counters) for callers that cannot allocate device memory.  Every device the
+// library runs on holds its own copy until the process ends.
+namespace {
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr int kScratchDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of the current device's scratch (looked up once per device with that device current;
+// the array's name is a host-side stand-in, not a device address) and its size.
+extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_scratch(void** ptr, size_t* bytes)
+{
+    static std::mutex mu;
+    static void* addr[kScratchDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kScratchBytes;
+    return hipSuccess;
+}
+
 // ---- host-callable launchers (C linkage inside the library) --------------------------------------
 using namespace hrlb;
 

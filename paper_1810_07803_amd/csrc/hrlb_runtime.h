@@ -21,6 +21,7 @@ extern "C" hipError_t hrlbk_renorm(int fp32, const hrlb::InstDesc* descs, int ni
 extern "C" hipError_t hrlbk_finalize(const hrlb::InstDesc* descs, int ninst, int with_res, hipStream_t st);
 extern "C" hipError_t hrlbk_init(int fp32, const hrlb::InstDesc* descs, int inst, size_t units, hipStream_t st);
 extern "C" hipError_t hrlbk_average(const hrlb::InstDesc* desc, int start, int nx, hipStream_t st);
+extern "C" hipError_t hrlbk_scratch(void** ptr, size_t* bytes);
 
 namespace hrlb {
 
@@ -97,10 +98,17 @@ struct SteadyTrack {
 hrlb_status steady_update(SteadyTrack& t, const double* dy, long n, double dt, double tol, int stop_rule);
 // sets the thread's error message of HRLB_E_RANGE
 void range_message(long steps);
+// HRLB_OK unless the case lives in the static scratch and a later static case on its device replaced it
+hrlb_status case_live(const hrlb_case* c);
 
 // byte offsets of the regions of a case workspace
 struct Layout {
-    size_t desc, dyn, tables, f[3], cell, cell_g, fields, avg, mom, res, tiles, cells, ctr, total;
+    // auxiliary region (offsets from its base): descriptor, dynamic scalars, tables, cell tables,
+    // fields, averages, moment and residual partials, work lists, counters; state region (offsets
+    // from its own base): the three population buffers f[0..2]
+    size_t desc, dyn, tables, cell, cell_g, fields, avg, mom, res, tiles, cells, ctr, aux_total;
+    size_t f[3], state_total;
+    size_t total;  // aux_total + state_total: one workspace holding both regions
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_vT, t_vMu, t_vOm,
         t_vPr, t_dts, t_jres, t_az2, t_aw2, t_hZ2, t_n;
@@ -145,6 +153,8 @@ struct hrlb_case {
     double mass0;
     std::vector<double> x, jdeta;
     bool needs_analyze;  // moments/tables of the stored state not computed yet
+    int static_dev;      // device whose static scratch holds the auxiliary region, -1 for a workspace case
+    unsigned long static_gen;  // generation of that static case (hrlb::case_live)
     hrlb::Launcher run;
 };
 

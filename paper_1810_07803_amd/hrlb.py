@@ -26,6 +26,7 @@ FIELD_NAMES = ("n", "u_x", "u_y", "T", "P_xx", "P_xy", "P_yy", "T_zz", "q_x", "q
 
 EXPORTED = (
     "hrlb_init_quadrature", "hrlb_quadrature_nodes", "hrlb_case_workspace_bytes", "hrlb_init_case",
+    "hrlb_case_state_bytes", "hrlb_init_case_static",
     "hrlb_step", "hrlb_run_to_steady", "hrlb_moments", "hrlb_get_state", "hrlb_set_state",
     "hrlb_case_info", "hrlb_case_flags", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
     "hrlb_batch_workspace_bytes", "hrlb_batch_create", "hrlb_batch_step", "hrlb_batch_poll",
@@ -105,6 +106,8 @@ def load() -> C.CDLL:
                 "hrlb_quadrature_nodes": [vp, dp, dp, dp, dp],
                 "hrlb_case_workspace_bytes": [vp, C.POINTER(CaseParams), C.POINTER(C.c_size_t)],
                 "hrlb_init_case": [vp, C.POINTER(CaseParams), vp, C.c_size_t, vp, C.POINTER(vp)],
+                "hrlb_case_state_bytes": [vp, C.POINTER(CaseParams), C.POINTER(C.c_size_t)],
+                "hrlb_init_case_static": [vp, C.POINTER(CaseParams), vp, C.c_size_t, vp, C.POINTER(vp)],
                 "hrlb_step": [vp, C.c_long],
                 "hrlb_run_to_steady": [vp, C.c_double, C.c_long, C.c_int, C.c_int, C.POINTER(SteadyInfo)],
                 "hrlb_moments": [vp, dp, dp, dp, dp],
@@ -223,14 +226,23 @@ def workspace_bytes(quad: Quadrature, params: CaseParams) -> int:
 
 
 # ---- one case ----------------------------------------------------------------------------------
-class Case:
-    """One Couette problem resident in a torch-allocated device workspace (hrlb_init_case)."""
+def state_bytes(quad: Quadrature, params: CaseParams) -> int:
+    n = C.c_size_t()
+    _check(load().hrlb_case_state_bytes(quad.handle, C.byref(params), C.byref(n)))
+    return n.value
 
-    def __init__(self, quad: Quadrature, params: CaseParams, device="cuda:0", stream=None, workspace=None):
+
+class Case:
+    """One Couette problem resident in a torch-allocated device workspace (hrlb_init_case).  With
+    static=True the caller's memory holds the populations only and the rest of the case lives in the
+    library's static scratch (hrlb_init_case_static; one such case per device at a time)."""
+
+    def __init__(self, quad: Quadrature, params: CaseParams, device="cuda:0", stream=None, workspace=None,
+                 static: bool = False):
         import torch
 
         self.quad, self.params = quad, params
-        nbytes = workspace_bytes(quad, params)
+        nbytes = state_bytes(quad, params) if static else workspace_bytes(quad, params)
         if workspace is None:
             workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         self._ws_tensor = workspace
@@ -240,8 +252,9 @@ class Case:
             raise HrlbError(HRLB_E_NOMEM, "workspace tensor too small")
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         h = C.c_void_p()
-        _check(load().hrlb_init_case(quad.handle, C.byref(params), C.c_void_p(base + off), nbytes,
-                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        init = load().hrlb_init_case_static if static else load().hrlb_init_case
+        _check(init(quad.handle, C.byref(params), C.c_void_p(base + off), nbytes,
+                    C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.handle = h
         dt, nv, nc, sd = C.c_double(), C.c_int(), C.c_int(), C.c_long()
         _check(load().hrlb_case_info(h, C.byref(dt), C.byref(nv), C.byref(nc), C.byref(sd)))
