@@ -344,11 +344,14 @@ struct Win {
 // cells are stored as [4 cells of a thread][16 threads of a row], so that the 16 lanes of a row read
 // 16 consecutive words; slots are kLdsSlot elements apart, which puts the 4 rows of a wave (reading
 // slots one apart for g_x) on disjoint bank ranges.
+// The FP64 scalar slots are read at the same slot by every row (broadcast), so they are packed
+// kTileCells apart.
 __host__ __device__ constexpr int g_lds_slots(int qy) { return 1 + qy + kRows; }
 constexpr int kLdsSlot = kTileCells + kTPR;
+constexpr int kScSlot = kTileCells;
 __host__ __device__ constexpr size_t cell_lds_bytes(int qy, size_t es)
 {
-    return sizeof(double) * kNSc * kLdsSlot + es * (size_t)g_lds_slots(qy) * kLdsSlot;
+    return sizeof(double) * kNSc * kScSlot + es * (size_t)g_lds_slots(qy) * kLdsSlot;
 }
 
 // MODE: kModeAnalyze (no update; partials of the current state f[0], used after set-up or a state
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
         pfbuf = s_pf;
     }
     double* const lds_sc = reinterpret_cast<double*>(smem);
-    T* const lds_g = reinterpret_cast<T*>(smem + sizeof(double) * kNSc * kLdsSlot);
+    T* const lds_g = reinterpret_cast<T*>(smem + sizeof(double) * kNSc * kScSlot);
     __shared__ double lds_red[kThreads / 64][2];
 
     const int tid = threadIdx.x;
@@ -464,7 +467,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
             if (row_on) prefetch(0);
         // per-tile copies of p_y (all j) and of the wall populations of the tile's velocities
         double* const lds_py = reinterpret_cast<double*>(smem + cell_lds_bytes(qy, es));
-        double* const lds_gw = lds_py + qy;  // [left, right][row][k]
+        // wall equilibria g_x(0,T_w) g_y(-/+u_w,T_w) of the tile's velocities in the storage precision (the
+        // wall populations they scale are stored in it): [left, right][row][k]
+        T* const lds_gw = reinterpret_cast<T*>(lds_py + qy);
 
         if (!ANALYZE) {
             // stage the tile's cell tables: the FP64 scalars; 1/(J deta), g_y (all j) and g_x of each
@@ -480,7 +485,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                     double v4[4];
                     bld4(rsc, ((uint32_t)slot * nx + cc) * 8u, v4);
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) lds_sc[slot * kLdsSlot + c * kTPR + q4] = v4[c];
+                    for (int c = 0; c < 4; ++c) lds_sc[slot * kScSlot + c * kTPR + q4] = v4[c];
                 } else {
                     const int gs = slot - kNSc;
                     int src;
@@ -508,8 +513,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                         gl = D.gw_l[vv];
                         gr = D.gw_r[vv];
                     }
-                    lds_gw[i] = gl;
-                    lds_gw[kRows * vpt + i] = gr;
+                    lds_gw[i] = (T)gl;
+                    lds_gw[kRows * vpt + i] = (T)gr;
                 }
             }
             __syncthreads();
@@ -711,10 +716,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
                     for (int c = 0; c < kStrip; ++c) {
                         const T p = P.w[4 + c], x = X.w[4 + c];
-                        const double ux = Ls[SC_UX * kLdsSlot + c * kTPR], uy = Ls[SC_UY * kLdsSlot + c * kTPR];
-                        const double Tt = Ls[SC_T * kLdsSlot + c * kTPR], itau = Ls[SC_INVTAU * kLdsSlot + c * kTPR];
-                        const double AS = Ls[SC_AS * kLdsSlot + c * kTPR], A5 = Ls[SC_AS5T * kLdsSlot + c * kTPR];
-                        const double qxv = Ls[SC_QX * kLdsSlot + c * kTPR], qyv = Ls[SC_QY * kLdsSlot + c * kTPR];
+                        const double ux = Ls[SC_UX * kScSlot + c * kTPR], uy = Ls[SC_UY * kScSlot + c * kTPR];
+                        const double Tt = Ls[SC_T * kScSlot + c * kTPR], itau = Ls[SC_INVTAU * kScSlot + c * kTPR];
+                        const double AS = Ls[SC_AS * kScSlot + c * kTPR], A5 = Ls[SC_AS5T * kScSlot + c * kTPR];
+                        const double qxv = Ls[SC_QX * kScSlot + c * kTPR], qyv = Ls[SC_QY * kScSlot + c * kTPR];
                         const T ijd = Lg[kGIjd * kLdsSlot + c * kTPR];
                         const T gy = Lg[(1 + j) * kLdsSlot + c * kTPR];
                         const T gx = Lg[(1 + qy + row) * kLdsSlot + c * kTPR];
@@ -1379,7 +1384,8 @@ extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_stage_lds(int fp32
 {
     const size_t es = fp32 ? sizeof(float) : sizeof(double);
     // FP32: the cell tables are followed by p_y and the wall populations of the tile's velocities
-    const size_t vel = fp32 ? sizeof(double) * (size_t)(qy_max + 2 * kRows * std::min(qy_max, kMaxVpt)) : 0;
+    const size_t vel =
+        fp32 ? sizeof(double) * (size_t)qy_max + sizeof(float) * (size_t)(2 * kRows * std::min(qy_max, kMaxVpt)) : 0;
     const size_t cells = cell_lds_bytes(qy_max, es) + vel;
     const size_t moms = sizeof(double) * moments_per_pass(fp32 ? sizeof(float) : sizeof(double)) * kRows * kTileCells;
     return cells > moms ? cells : moms;
