@@ -346,6 +346,12 @@ def main(argv=None):
     quads, cases, batch, tuned = _build(spec, insts, tune=not args.no_tune, tile_vpt=args.tile_vpt,
                                         cell_lanes=lanes, rows=rows)
     units = sum(c.nv * c.ncell for c in cases)
+    from paper_1810_07803_amd import hrlb as _h
+
+    # the stage kernel advances the cases of the tiled path; the small path's cases run one launch of
+    # their own per block of steps
+    tiled_units = sum(c.nv * c.ncell for c in cases if c.kernel_path() == _h.HRLB_PATH_TILED)
+    n_small = sum(1 for c in cases if c.kernel_path() == _h.HRLB_PATH_SMALL)
     batch.set_graph_steps(args.graph_steps)
     batch.set_streams(args.streams)
     stream = torch.cuda.current_stream()
@@ -381,7 +387,7 @@ def main(argv=None):
     # algorithmic bytes per stage launch: read f_in and write f_out (both dists) in every stage,
     # plus f^n in stages 2 and 3: (2 + 3 + 3)/3 passes of 2 dists per unit on average
     bytes_per_unit = es * 2 * (2 + 3 + 3) / 3.0
-    achieved = units * bytes_per_unit / (stage_ms * 1e-3) / 1e9
+    achieved = tiled_units * bytes_per_unit / (stage_ms * 1e-3) / 1e9
     from paper_1810_07803_amd import profiling
 
     traffic = profiling.load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_stage_kernel_traffic.txt"))
@@ -389,7 +395,8 @@ def main(argv=None):
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "stage_kernel<%s, 1>" % ("float" if es == 4 else "double"),
                 "kernel_ms": round(stage_ms, 4), "cell_kernel_ms": round(cell_ms, 4),
-                "bytes_per_unit_per_launch": bytes_per_unit, "units_per_launch": units,
+                "bytes_per_unit_per_launch": bytes_per_unit, "units_per_launch": tiled_units,
+                "small_path_instances": n_small,
                 "launches": "whole batch on one stream"}
 
     cpu = None

@@ -59,6 +59,7 @@ enum { HRLB_FLAG_NONFINITE = 1u, HRLB_FLAG_RANGE = 2u };
 enum { HRLB_FP64 = 0, HRLB_FP32_STORE_FP64_MOM = 1 };
 enum { HRLB_ROUND_NEAREST = 0, HRLB_ROUND_STOCHASTIC = 1 };
 enum { HRLB_STOP_RESIDUAL = 0, HRLB_STOP_PXY = 1 };
+enum { HRLB_PATH_AUTO = 0, HRLB_PATH_TILED = 1, HRLB_PATH_SMALL = 2 };
 
 typedef struct hrlb_quad hrlb_quad;   /* immutable velocity set; may be shared by many cases */
 typedef struct hrlb_case hrlb_case;   /* one Couette problem resident in a device workspace */
@@ -128,6 +129,14 @@ typedef struct {
      * recomputes the moments.  The residual becomes ||(f_new - f_old)/dt_s|| / ||f_old||.  The
      * fixed point R(f) = 0, and so the steady state, is the one of the global step.  At most 1e6. */
     double local_dt_cap;
+    /* Kernels that advance the case.  HRLB_PATH_TILED: two launches per Runge-Kutta stage over tiles of
+     * 64 cells x 16 velocity rows (every case, any size).  HRLB_PATH_SMALL: one launch per block of steps
+     * in which one workgroup holds the whole case (populations, stage buffers, tables) in 64 KB of LDS,
+     * for cases of a few thousand cell-velocity units whose tiled steps are bound by launch latency;
+     * HRLB_E_INVALID if the case does not fit.  HRLB_PATH_AUTO (0): the small path when the case fits.
+     * The two paths sum the moments in different orders; a case takes its path alone and in any batch,
+     * so it keeps its bits there. */
+    int kernel_path;
 } hrlb_case_params;
 
 /* Device workspace size (bytes) needed by a case with these parameters. */
@@ -219,6 +228,9 @@ hrlb_status hrlb_set_state(hrlb_case *c, const double *host_state);
  * kernel sets it at every stage, so it covers steps taken with hrlb_step too). */
 hrlb_status hrlb_case_flags(hrlb_case *c, unsigned *flags);
 
+/* The kernels that advance the case: HRLB_PATH_TILED or HRLB_PATH_SMALL (see kernel_path). */
+hrlb_status hrlb_case_kernel_path(const hrlb_case *c, int *path);
+
 /* Time step in use and the number of velocities / cells of the case. */
 hrlb_status hrlb_case_info(const hrlb_case *c, double *dt, int *n_vel, int *n_cells, long *steps_done);
 
@@ -227,11 +239,12 @@ void hrlb_free_quadrature(hrlb_quad *q);
 const char *hrlb_last_error(void);
 
 /* ---- batching: several cases, possibly of different sizes and velocity sets, advanced by shared
- * kernel launches.  The cases are split into parts of about equal work (velocities x cells); each
- * part is advanced by one persistent launch per stage and kernel on a stream of its own, forked
- * from and joined back into the cases' stream, so that one part's per-cell kernel overlaps another
- * part's stage kernel.  Three parts by default for batches of at least 2e7 cell-velocity units,
- * one part below (measured faster on MI355X).  Each case keeps its own
+ * kernel launches.  The cases of the tiled path are split into parts of about equal work (velocities x
+ * cells); each part is advanced by one persistent launch per stage and kernel on a stream of its own,
+ * forked from and joined back into the cases' stream, so that one part's per-cell kernel overlaps
+ * another part's stage kernel.  Three parts by default for batches of at least 2e7 cell-velocity
+ * units, one part below (measured faster on MI355X).  The cases of the small path (kernel_path) form
+ * one more part, one block per case and one launch per block of steps.  Each case keeps its own
  * workspace and results; a case's numbers are the same alone, in any batch and in any split.  All
  * cases must share one stream and one precision.  The batch needs its own device workspace for
  * descriptors and tile lists (sized for any split into 1 to 4 parts). */
@@ -244,8 +257,9 @@ hrlb_status hrlb_batch_step(hrlb_batch *b, long n_steps, int check);
 /* Synchronous: residual[i], pxy_mean[i] of case i from the last checked step (NULL allowed). */
 hrlb_status hrlb_batch_poll(hrlb_batch *b, double *residual, double *pxy_mean);
 void hrlb_batch_free(hrlb_batch *b);
-/* Splits the batch into n_streams parts (1..4), each on its own stream; synchronous (waits for the
- * batch's stream, then re-uploads the launch tables). */
+/* Splits the batch's tiled cases into n_streams parts (1..4), each on its own stream (the small-path
+ * cases keep their own part); synchronous (waits for the batch's stream, then re-uploads the launch
+ * tables). */
 hrlb_status hrlb_batch_set_streams(hrlb_batch *b, int n_streams);
 
 /* Step blocks of this many steps are captured once as a HIP graph (on a library-private stream)
@@ -256,8 +270,9 @@ hrlb_status hrlb_case_set_graph_steps(hrlb_case *c, int steps_per_graph);
 hrlb_status hrlb_batch_set_graph_steps(hrlb_batch *b, int steps_per_graph);
 
 /* Profiling: runs n_steps steps of the batch like hrlb_batch_step, with a HIP event pair recorded
- * on the batch's stream around every kernel launch, then waits and returns the mean duration (ms)
- * of one launch of the stage kernel and of the per-cell kernel.  Synchronous. */
+ * on the batch's stream around every kernel launch of the tiled path, then waits and returns the mean
+ * duration (ms) of one launch of the stage kernel and of the per-cell kernel (cases on the small path
+ * take the same steps, untimed).  Synchronous. */
 hrlb_status hrlb_batch_profile(hrlb_batch *b, long n_steps, double *stage_kernel_ms, double *cell_kernel_ms);
 
 /* ---- serving: a request loop with continuous batching.  Couette solves (any velocity set, grid,

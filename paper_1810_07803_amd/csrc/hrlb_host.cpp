@@ -178,6 +178,8 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
         return fail(HRLB_E_INVALID, "cell_lanes=%d must be 0 or a power of two up to %d", p->cell_lanes, kMaxCellLanes);
     if (p->half_channel != 0 && p->half_channel != 1) return fail(HRLB_E_INVALID, "half_channel must be 0 or 1");
     if (!(p->local_dt_cap >= 0.0 && p->local_dt_cap <= 1e6)) return fail(HRLB_E_INVALID, "local_dt_cap outside [0, 1e6]");
+    if (p->kernel_path != HRLB_PATH_AUTO && p->kernel_path != HRLB_PATH_TILED && p->kernel_path != HRLB_PATH_SMALL)
+        return fail(HRLB_E_INVALID, "unknown kernel_path %d", p->kernel_path);
     if (p->visc_table_n != 0) {
         const int nt = p->visc_table_n;
         if (nt < 2 || nt > kMaxViscTable) return fail(HRLB_E_INVALID, "visc_table_n=%d outside [2, %d]", nt, kMaxViscTable);
@@ -193,6 +195,9 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
     }
     return HRLB_OK;
 }
+
+// LDS of one small-case block at most: two such blocks fit a CU beside other launches' blocks
+constexpr size_t kSmallLdsMax = size_t(64) << 10;
 
 // velocities per row: the requested divisor, or the largest divisor of qy not above 8 that still
 // fills the 16 rows of a group
@@ -337,6 +342,9 @@ void grid_of(const hrlb_case_params* p, std::vector<double>& x, std::vector<doub
 
 hrlb_status enqueue_eager(const Launcher& L, long n_steps, bool check_last, hipStream_t st)
 {
+    // the small cases: all n_steps in one launch (their check, rescaling and re-analysis inside)
+    if (L.nsmall > 0 && n_steps > 0)
+        HIP_TRY(hrlbk_small(L.fp32, L.small_descs, L.nsmall, (int)n_steps, check_last ? 1 : 0, L.small_lds, st));
     for (long s = 0; s < n_steps; ++s) {
         const bool chk = check_last && s + 1 == n_steps;
         for (int stage = 0; stage < 3; ++stage) {
@@ -637,17 +645,34 @@ hrlb_status init_case_in(const hrlb_quad* q, const hrlb_case_params* p, const La
         return fail(HRLB_E_INVALID, "internal: inconsistent tile list");
     }
     c->ntiles = (int)tiles.size();
+    // the small-case kernel when the case fits its LDS (kernel_path)
+    c->small_lds = hrlbk_small_lds(&D);
+    const bool fits = c->small_lds <= kSmallLdsMax && D.nxb <= 11 && D.nyb != 0 && D.nyb <= 12;
+    if (p->kernel_path == HRLB_PATH_SMALL && !fits) {
+        const size_t need = c->small_lds;
+        delete c;
+        return fail(HRLB_E_INVALID,
+                    "the small path takes cases of at most %zu bytes of LDS (this one: %zu) and expansion orders "
+                    "N_x <= 10, N_y <= 11", kSmallLdsMax, need);
+    }
+    c->small = p->kernel_path == HRLB_PATH_SMALL || (p->kernel_path == HRLB_PATH_AUTO && fits);
     c->run.fp32 = p->precision == HRLB_FP32_STORE_FP64_MOM;
-    c->run.descs = c->d_desc;
-    c->run.ninst = 1;
-    c->run.tiles = c->d_tiles;
-    c->run.ctr = c->d_ctr;
-    c->run.ntiles = c->ntiles;
-    c->run.cells = c->d_cells;
-    c->run.ncellblocks = L.ncellblocks;
-    c->run.qy_max = qy;
-    c->run.any_lts = p->local_dt_cap > 1.0;
     c->run.stream = c->stream;
+    c->run.qy_max = qy;
+    if (c->small) {
+        c->run.small_descs = c->d_desc;
+        c->run.nsmall = 1;
+        c->run.small_lds = c->small_lds;
+    } else {
+        c->run.descs = c->d_desc;
+        c->run.ninst = 1;
+        c->run.tiles = c->d_tiles;
+        c->run.ctr = c->d_ctr;
+        c->run.ntiles = c->ntiles;
+        c->run.cells = c->d_cells;
+        c->run.ncellblocks = L.ncellblocks;
+        c->run.any_lts = p->local_dt_cap > 1.0;
+    }
     std::vector<CellRef> cells;
     cells = plan_cell_blocks(std::vector<int>{nx}, std::vector<int>{kCellThreads / L.cell_lanes},
                              std::vector<char>{(char)wall_blocks_of_their_own(qx, qy)});
@@ -782,6 +807,13 @@ extern "C" hrlb_status hrlb_case_flags(hrlb_case* c, unsigned* flags)
     HIP_TRY(hipMemcpyAsync(dy, c->desc.dyn, sizeof dy, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     *flags = (dy[DY_FLAGS] != 0.0 ? HRLB_FLAG_NONFINITE : 0u) | (dy[DY_RANGE] != 0.0 ? HRLB_FLAG_RANGE : 0u);
+    return HRLB_OK;
+}
+
+extern "C" hrlb_status hrlb_case_kernel_path(const hrlb_case* c, int* path)
+{
+    if (!c || !path) return fail(HRLB_E_INVALID, "NULL argument");
+    *path = c->small ? HRLB_PATH_SMALL : HRLB_PATH_TILED;
     return HRLB_OK;
 }
 
@@ -1117,11 +1149,16 @@ constexpr int kSplitParts = 3;
 
 // cases of a batch split into n parts of about equal work (units = velocities x cells): largest first
 // onto the least loaded part; each part keeps its cases in ascending order
-std::vector<std::vector<int>> split_batch(hrlb_case* const* cases, int n, int parts)
+// The cases of the tiled path split into `parts` parts of about equal work, and the cases of the small
+// path (if any) in one part of their own after them, whose one launch per block of steps then overlaps
+// the tiled parts' launches on its own stream.  all_tiled: every case counts as tiled (analysis passes).
+std::vector<std::vector<int>> split_batch(hrlb_case* const* cases, int n, int parts, bool all_tiled = false)
 {
-    parts = std::max(1, std::min(parts, n));
-    std::vector<int> order(n);
-    for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<int> order, smalls;
+    for (int i = 0; i < n; ++i) (all_tiled || !cases[i]->small ? order : smalls).push_back(i);
+    const int nt = (int)order.size();
+    parts = std::max(1, std::min(parts, nt));
+    if (nt == 0) return {smalls};
     auto units = [&](int i) { return (double)cases[i]->nv * cases[i]->p.n_cells; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return units(a) > units(b); });
     std::vector<std::vector<int>> out(parts);
@@ -1132,6 +1169,7 @@ std::vector<std::vector<int>> split_batch(hrlb_case* const* cases, int n, int pa
         load[k] += units(i);
     }
     for (auto& v : out) std::sort(v.begin(), v.end());
+    if (!smalls.empty()) out.push_back(smalls);
     return out;
 }
 
@@ -1150,15 +1188,32 @@ struct PartLayout {
 };
 
 // workspace layout of a batch split into `parts` parts (descriptors, tile list and cell list per part)
-size_t parts_layout(hrlb_case* const* cases, const std::vector<std::vector<int>>& split, std::vector<PartLayout>* L)
+// the cases of a part in launch order: those on the tiled kernels, then those on the small-case kernel
+// (every case on the tiled kernels for an analysis pass, which runs them on any case)
+std::vector<int> launch_order(hrlb_case* const* cases, const std::vector<int>& idx, bool all_tiled, int* ntiled)
+{
+    std::vector<int> out;
+    for (int i : idx)
+        if (all_tiled || !cases[i]->small) out.push_back(i);
+    *ntiled = (int)out.size();
+    for (int i : idx)
+        if (!all_tiled && cases[i]->small) out.push_back(i);
+    return out;
+}
+
+size_t parts_layout(hrlb_case* const* cases, const std::vector<std::vector<int>>& split, std::vector<PartLayout>* L,
+                    bool all_tiled = false)
 {
     size_t off = 0;
     if (L) L->clear();
-    for (const auto& idx : split) {
+    for (const auto& part : split) {
         PartLayout P{};
-        P.ntiles = (int)part_tiles(cases, idx).size();
+        int ntiled = 0;
+        const std::vector<int> idx = launch_order(cases, part, all_tiled, &ntiled);
+        const std::vector<int> tiled(idx.begin(), idx.begin() + ntiled);
+        P.ntiles = (int)part_tiles(cases, tiled).size();
         P.ncellblocks = 0;
-        for (int i : idx) P.ncellblocks += cases[i]->L.ncellblocks;
+        for (int i : tiled) P.ncellblocks += cases[i]->L.ncellblocks;
         P.descs = off;
         off = align256(off + sizeof(InstDesc) * idx.size());
         P.tiles = off;
@@ -1190,26 +1245,27 @@ hrlb_status batch_check(hrlb_case* const* cases, int n)
 // workspace that holds the launch tables of any split into 1..kMaxBatchParts parts
 size_t batch_bytes(hrlb_case* const* cases, int n)
 {
-    size_t m = 0;
+    size_t m = parts_layout(cases, split_batch(cases, n, 1, true), nullptr, true);
     for (int p = 1; p <= kMaxBatchParts; ++p) m = std::max(m, parts_layout(cases, split_batch(cases, n, p), nullptr));
     return m;
 }
 
-// (re)builds the parts of a batch inside its workspace and uploads their tables (synchronous)
-hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
+// (re)builds the parts of a batch inside its workspace and uploads their tables (synchronous);
+// all_tiled: every case on the tiled kernels (the batch's analysis pass)
+hrlb_status batch_build_parts(hrlb_batch* b, int nparts, bool all_tiled = false)
 {
     const int n = (int)b->cases.size();
     hrlb_case* const* cases = b->cases.data();
-    const auto split = split_batch(cases, n, nparts);
+    const auto split = split_batch(cases, n, nparts, all_tiled);
     std::vector<PartLayout> L;
-    const size_t need = parts_layout(cases, split, &L);
+    const size_t need = parts_layout(cases, split, &L, all_tiled);
     if (need > b->ws_bytes) return fail(HRLB_E_INVALID, "internal: batch workspace too small for %d parts", nparts);
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->parts.clear();
     for (size_t k = 0; k < split.size(); ++k) {
         auto part = std::make_unique<hrlb_batch_part>();
         hrlb_batch_part& P = *part;
-        P.idx = split[k];
+        P.idx = launch_order(cases, split[k], all_tiled, &P.ntiled);
         P.d_descs = (InstDesc*)(b->ws + L[k].descs);
         P.d_tiles = (TileRef*)(b->ws + L[k].tiles);
         P.d_cells = (CellRef*)(b->ws + L[k].cells);
@@ -1223,13 +1279,18 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
             P.own_stream = true;
             HIP_TRY(hipEventCreateWithFlags(&P.done, hipEventDisableTiming));
         }
-        const int ni = (int)P.idx.size();
+        const int ni = (int)P.idx.size(), nt = P.ntiled;
         std::vector<InstDesc> descs(ni);
-        std::vector<int> nct(ni), ngr(ni), ncell(ni), cpb(ni);
-        std::vector<char> own(ni);
+        std::vector<int> nct(nt), ngr(nt), ncell(nt), cpb(nt);
+        std::vector<char> own(nt);
+        size_t small_lds = 0;
         for (int q = 0; q < ni; ++q) {
             const hrlb_case* c = cases[P.idx[q]];
             descs[q] = c->desc;
+            if (q >= nt) {
+                small_lds = std::max(small_lds, c->small_lds);
+                continue;
+            }
             nct[q] = c->L.nctiles;
             ngr[q] = c->L.ngroups;
             ncell[q] = c->p.n_cells;
@@ -1237,9 +1298,9 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
             own[q] = wall_blocks_of_their_own(c->q->qx, c->q->qy);
         }
         const std::vector<CellRef> cells = plan_cell_blocks(ncell, cpb, own);
-        const std::vector<TileRef> tiles = part_tiles(cases, P.idx);
+        const std::vector<TileRef> tiles = part_tiles(cases, std::vector<int>(P.idx.begin(), P.idx.begin() + nt));
         if ((int)tiles.size() != P.ntiles || (int)cells.size() != P.ncellblocks ||
-            !tiles_valid(tiles, (size_t)P.ntiles, ni, nct.data(), ngr.data()))
+            !tiles_valid(tiles, (size_t)P.ntiles, nt, nct.data(), ngr.data()))
             return fail(HRLB_E_INVALID, "internal: inconsistent batch tile list");
         static const unsigned zeros[kXcds + 1] = {};
         Copies cp(b->stream);  // the staging vectors end with this iteration
@@ -1251,7 +1312,10 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
         if (sc != HRLB_OK) return sc;
         P.run.fp32 = b->fp32;
         P.run.descs = P.d_descs;
-        P.run.ninst = ni;
+        P.run.ninst = nt;
+        P.run.small_descs = P.d_descs + nt;
+        P.run.nsmall = ni - nt;
+        P.run.small_lds = small_lds;
         P.run.tiles = P.d_tiles;
         P.run.ctr = P.d_ctr;
         P.run.ntiles = P.ntiles;
@@ -1260,7 +1324,7 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts)
         P.run.shmem = b->shmem;
         P.run.qy_max = b->qy_max;
         P.run.any_lts = false;
-        for (int i : P.idx) P.run.any_lts = P.run.any_lts || cases[i]->p.local_dt_cap > 1.0;
+        for (int q = 0; q < nt; ++q) P.run.any_lts = P.run.any_lts || cases[P.idx[q]]->p.local_dt_cap > 1.0;
         P.run.stream = P.stream;
         P.run.graph_steps = b->graph_steps;
         b->parts.push_back(std::move(part));
@@ -1323,7 +1387,7 @@ extern "C" hrlb_status hrlb_batch_create(hrlb_case* const* cases, int n_cases, v
     bool any = false;
     for (int i = 0; i < n_cases; ++i) any = any || cases[i]->needs_analyze;
     if (any) {
-        st = batch_build_parts(b.get(), 1);
+        st = batch_build_parts(b.get(), 1, true);
         if (st != HRLB_OK) return st;
         const hrlb_batch_part& P = *b->parts[0];
         HIP_TRY(hrlbk_stage(b->fp32, P.d_descs, P.d_tiles, P.ntiles, P.d_ctr, -1, 0, b->qy_max, b->stream));
@@ -1438,17 +1502,27 @@ extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* s
             if (e == hipSuccess) e = hipEventRecord(e4[3], P.stream);
             if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profiled launch: %s", hipGetErrorString(e));
         }
+        // the part's small cases take the same steps (not timed)
+        if (st == HRLB_OK && P.run.nsmall > 0) {
+            const hipError_t e = hrlbk_small(b->fp32, P.run.small_descs, P.run.nsmall, (int)n_steps, 0,
+                                             P.run.small_lds, P.stream);
+            if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "small-case launch: %s", hipGetErrorString(e));
+        }
     }
     if (st == HRLB_OK) st = batch_join(b);
+    // the mean over the launches of the parts that hold tiled cases (the small-case part has none)
     double ts = 0, tc = 0;
+    size_t timed = 0;
     if (st == HRLB_OK) {
         hipError_t e = hipStreamSynchronize(b->stream);
         for (size_t i = 0; i < nl * np && e == hipSuccess; ++i) {
+            if (b->parts[i / nl]->ntiles == 0) continue;
             float a = 0, c = 0;
             e = hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]);
             if (e == hipSuccess) e = hipEventElapsedTime(&c, ev[4 * i + 2], ev[4 * i + 3]);
             ts += a;
             tc += c;
+            ++timed;
         }
         if (e != hipSuccess) st = fail(HRLB_E_DEVICE, "profile events: %s", hipGetErrorString(e));
     }
@@ -1456,7 +1530,7 @@ extern "C" hrlb_status hrlb_batch_profile(hrlb_batch* b, long n_steps, double* s
         if (e) (void)hipEventDestroy(e);
     if (st != HRLB_OK) return st;
     for (hrlb_case* c : b->cases) c->steps_done += n_steps;
-    if (stage_kernel_ms) *stage_kernel_ms = ts / (double)(nl * np);
-    if (cell_kernel_ms) *cell_kernel_ms = tc / (double)(nl * np);
+    if (stage_kernel_ms) *stage_kernel_ms = timed ? ts / (double)timed : 0.0;
+    if (cell_kernel_ms) *cell_kernel_ms = timed ? tc / (double)timed : 0.0;
     return HRLB_OK;
 }

@@ -1097,6 +1097,135 @@ __device__ __forceinline__ void gy_nodes_long(int q, int LN, int nyo, double uy,
     }
 }
 
+// The per-cell part of the per-cell kernel: from the raw moment sums R of cell s (the partial sums of
+// the cell's LN lanes, lane q) to the FP64 scalars sc[slot * nx + s] and the storage-precision table
+// cell[slot * nx + s] of the next stage, and with FLAG_STEP_DONE / FLAG_FIELDS the fields, the running
+// averages and the range flag.  Shared by the per-cell kernel (global tables) and the small-case kernel
+// (tables in LDS, same layout).
+// SMALLB: only the unrolled buckets of expansion orders up to N_x = 10, N_y = 11 (the small-case path
+// admits no others), which keeps its register use down
+template <typename T, bool SMALLB = false>
+__device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom], int q, int LN, int s, bool on,
+                                            int flags, double* sc, T* cell, const double* ktab, const CellLds& lay)
+{
+    const int nx = D.nx;
+    const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
+    const double* s_wx = ktab + lay.wx;
+    const double* s_wy = ktab + lay.wy;
+    const double* s_az = ktab + lay.az;
+    const double* s_aw = ktab + lay.aw;
+    const double* s_hZ = ktab + lay.hZ;
+    const double* s_hz = ktab + lay.hz;
+    const double* s_he = ktab + lay.he;
+    const double* s_az2 = ktab + lay.az2;
+#pragma unroll
+    for (int m = 0; m < kNMom; ++m) R[m] = lane_sum(R[m], LN);
+
+    // moments of Sec. II from the raw sums (shift to the peculiar velocity xi = p - u)
+    const double n = R[0];
+    const double ux = R[1] / n, uy = R[2] / n;
+    const double pxx = R[3] - n * ux * ux;
+    const double pxy = R[4] - n * ux * uy;
+    const double pyy = R[5] - n * uy * uy;
+    const double tzz = R[8];
+    const double Tm = (pxx + pyy + tzz) / (3.0 * n);
+    const double u2 = ux * ux + uy * uy;
+    const double b = R[3] + R[5];
+    const double c0 = ux * R[1] + uy * R[2];
+    const double cx = ux * R[3] + uy * R[4];
+    const double cy = ux * R[4] + uy * R[5];
+    const double qx = 0.5 * (R[6] - ux * b - 2.0 * cx + 2.0 * ux * c0 + u2 * (R[1] - ux * R[0]) + R[9] - ux * R[8]);
+    const double qy = 0.5 * (R[7] - uy * b - 2.0 * cy + 2.0 * uy * c0 + u2 * (R[2] - uy * R[0]) + R[10] - uy * R[8]);
+
+    // eq. (tau) with mu ~ T^omega (eq. mu) or the tabulated law; Shakhov prefactor (1 - Pr)/(n K_B^2 T^2).
+    // Every lane of the cell evaluates them (the same value): outside a one-lane branch the chain overlaps
+    // the projection below instead of preceding it.
+    double invtau, pr = D.Pr;
+    if (D.ntab > 0) {
+        // tabulated law, eqs. (mun) and (interp): 1/tau = tau_pref n (T/T_w) mu(T_w)/mu(T)
+        double mu;
+        visc_lookup(D.vT, D.vMu, D.vOm, D.vPr, D.ntab, Tm, &mu, &pr);
+        invtau = D.tau_pref * n * (Tm / D.Tw) * (D.mu_w / mu);
+    } else {
+        invtau = D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
+    }
+    if (D.collisionless) invtau = 0.0;
+    const double As = (1.0 - pr) / (n * Tm * Tm);
+    const double As5T = As / (5.0 * Tm);
+
+    if (on && q == 0) {
+        if (flags & (FLAG_STEP_DONE | FLAG_FIELDS)) {
+            double* F = D.fields;
+            F[F_N * nx + s] = n;
+            F[F_UX * nx + s] = ux;
+            F[F_UY * nx + s] = uy;
+            F[F_T * nx + s] = Tm;
+            F[F_PXX * nx + s] = pxx;
+            F[F_PXY * nx + s] = pxy;
+            F[F_PYY * nx + s] = pyy;
+            F[F_TZZ * nx + s] = tzz;
+            F[F_QX * nx + s] = qx;
+            F[F_QY * nx + s] = qy;
+        }
+        sc[SC_UX * nx + s] = ux;
+        sc[SC_UY * nx + s] = uy;
+        sc[SC_T * nx + s] = Tm;
+        sc[SC_INVTAU * nx + s] = invtau;
+        sc[SC_AS * nx + s] = As;
+        sc[SC_AS5T * nx + s] = As5T;
+        sc[SC_QX * nx + s] = qx;
+        sc[SC_QY * nx + s] = qy;
+        if constexpr (!SMALLB) cell[kGIjd * nx + s] = (T)D.inv_jdeta[s];  // the small path fills it once
+        // the band in which the projection of eq. (gx) is verified (a finite state outside it is
+        // flagged; non-finite values are caught by the residual check)
+        const double Tr = Tm / D.Tw;
+        if (Tr < kAuxTlo || Tr > kAuxThi || fabs(ux) > kAuxUmax * sqrt(D.Tw)) D.dyn[DY_RANGE] = 1.0;
+        if ((flags & FLAG_STEP_DONE) && D.dyn[DY_AVG_ON] != 0.0) {
+            // running sums of the fields at the end of every step (time averages, hrlb_average_*)
+            double* A = D.avg;
+            A[F_N * nx + s] += n;
+            A[F_UX * nx + s] += ux;
+            A[F_UY * nx + s] += uy;
+            A[F_T * nx + s] += Tm;
+            A[F_PXX * nx + s] += pxx;
+            A[F_PXY * nx + s] += pxy;
+            A[F_PYY * nx + s] += pyy;
+            A[F_TZZ * nx + s] += tzz;
+            A[F_QX * nx + s] += qx;
+            A[F_QY * nx + s] += qy;
+        }
+    }
+
+    // g_x (eq. gx) and g_y (eq. gy) with the loops over the expansion order unrolled for the case's
+    // padded row count (uniform over the block)
+    switch (nxb) {
+        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        default:
+            if constexpr (!SMALLB)
+                gx_nodes<T, 17>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell);
+            break;
+    }
+    if constexpr (SMALLB) {
+        switch (nyb) {
+            case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+            case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+            default: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        }
+        return;
+    }
+    switch (nyb) {
+        case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 12: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 16: gy_nodes<T, 16>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 20: gy_nodes<T, 20>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 32: gy_nodes<T, 32>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        default: gy_nodes_long<T>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+    }
+}
+
 // at most 128 registers: 4 waves per SIMD (the largest projection bucket spills a few words)
 template <typename T>
 __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4))) void cell_kernel(const InstDesc* __restrict__ descs,
@@ -1133,8 +1262,7 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     // thread issues up to 8 loads before its first LDS write, so the copy takes one memory round
     // trip (up to 2048 doubles: every velocity set up to Qx = 80, Nx = 10) instead of one per table
     // row block
-    const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
-    const CellLds lay = cell_lds(qxn, nqy, nxb, nyb, nyo, uses_aux2(D.cell_lanes));
+    const CellLds lay = cell_lds(D.qx, D.qy, D.nxb, D.nyb, D.nyo, uses_aux2(D.cell_lanes));
     constexpr int kStageBatch = 8;
     for (int base = 0; base < lay.total; base += kStageBatch * kCellThreads) {
         double v[kStageBatch];
@@ -1147,14 +1275,6 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
         }
     }
     __syncthreads();
-    const double* s_wx = ktab + lay.wx;
-    const double* s_wy = ktab + lay.wy;
-    const double* s_az = ktab + lay.az;
-    const double* s_aw = ktab + lay.aw;
-    const double* s_hZ = ktab + lay.hZ;
-    const double* s_hz = ktab + lay.hz;
-    const double* s_he = ktab + lay.he;
-    const double* s_az2 = ktab + lay.az2;
 
     if (!wall_blocks_of_their_own(D.qx, D.qy)) {
         // walls done by the edge blocks: the block holding cell 0 the left wall, the one holding
@@ -1163,99 +1283,361 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (cr.cell0 + kCellThreads / LN >= nx) wall_right<T>(D, fcur);
     }
 
+    cell_tables<T>(D, R, q, LN, s, on, flags, D.sc, (T*)D.cell, ktab, lay);
+}
+
+// ---- small-case kernel ---------------------------------------------------------------------------
+// One workgroup holds one small case in LDS -- its three state buffers, the per-cell tables of the
+// collision, the quadrature tables of eqs. (gx), (gy) and every per-velocity and per-cell constant --
+// and runs n_steps full SSP-RK3 steps in one launch.  Per stage: the wall densities of eq.
+// (diffuse_nw) (both walls in one reduction) and the moments of the stage input (FP64 sums over every
+// velocity of a cell, split over the cell's lanes), the per-cell tables (cell_tables, as in the
+// per-cell kernel), then the update of every (distribution, velocity, 4-cell strip): WENO-5 faces
+// with the wall and mirror ghosts of the tiled path, the FP64 Shakhov collision and the FP64 stage
+// combine.  For cases of a few thousand cell-velocity units, whose tiled steps (six launches) are
+// bound by launch latency; with one block per case, its latency is what remains, so nothing it reads
+// inside the step loop comes from global memory.  The step counter, the fields of the final state, the
+// running averages, the wall densities and, at a checked last step, the residual, the mean P_xy, the
+// mass and the local-time-step rescaling are kept as the tiled path keeps them; the numbers are this
+// path's own (another summation order).
+constexpr int kSmallThreads = 256;
+
+// LDS layout of a small case (bytes from the start of the dynamic LDS)
+struct SmallLds {
+    size_t buf[3], sc, g, ktab, pm, vel, cel, total;
+};
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline int small_lanes(int nx)
+{
+    int ln = kMaxCellLanes;
+    while (ln > 1 && ln * nx > kSmallThreads) ln >>= 1;
+    return ln;
+}
+// per-velocity constants [p_x of the 2 Q_x nodes | p_y of the Q_y nodes | g_w left (nv) | g_w right (nv)]
+// and per-cell ones [dt_s | residual weight | J deta | 1/(J deta)], FP64
+__host__ __device__ inline SmallLds small_lds(int nx, int nv, int qx, int qy, int ktab_total, size_t es)
+{
+    SmallLds o;
+    size_t off = 0;
+    for (int k = 0; k < 3; ++k) {
+        o.buf[k] = off;
+        off = align16(off + es * 2 * (size_t)nv * nx);
+    }
+    o.sc = off;
+    off = align16(off + sizeof(double) * kNSc * nx);
+    o.g = off;
+    off = align16(off + es * (size_t)g_slots(qx, qy) * nx);
+    o.ktab = off;
+    off = align16(off + sizeof(double) * (size_t)ktab_total);
+    o.pm = off;  // per cell: n and P_xy of the last analysed state
+    off = align16(off + sizeof(double) * 2 * (size_t)nx);
+    o.vel = off;
+    off = align16(off + sizeof(double) * (size_t)(2 * qx + qy + 2 * nv));
+    o.cel = off;
+    off = align16(off + sizeof(double) * 4 * (size_t)nx);
+    o.total = off;
+    return o;
+}
+
+// block-wide sums of N values in a fixed order (a shuffle tree per wave, then the waves in order)
+template <int N>
+__device__ inline void small_block_sum(double (&x)[N], double (*red)[N])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int m = 0; m < kNMom; ++m) R[m] = lane_sum(R[m], LN);
+    for (int i = 0; i < N; ++i) {
+        for (int o = 32; o > 0; o >>= 1) x[i] += __shfl_xor(x[i], o, 64);
+        if (lane == 0) red[wave][i] = x[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < kSmallThreads / 64; ++w) s += red[w][i];
+        x[i] = s;
+    }
+    __syncthreads();
+}
 
-    // moments of Sec. II from the raw sums (shift to the peculiar velocity xi = p - u)
-    const double n = R[0];
-    const double ux = R[1] / n, uy = R[2] / n;
-    const double pxx = R[3] - n * ux * ux;
-    const double pxy = R[4] - n * ux * uy;
-    const double pyy = R[5] - n * uy * uy;
-    const double tzz = R[8];
-    const double Tm = (pxx + pyy + tzz) / (3.0 * n);
-    const double u2 = ux * ux + uy * uy;
-    const double b = R[3] + R[5];
-    const double c0 = ux * R[1] + uy * R[2];
-    const double cx = ux * R[3] + uy * R[4];
-    const double cy = ux * R[4] + uy * R[5];
-    const double qx = 0.5 * (R[6] - ux * b - 2.0 * cx + 2.0 * ux * c0 + u2 * (R[1] - ux * R[0]) + R[9] - ux * R[8]);
-    const double qy = 0.5 * (R[7] - uy * b - 2.0 * cy + 2.0 * uy * c0 + u2 * (R[2] - uy * R[0]) + R[10] - uy * R[8]);
+// LDS pointers of a small case
+template <typename T>
+struct SmallPtrs {
+    T *b0, *b1, *b2;                        // state buffers: f^n, stage 1 and stage 2 outputs
+    double* sc;                             // FP64 per-cell scalars [kNSc][nx]
+    T* g;                                   // per-cell table [g_slots][nx]
+    double* ktab;                           // quadrature tables of eqs. (gx), (gy)
+    double* pm;                             // n and P_xy per cell of the last analysed state
+    const double *px, *py, *gwl, *gwr;      // per-velocity constants
+    const double *dts, *jres, *jdeta;       // per-cell constants
+    __device__ __forceinline__ T* buf(int k) const { return k == 0 ? b0 : k == 1 ? b1 : b2; }
+};
 
-    T* cell = (T*)D.cell;
-    if (on && q == 0) {
-        // eq. (tau) with mu ~ T^omega (eq. mu) or the tabulated law; Shakhov prefactor (1 - Pr)/(n K_B^2 T^2)
-        double invtau, pr = D.Pr;
-        if (D.ntab > 0) {
-            // tabulated law, eqs. (mun) and (interp): 1/tau = tau_pref n (T/T_w) mu(T_w)/mu(T)
-            double mu;
-            visc_lookup(D.vT, D.vMu, D.vOm, D.vPr, D.ntab, Tm, &mu, &pr);
-            invtau = D.tau_pref * n * (Tm / D.Tw) * (D.mu_w / mu);
+// walls, moments and per-cell tables of the state f (block-wide); flags as the per-cell kernel's
+// (FLAG_STEP_DONE also counts the step and its average); returns the wall densities
+template <typename T>
+__device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs<T>& S, const T* f, const CellLds& lay, int LN,
+                              int flags, double (*red)[4], double& nwl, double& nwr)
+{
+    const int nx = D.nx, nv = D.nv, qy = D.qy, half = D.qx * qy;
+    const int tid = threadIdx.x;
+    // leaving fluxes through both walls (eq. diffuse_nw): p_x F and p_x p_y F of the leaving face values,
+    // F formed exactly as the per-cell kernel's wall blocks form it; velocity v < half leaves through the
+    // right wall (p_x > 0), v >= half through the left one
+    double w[4] = {0.0, 0.0, 0.0, 0.0};  // left flux, left momentum, right flux, right momentum
+    for (int v = tid; v < 2 * half; v += kSmallThreads) {
+        const bool right = v < half;
+        if (!right && D.half) continue;
+        const T* r = f + (size_t)v * nx;
+        const T F = right ? wall_face_right(r[nx - 3], r[nx - 2], r[nx - 1]) : wall_face_left(r[0], r[1], r[2]);
+        const double pxv = S.px[v / qy], pyv = S.py[v % qy];
+        const double a = pxv * (double)F, b = pxv * pyv * (double)F;
+        if (right) {
+            w[2] += a;
+            w[3] += b;
         } else {
-            invtau = D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
-        }
-        if (D.collisionless) invtau = 0.0;
-        const double As = (1.0 - pr) / (n * Tm * Tm);
-        if (flags & (FLAG_STEP_DONE | FLAG_FIELDS)) {
-            double* F = D.fields;
-            F[F_N * nx + s] = n;
-            F[F_UX * nx + s] = ux;
-            F[F_UY * nx + s] = uy;
-            F[F_T * nx + s] = Tm;
-            F[F_PXX * nx + s] = pxx;
-            F[F_PXY * nx + s] = pxy;
-            F[F_PYY * nx + s] = pyy;
-            F[F_TZZ * nx + s] = tzz;
-            F[F_QX * nx + s] = qx;
-            F[F_QY * nx + s] = qy;
-        }
-        double* sc = D.sc;
-        sc[SC_UX * nx + s] = ux;
-        sc[SC_UY * nx + s] = uy;
-        sc[SC_T * nx + s] = Tm;
-        sc[SC_INVTAU * nx + s] = invtau;
-        sc[SC_AS * nx + s] = As;
-        sc[SC_AS5T * nx + s] = As / (5.0 * Tm);
-        sc[SC_QX * nx + s] = qx;
-        sc[SC_QY * nx + s] = qy;
-        cell[kGIjd * nx + s] = (T)D.inv_jdeta[s];
-        // the band in which the projection of eq. (gx) is verified (a finite state outside it is
-        // flagged; non-finite values are caught by the residual check)
-        const double Tr = Tm / D.Tw;
-        if (Tr < kAuxTlo || Tr > kAuxThi || fabs(ux) > kAuxUmax * sqrt(D.Tw)) D.dyn[DY_RANGE] = 1.0;
-        if ((flags & FLAG_STEP_DONE) && D.dyn[DY_AVG_ON] != 0.0) {
-            // running sums of the fields at the end of every step (time averages, hrlb_average_*)
-            double* A = D.avg;
-            A[F_N * nx + s] += n;
-            A[F_UX * nx + s] += ux;
-            A[F_UY * nx + s] += uy;
-            A[F_T * nx + s] += Tm;
-            A[F_PXX * nx + s] += pxx;
-            A[F_PXY * nx + s] += pxy;
-            A[F_PYY * nx + s] += pyy;
-            A[F_TZZ * nx + s] += tzz;
-            A[F_QX * nx + s] += qx;
-            A[F_QY * nx + s] += qy;
+            w[0] += a;
+            w[1] += b;
         }
     }
+    small_block_sum<4>(w, red);
+    nwl = D.half ? 0.0 : -w[0] / D.den_l;
+    nwr = -w[2] / D.den_r;
+    const int q = tid % LN;
+#pragma unroll 1
+    for (int c0 = 0; c0 < nx; c0 += kSmallThreads / LN) {
+        const int s = c0 + tid / LN;
+        const bool on = s < nx;
+        const int sc_ = on ? s : 0;
+        // raw sums of Sec. II's moments over the velocities v = q, q + LN, ... of the cell
+        double R[kNMom];
+#pragma unroll
+        for (int m = 0; m < kNMom; ++m) R[m] = 0.0;
+        for (int v = q; v < nv; v += LN) {
+            const double pxv = S.px[v / qy], pyv = S.py[v % qy];
+            const double o = (double)f[(size_t)v * nx + sc_], x = (double)f[(size_t)(nv + v) * nx + sc_];
+            const double p2 = pxv * pxv + pyv * pyv;
+            R[0] += o;
+            R[1] += pxv * o;
+            R[2] += pyv * o;
+            R[3] += pxv * pxv * o;
+            R[4] += pxv * pyv * o;
+            R[5] += pyv * pyv * o;
+            R[6] += p2 * pxv * o;
+            R[7] += p2 * pyv * o;
+            R[8] += x;
+            R[9] += pxv * x;
+            R[10] += pyv * x;
+        }
+        cell_tables<T, true>(D, R, q, LN, s, on, flags, S.sc, S.g, S.ktab, lay);
+        if (on && q == 0) {
+            // the same arithmetic as the fields of cell_tables: n and P_xy of the cell
+            const double n = R[0], ux = R[1] / n, uy = R[2] / n;
+            S.pm[s] = n;
+            S.pm[nx + s] = R[4] - n * ux * uy;
+        }
+    }
+    if (tid == 0) {
+        D.dyn[DY_NWL] = nwl;
+        D.dyn[DY_NWR] = nwr;
+        D.dyn[DY_SHEAR_L] = D.half ? 0.0 : w[1] + nwl * D.mom_l;
+        D.dyn[DY_SHEAR_R] = w[3] + nwr * D.mom_r;
+        if (flags & FLAG_STEP_DONE) {
+            D.dyn[DY_STEP] += 1.0;
+            if (D.dyn[DY_AVG_ON] != 0.0) D.dyn[DY_AVG_STEPS] += 1.0;
+        }
+    }
+    __syncthreads();
+}
 
-    // g_x (eq. gx) and g_y (eq. gy) with the loops over the expansion order unrolled for the case's
-    // padded row count (uniform over the block)
-    switch (nxb) {
-        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        default: gx_nodes<T, 17>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+// one SSP-RK3 stage from fin (f^n in S.b0) into fout, each item one distribution of one velocity over 4
+// cells; residual partials on request
+template <typename T>
+__device__ __forceinline__ void small_update(const InstDesc& D, const SmallPtrs<T>& S, const T* fin, T* fout, int stage,
+                             uint32_t stepc, bool want_res, double nwl, double nwr, double& rnum, double& rden)
+{
+    const int nx = D.nx, nv = D.nv, qx = D.qx, qy = D.qy;
+    const double ca = stage == 1 ? 0.75 : stage == 2 ? (1.0 / 3.0) : 0.0;
+    const double cb = stage == 1 ? 0.25 : stage == 2 ? (2.0 / 3.0) : 1.0;
+    const uint32_t rkey = D.rounding ? hash32(D.seed ^ hash32(stepc * 3u + (uint32_t)stage + 0x9e3779b9u)) : 0u;
+    const int nstrip = nx / kStrip, per_dist = nv * nstrip;
+    const T* fn = S.b0;
+#pragma unroll 1
+    for (int it = threadIdx.x; it < 2 * per_dist; it += kSmallThreads) {
+        const int d = it >= per_dist, r = it - d * per_dist;
+        const int v = r / nstrip, s0 = (r - v * nstrip) * kStrip;
+        const int hi = v / qy, j = v - hi * qy;
+        const double pxd = S.px[hi], pyd = S.py[j];
+        const T pxt = (T)pxd;
+        const bool first = s0 == 0 && !D.half, mirror = s0 == 0 && D.half, last = s0 + kStrip == nx;
+        const size_t row = (size_t)(d * nv + v) * nx;
+        const T* fr = fin + row;
+        Win<T> P;
+        // window cells s0-4 .. s0+7; the tiled path's loads: cells 0..3 for the left window of the strip
+        // at cell 0, cells s0..s0+3 for the right window of the last strip (the ghost logic below replaces
+        // whatever of them the faces read)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            P.w[c] = fr[s0 == 0 ? c : s0 - 4 + c];
+            P.w[4 + c] = fr[s0 + c];
+            P.w[8 + c] = fr[last ? s0 + c : s0 + 4 + c];
+        }
+        if (mirror) {
+            // point symmetry of Sec. II about x = 0: ghost cells -1..-4 of (p_x, p_y) hold the values of
+            // (-p_x, -p_y) in cells 0..3
+            const int hmir = hi < qx ? hi + qx : hi - qx;
+            const T* fm = fin + (size_t)(d * nv + hmir * qy + (qy - 1 - j)) * nx;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) P.w[3 - c] = fm[c];
+        }
+        // wall populations (eq. diffuse): n_w g_w for phi, T_w n_w g_w for chi
+        const double sl = d ? D.Tw * nwl : nwl, sr = d ? D.Tw * nwr : nwr;
+        const T wl = first ? (T)(sl * S.gwl[v]) : T(0), wr = last ? (T)(sr * S.gwr[v]) : T(0);
+        T F[5];
+        if (pxt > T(0)) {
+            if (first) P.w[1] = P.w[2] = P.w[3] = wl;
+            if (last) {
+                P.w[8] = ext_p3(P.w[5], P.w[6], P.w[7]);
+                P.w[9] = ext_p4(P.w[5], P.w[6], P.w[7]);
+            }
+            P.faces_pos(F);
+            if (first) F[0] = wl;
+        } else {
+            if (first) {
+                P.w[3] = ext_m1(P.w[4], P.w[5], P.w[6]);
+                P.w[2] = ext_m2(P.w[4], P.w[5], P.w[6]);
+            }
+            if (last) P.w[8] = P.w[9] = P.w[10] = wr;
+            P.faces_neg(F);
+            if (last) F[4] = wr;
+        }
+        uint32_t rbits[kStrip] = {0, 0, 0, 0};
+        if (D.rounding) {
+            const uint32_t base = rkey ^ ((uint32_t)v * 0x85ebca6bu) ^ ((uint32_t)s0 * 0xc2b2ae35u);
+#pragma unroll
+            for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : xorshift32(rbits[c - 1]);
+        }
+#pragma unroll
+        for (int c = 0; c < kStrip; ++c) {
+            const int s = s0 + c;
+            const T fv = P.w[4 + c];
+            const double* sc = S.sc + s;
+            const double ux = sc[SC_UX * nx], uy = sc[SC_UY * nx], itau = sc[SC_INVTAU * nx];
+            const double AS = sc[SC_AS * nx], A5 = sc[SC_AS5T * nx], qxv = sc[SC_QX * nx], qyv = sc[SC_QY * nx];
+            const T ijd = S.g[kGIjd * nx + s];
+            const T gy = S.g[(kGx0 + 2 * qx + j) * nx + s];
+            const T gx = S.g[(kGx0 + hi) * nx + s];
+            // reduced Shakhov collision, Sec. II, in FP64 (as the tiled path): phi relaxes to
+            // phi_eq (1 + S_phi), chi to T phi_eq (1 + S_chi)
+            const double xx = pxd - ux, xy = pyd - uy;
+            const double x2 = xx * xx + xy * xy;
+            const double qxi = qxv * xx + qyv * xy;
+            const double feq = (double)gx * (double)gy;
+            const double tg = d ? sc[SC_T * nx] * (feq + feq * (qxi * (A5 * x2 - 0.4 * AS)))
+                                : feq + feq * (qxi * (A5 * x2 - 0.8 * AS));
+            const T a = -pxt * (F[c + 1] - F[c]) * ijd;
+            const double L = (double)a + (tg - (double)fv) * itau;
+            const double fnd = stage > 0 ? (double)fn[row + s] : 0.0;
+            const double oe = ca * fnd + cb * ((double)fv + S.dts[s] * L);
+            // stage 3 writes f^n in place: f^n is read only at an item's own cells, by that item
+            fout[row + s] = store_round<T>(oe, D.rounding, d ? rbits[c] >> 16 : rbits[c]);
+            if (want_res) {
+                const double dd = oe - fnd;
+                rnum += S.jres[s] * (dd * dd);
+                rden += S.jdeta[s] * (fnd * fnd);
+            }
+        }
     }
-    switch (nyb) {
-        case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 12: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 16: gy_nodes<T, 16>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 20: gy_nodes<T, 20>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 32: gy_nodes<T, 32>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        default: gy_nodes_long<T>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+    __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __restrict__ descs, int n_steps,
+                                                                int check)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    __shared__ double red[kSmallThreads / 64][4];
+    const InstDesc& D = descs[blockIdx.x];
+    const int nx = D.nx, nv = D.nv, qx = D.qx, qy = D.qy;
+    const int LN = small_lanes(nx);
+    const CellLds lay = cell_lds(qx, qy, D.nxb, D.nyb, D.nyo, uses_aux2(LN));
+    const SmallLds L = small_lds(nx, nv, qx, qy, lay.total, sizeof(T));
+    double* vel = (double*)(lds + L.vel);
+    double* cel = (double*)(lds + L.cel);
+    SmallPtrs<T> S;
+    S.b0 = (T*)(lds + L.buf[0]);
+    S.b1 = (T*)(lds + L.buf[1]);
+    S.b2 = (T*)(lds + L.buf[2]);
+    S.sc = (double*)(lds + L.sc);
+    S.g = (T*)(lds + L.g);
+    S.ktab = (double*)(lds + L.ktab);
+    S.pm = (double*)(lds + L.pm);
+    S.px = vel;
+    S.py = vel + 2 * qx;
+    S.gwl = vel + 2 * qx + qy;
+    S.gwr = vel + 2 * qx + qy + nv;
+    S.dts = cel;
+    S.jres = cel + nx;
+    S.jdeta = cel + 2 * nx;
+    const int tid = threadIdx.x;
+    // the state, the quadrature tables and the constants into LDS
+    const T* f0 = (const T*)D.f[0];
+    const size_t nst = 2 * (size_t)nv * nx;
+    for (size_t k = tid; k < nst; k += kSmallThreads) S.b0[k] = f0[k];
+    for (int k = tid; k < lay.total; k += kSmallThreads) S.ktab[k] = ktab_source(D, lay, k);
+    for (int k = tid; k < 2 * qx; k += kSmallThreads) vel[k] = D.px[k];
+    for (int k = tid; k < qy; k += kSmallThreads) vel[2 * qx + k] = D.py[k];
+    for (int k = tid; k < nv; k += kSmallThreads) {
+        vel[2 * qx + qy + k] = D.gw_l[k];
+        vel[2 * qx + qy + nv + k] = D.gw_r[k];
     }
+    for (int k = tid; k < nx; k += kSmallThreads) {
+        cel[k] = D.dts[k];
+        cel[nx + k] = D.jres[k];
+        cel[2 * nx + k] = D.jdeta[k];
+        S.g[kGIjd * nx + k] = (T)D.inv_jdeta[k];
+    }
+    __syncthreads();
+    uint32_t stepc = (uint32_t)D.dyn[DY_STEP];
+    double nwl = 0.0, nwr = 0.0;
+    small_analyze<T>(D, S, S.b0, lay, LN, 0, red, nwl, nwr);
+    double rnum = 0.0, rden = 0.0;
+#pragma unroll 1
+    for (int k = 0; k < 3 * n_steps; ++k) {
+        // stage 1: f^n -> b1; stage 2: (b1, f^n) -> b2; stage 3: (b2, f^n) -> f^n in place
+        const int stage = k % 3;
+        const bool res = check && k + 1 == 3 * n_steps;
+        T* fin = S.buf(stage);
+        T* fout = S.buf(stage == 2 ? 0 : stage + 1);
+        small_update<T>(D, S, fin, fout, stage, stepc, res, nwl, nwr, rnum, rden);
+        if (stage == 2) ++stepc;
+        small_analyze<T>(D, S, fout, lay, LN, stage == 2 ? FLAG_STEP_DONE : 0, red, nwl, nwr);
+    }
+    if (check) {
+        // residual, J-weighted mean P_xy and mass of the final state, as the tiled path's check
+        double r[4] = {rnum, rden, 0.0, 0.0};
+        for (int s = tid; s < nx; s += kSmallThreads) {
+            r[2] += S.jdeta[s] * S.pm[nx + s];
+            r[3] += S.jdeta[s] * S.pm[s];
+        }
+        small_block_sum<4>(r, red);
+        if (tid == 0) {
+            D.dyn[DY_RES_NUM] = r[0];
+            D.dyn[DY_RES_DEN] = r[1];
+            D.dyn[DY_PXY_MEAN] = r[2] / D.jsum;
+            D.dyn[DY_MASS] = r[3];
+            const double chk = r[0] + r[1] + r[2] + r[3];
+            if (!(chk == chk) || chk - chk != 0.0) D.dyn[DY_FLAGS] = 1.0;
+        }
+        if (D.lts) {
+            // local time steps: back to the rest-state mass, then the moments of the rescaled state
+            const double scale = D.jsum / r[3];
+            for (size_t k = tid; k < nst; k += kSmallThreads) S.b0[k] = (T)((double)S.b0[k] * scale);
+            __syncthreads();
+            small_analyze<T>(D, S, S.b0, lay, LN, FLAG_FIELDS, red, nwl, nwr);
+        }
+    }
+    T* fo = (T*)D.f[0];
+    for (size_t k = tid; k < nst; k += kSmallThreads) fo[k] = S.b0[k];
 }
 
 // ---- per-instance reductions at a check point: residual, mean P_xy, mass ----------------------
@@ -1449,6 +1831,27 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_cell(int fp32,
         hipLaunchKernelGGL(cell_kernel<float>, dim3(ncells), dim3(kCellThreads), shmem, st, descs, cells, buf, flags);
     else
         hipLaunchKernelGGL(cell_kernel<double>, dim3(ncells), dim3(kCellThreads), shmem, st, descs, cells, buf, flags);
+    return hipGetLastError();
+}
+
+// bytes of dynamic LDS the small-case kernel needs for one instance
+extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_small_lds(const InstDesc* D)
+{
+    const int LN = small_lanes(D->nx);
+    const CellLds lay = cell_lds(D->qx, D->qy, D->nxb, D->nyb, D->nyo, uses_aux2(LN));
+    return small_lds(D->nx, D->nv, D->qx, D->qy, lay.total, D->precision == 1 ? sizeof(float) : sizeof(double)).total;
+}
+
+// n_steps steps of every small instance of descs (one block each); check: the last step is checked
+extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_small(int fp32, const InstDesc* descs, int ninst,
+                                                                          int n_steps, int check, size_t lds,
+                                                                          hipStream_t st)
+{
+    if (ninst <= 0 || n_steps <= 0) return hipSuccess;
+    if (fp32)
+        hipLaunchKernelGGL(small_kernel<float>, dim3(ninst), dim3(kSmallThreads), lds, st, descs, n_steps, check);
+    else
+        hipLaunchKernelGGL(small_kernel<double>, dim3(ninst), dim3(kSmallThreads), lds, st, descs, n_steps, check);
     return hipGetLastError();
 }
 

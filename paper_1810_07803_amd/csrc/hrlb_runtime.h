@@ -22,6 +22,9 @@ extern "C" hipError_t hrlbk_finalize(const hrlb::InstDesc* descs, int ninst, int
 extern "C" hipError_t hrlbk_init(int fp32, const hrlb::InstDesc* descs, int inst, size_t units, hipStream_t st);
 extern "C" hipError_t hrlbk_average(const hrlb::InstDesc* desc, int start, int nx, hipStream_t st);
 extern "C" hipError_t hrlbk_scratch(void** ptr, size_t* bytes);
+extern "C" size_t hrlbk_small_lds(const hrlb::InstDesc* D);
+extern "C" hipError_t hrlbk_small(int fp32, const hrlb::InstDesc* descs, int ninst, int n_steps, int check, size_t lds,
+                                  hipStream_t st);
 
 namespace hrlb {
 
@@ -71,6 +74,9 @@ struct Launcher {
     size_t shmem = 0;
     int qy_max = 0;
     bool any_lts = false;  // some instance takes local time steps: rescale + re-analyse after checks
+    const InstDesc* small_descs = nullptr;  // instances on the small-case kernel (one block each)
+    int nsmall = 0;
+    size_t small_lds = 0;                   // dynamic LDS of that launch (its largest instance)
     hipStream_t stream = nullptr;
     int graph_steps = 0;  // steps per captured graph; < 2 launches directly (faster on this stack)
     int graph_len = 0;
@@ -153,6 +159,8 @@ struct hrlb_case {
     double mass0;
     std::vector<double> x, jdeta;
     bool needs_analyze;  // moments/tables of the stored state not computed yet
+    bool small;          // advanced by the small-case kernel (kernel_path)
+    size_t small_lds;    // its dynamic LDS
     int static_dev;      // device whose static scratch holds the auxiliary region, -1 for a workspace case
     unsigned long static_gen;  // generation of that static case (hrlb::case_live)
     hrlb::Launcher run;
@@ -160,8 +168,9 @@ struct hrlb_case {
 
 // cases of a batch advanced on one stream by shared launches
 struct hrlb_batch_part {
-    std::vector<int> idx;  // indices into hrlb_batch::cases, ascending
-    hrlb::InstDesc* d_descs = nullptr;
+    std::vector<int> idx;  // indices into hrlb_batch::cases, ascending: the tiled cases, then the small ones
+    int ntiled = 0;        // the first ntiled of idx run the tiled kernels, the rest the small-case kernel
+    hrlb::InstDesc* d_descs = nullptr;  // descriptors of idx in that order
     hrlb::TileRef* d_tiles = nullptr;
     hrlb::CellRef* d_cells = nullptr;
     unsigned* d_ctr = nullptr;

@@ -21,6 +21,7 @@ HRLB_FLAG_NONFINITE, HRLB_FLAG_RANGE = 1, 2
 HRLB_FP64, HRLB_FP32_STORE_FP64_MOM = 0, 1
 HRLB_ROUND_NEAREST, HRLB_ROUND_STOCHASTIC = 0, 1
 HRLB_STOP_RESIDUAL, HRLB_STOP_PXY = 0, 1
+HRLB_PATH_AUTO, HRLB_PATH_TILED, HRLB_PATH_SMALL = 0, 1, 2
 
 FIELD_NAMES = ("n", "u_x", "u_y", "T", "P_xx", "P_xy", "P_yy", "T_zz", "q_x", "q_y")
 
@@ -28,7 +29,7 @@ EXPORTED = (
     "hrlb_init_quadrature", "hrlb_quadrature_nodes", "hrlb_case_workspace_bytes", "hrlb_init_case",
     "hrlb_case_state_bytes", "hrlb_init_case_static",
     "hrlb_step", "hrlb_run_to_steady", "hrlb_moments", "hrlb_get_state", "hrlb_set_state",
-    "hrlb_case_info", "hrlb_case_flags", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
+    "hrlb_case_info", "hrlb_case_flags", "hrlb_case_kernel_path", "hrlb_free_case", "hrlb_free_quadrature", "hrlb_last_error",
     "hrlb_batch_workspace_bytes", "hrlb_batch_create", "hrlb_batch_step", "hrlb_batch_poll",
     "hrlb_batch_free", "hrlb_batch_profile", "hrlb_batch_set_streams", "hrlb_case_set_graph_steps",
     "hrlb_batch_set_graph_steps",
@@ -52,7 +53,7 @@ class CaseParams(C.Structure):
         ("precision", C.c_int), ("rounding", C.c_int), ("cfl", C.c_double), ("dt", C.c_double),
         ("seed", C.c_uint), ("tile_vpt", C.c_int), ("cell_lanes", C.c_int), ("half_channel", C.c_int),
         ("visc_table_n", C.c_int), ("visc_T", C.POINTER(C.c_double)), ("visc_mu", C.POINTER(C.c_double)),
-        ("visc_Pr", C.POINTER(C.c_double)), ("local_dt_cap", C.c_double),
+        ("visc_Pr", C.POINTER(C.c_double)), ("local_dt_cap", C.c_double), ("kernel_path", C.c_int),
     ]
 
 
@@ -115,6 +116,7 @@ def load() -> C.CDLL:
                 "hrlb_set_state": [vp, dp],
                 "hrlb_case_info": [vp, dp, ip, ip, C.POINTER(C.c_long)],
                 "hrlb_case_flags": [vp, C.POINTER(C.c_uint)],
+                "hrlb_case_kernel_path": [vp, ip],
                 "hrlb_batch_workspace_bytes": [C.POINTER(vp), C.c_int, C.POINTER(C.c_size_t)],
                 "hrlb_batch_create": [C.POINTER(vp), C.c_int, vp, C.c_size_t, C.POINTER(vp)],
                 "hrlb_batch_step": [vp, C.c_long, C.c_int],
@@ -189,12 +191,13 @@ def init_quadrature(Qx, Nx, Qy, Ny, p0=1.0) -> Quadrature:
 
 def make_params(*, delta, uw, ncell, stretch_A=0.0, Tw=1.0, Pr=2.0 / 3.0, omega=0.7, precision=HRLB_FP64,
                 rounding=HRLB_ROUND_NEAREST, cfl=0.5, dt=0.0, seed=0, tile_vpt=0, cell_lanes=0,
-                half_channel=0, visc_table=None, local_dt_cap=0.0) -> CaseParams:
+                half_channel=0, visc_table=None, local_dt_cap=0.0, kernel_path=HRLB_PATH_AUTO) -> CaseParams:
     """Case parameters.  visc_table: rows (T_k, mu_k, Pr_k) of the tabulated transport law (copied by
     the library when the case is created; the returned struct keeps the arrays alive until then)."""
     p = CaseParams(delta, uw, Tw, Pr, omega, ncell, stretch_A, precision, rounding, cfl, dt, seed & 0xFFFFFFFF,
                    tile_vpt, cell_lanes, int(half_channel))
     p.local_dt_cap = float(local_dt_cap)
+    p.kernel_path = int(kernel_path)
     if visc_table is not None:
         cols = [np.ascontiguousarray(c, dtype=np.float64) for c in np.asarray(visc_table, np.float64).T]
         p.visc_table_n = len(cols[0])
@@ -311,6 +314,12 @@ class Case:
         f = C.c_uint()
         _check(load().hrlb_case_flags(self.handle, C.byref(f)))
         return f.value
+
+    def kernel_path(self) -> int:
+        """HRLB_PATH_TILED or HRLB_PATH_SMALL: the kernels that advance this case."""
+        p = C.c_int()
+        _check(load().hrlb_case_kernel_path(self.handle, C.byref(p)))
+        return p.value
 
     def steps_done(self) -> int:
         sd = C.c_long()

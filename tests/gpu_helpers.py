@@ -16,8 +16,9 @@ def say(*args):
 
 
 def make_pair(Qx, Qy, ncell, *, stretch_A=0.0, delta=1.0, uw=0.05, Tw=1.0, Pr=2.0 / 3.0, omega=0.7,
-              precision=0, rounding=0, dt=0.0, cfl=0.5, seed=0, half_channel=False, Nx=None, Ny=None):
-    """(gpu_case, oracle_problem) sharing dt; the oracle picks dt by the same rule when dt <= 0."""
+              precision=0, rounding=0, dt=0.0, cfl=0.5, seed=0, half_channel=False, Nx=None, Ny=None, path=1):
+    """(gpu_case, oracle_problem) sharing dt; the oracle picks dt by the same rule when dt <= 0.  path: the
+    GPU case's kernel path (default the tiled kernels; the small-case path has tests of its own)."""
     from oracle.oracle import OracleProblem
     from paper_1810_07803_amd import hrlb
 
@@ -27,7 +28,7 @@ def make_pair(Qx, Qy, ncell, *, stretch_A=0.0, delta=1.0, uw=0.05, Tw=1.0, Pr=2.
     q = hrlb.Quadrature(Qx, Qy, orc.Nx, orc.Ny)
     params = hrlb.make_params(delta=delta, uw=uw, ncell=ncell, stretch_A=stretch_A, Tw=Tw, Pr=Pr, omega=omega,
                               precision=precision, rounding=rounding, cfl=cfl, dt=orc.dt, seed=seed,
-                              half_channel=int(half_channel))
+                              half_channel=int(half_channel), kernel_path=path)
     case = hrlb.Case(q, params)
     case._quad_ref = q
     return case, orc

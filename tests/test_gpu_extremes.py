@@ -10,7 +10,7 @@ from tests.gpu_helpers import make_pair, parity, say
 pytestmark = pytest.mark.gpu
 
 
-def _parity(Qx, Qy, nx, steps, tol, *, precision=0, rounding=0, Nx=None, half=False, tile_vpt=0, **kw):
+def _parity(Qx, Qy, nx, steps, tol, *, precision=0, rounding=0, Nx=None, half=False, tile_vpt=0, path=1, **kw):
     from oracle.oracle import OracleProblem
     from paper_1810_07803_amd import hrlb
 
@@ -18,7 +18,7 @@ def _parity(Qx, Qy, nx, steps, tol, *, precision=0, rounding=0, Nx=None, half=Fa
     q = hrlb.Quadrature(Qx, Qy, orc.Nx, orc.Ny)
     case = hrlb.Case(q, hrlb.make_params(delta=kw["delta"], uw=kw["uw"], ncell=nx, stretch_A=kw.get("stretch_A", 0.0),
                                          precision=precision, rounding=rounding, dt=orc.dt, seed=5,
-                                         half_channel=int(half), tile_vpt=tile_vpt))
+                                         half_channel=int(half), tile_vpt=tile_vpt, kernel_path=path))
     case._quad_ref = q
     phi, chi = orc.init_state()
     phi, chi = perturb(phi, 0.05, 61), perturb(chi, 0.05, 62)
@@ -31,10 +31,11 @@ def _parity(Qx, Qy, nx, steps, tol, *, precision=0, rounding=0, Nx=None, half=Fa
 
 @pytest.mark.parametrize("precision,rounding,tol", [(0, 0, 1e-12), (1, 1, 1e-5)])
 @pytest.mark.parametrize("half", [False, True])
-def test_smallest_grid_and_velocity_set(precision, rounding, tol, half):
-    say("[extremes] 8 cells, HHLB(2;3) x HLB(2;3)")
+@pytest.mark.parametrize("path", [1, 2])
+def test_smallest_grid_and_velocity_set(precision, rounding, tol, half, path):
+    say(f"[extremes] 8 cells, HHLB(2;3) x HLB(2;3), kernel path {path}")
     assert _parity(3, 3, 8, 30, tol, precision=precision, rounding=rounding, half=half, delta=1.0, uw=0.4,
-                   stretch_A=0.9)
+                   stretch_A=0.9, path=path)
 
 
 @pytest.mark.parametrize("precision,rounding,tol", [(0, 0, 1e-12), (1, 1, 1e-5)])
