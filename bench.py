@@ -54,6 +54,13 @@ WORKLOADS = {
     # the same trace with local time steps (steady-state acceleration, cap 64)
     "couette_serve_poisson200_lts": dict(kind="serve", precision=1, rounding=1, requests=64, rate=200.0,
                                          tol=2e-6, max_steps=100000, check_every=1000, local_dt_cap=64.0),
+    # the serving metric: each solve stops once the estimated remaining error of its mean P_xy is below
+    # 3e-6 on two checks (the rule that keeps every oracle-checked calibration draw within 1e-5 of the
+    # oracle's steady state), local time steps, at most 1M steps; the default run serves the first 32
+    # requests of this trace next to the batch
+    "couette_serve_poisson200_pxyerr": dict(kind="serve", precision=1, rounding=1, requests=64, rate=200.0,
+                                            tol=3e-6, stop_rule=2, max_steps=1000000, check_every=500,
+                                            local_dt_cap=64.0),
     # the quadrature-convergence claim of Sec. IV in its own setting: half channel, A = 0.98,
     # u_w = sqrt(2 K_B T_w/m), delta in {10, 1, 0.1}; the production models HHLB(6;7) x HLB(6;7)
     # (delta = 10, 1) and HHLB(10;16) x HLB(6;7) (delta = 0.1) on S = 16 cells against the reference
@@ -144,13 +151,14 @@ def _cpu_baseline(insts, budget_s: float, half: bool = False):
                       f"({units} cell·velocity updates in {dt:.1f} s)"}
 
 
-def _serve_main(args, spec):
-    """Serving workload: requests arrive on a Poisson trace and are served with continuous batching."""
+def _serve_trace(args, spec, n_requests, wall_limit_s):
+    """Serves a Poisson trace of n_requests solves drawn like the ragged batch with Nx up to 2048 (seed 1,
+    arrivals seed 2) with continuous batching; returns (summary, totals)."""
     from hrlb_inputs import batch_draws, poisson_arrivals
     from paper_1810_07803_amd import hrlb, serve
 
-    reqs = batch_draws(spec["requests"], seed=1, nx_choices=(64, 128, 256, 512, 1024, 2048))
-    arrivals = poisson_arrivals(spec["requests"], spec["rate"], seed=2)
+    reqs = batch_draws(n_requests, seed=1, nx_choices=(64, 128, 256, 512, 1024, 2048))
+    arrivals = poisson_arrivals(n_requests, spec["rate"], seed=2)
     arrivals = arrivals - arrivals[0]
     srv = hrlb.Server(args.arena_mib << 20, max_active=256, check_every=spec["check_every"], max_bypass=4,
                       precision=spec["precision"])
@@ -161,11 +169,28 @@ def _serve_main(args, spec):
         pass
     print(f"# serving {len(reqs)} requests", file=sys.stderr, flush=True)
     records, tot = serve.run_trace(srv, reqs, arrivals, tol=spec["tol"], max_steps=spec["max_steps"],
-                                   wall_limit_s=args.serve_wall_s, local_dt_cap=spec.get("local_dt_cap", 0.0))
+                                   stop_rule=spec.get("stop_rule", hrlb.HRLB_STOP_PXY), wall_limit_s=wall_limit_s,
+                                   local_dt_cap=spec.get("local_dt_cap", 0.0))
     summ = serve.latency_summary(records)
     summ["solves_per_s"] = summ["finished"] / tot["wall_s"]
+    summ["updates_per_s"] = tot["units"] / tot["wall_s"]
     summ["rounds"] = tot["rounds"]
     summ["wall_s"] = tot["wall_s"]
+    srv.free()
+    return summ, tot, reqs
+
+
+def _stop_desc(spec):
+    from paper_1810_07803_amd import hrlb
+
+    rule = {hrlb.HRLB_STOP_PXY: "pxy_drift", hrlb.HRLB_STOP_PXY_ERR: "pxy_error_estimate",
+            hrlb.HRLB_STOP_RESIDUAL: "residual"}[spec.get("stop_rule", hrlb.HRLB_STOP_PXY)]
+    return {"rule": rule, "tol": spec["tol"], "max_steps": spec["max_steps"], "check_every": spec["check_every"]}
+
+
+def _serve_main(args, spec):
+    """Serving workload: requests arrive on a Poisson trace and are served with continuous batching."""
+    summ, tot, reqs = _serve_trace(args, spec, spec["requests"], args.serve_wall_s)
     out = {
         "metric": "cell·velocity updates/s",
         "value": tot["units"] / tot["wall_s"],
@@ -174,8 +199,7 @@ def _serve_main(args, spec):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "moments_dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "requests": len(reqs), "arrival_rate_per_s": spec["rate"],
-                   "stop": {"rule": "pxy_drift", "tol": spec["tol"], "max_steps": spec["max_steps"],
-                            "check_every": spec["check_every"]},
+                   "stop": _stop_desc(spec),
                    "arena_mib": args.arena_mib, "local_dt_cap": spec.get("local_dt_cap", 0.0),
                    "parallelism": "single GPU, continuous batching"},
         "serving": summ,
@@ -320,6 +344,10 @@ def main(argv=None):
                     "long-row plan (up to 16); default: the workload's own choice")
     ap.add_argument("--arena-mib", type=int, default=4096, help="serving: device arena for resident solves")
     ap.add_argument("--serve-wall-s", type=float, default=240.0, help="serving: wall-clock limit of the trace")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="default workload: requests of the serving trace run after the batch (0 skips it)")
+    ap.add_argument("--serve-leg-wall-s", type=float, default=180.0,
+                    help="default workload: wall-clock limit of that serving trace")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -404,6 +432,21 @@ def main(argv=None):
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         cpu = _cpu_baseline(insts, args.cpu_seconds, half=bool(spec.get("half")))
 
+    # the serving half of the metric: solves/s and time to steady at a fixed P_xy error, on a bounded trace
+    serving = None
+    n_inst = len(cases)
+    if args.serve_requests > 0 and args.workload == "couette_batch512_ragged_fp32":
+        batch.free()
+        for c in cases:
+            c.free()
+        del cases, batch
+        sspec = WORKLOADS["couette_serve_poisson200_pxyerr"]
+        summ, _, reqs = _serve_trace(args, sspec, args.serve_requests, args.serve_leg_wall_s)
+        serving = dict(summ, workload="couette_serve_poisson200_pxyerr", requests=len(reqs),
+                       arrival_rate_per_s=sspec["rate"], stop=_stop_desc(sspec),
+                       local_dt_cap=sspec["local_dt_cap"], dtype="f32", moments_dtype="f64",
+                       target="mean P_xy within 1e-5 of the steady state")
+
     out = {
         "metric": "cell·velocity updates/s",
         "value": value,
@@ -418,7 +461,7 @@ def main(argv=None):
         "dtype": "f32" if es == 4 else "f64",
         "moments_dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "instances": len(cases), "units_per_step": units,
+        "config": {"workload": args.workload, "instances": n_inst, "units_per_step": units,
                    "half_channel": bool(spec.get("half")),
                    "graph_steps": args.graph_steps, "streams": args.streams, "rows": rows, "cell_lanes": lanes,
                    "tuned_plan": {"tile_vpt": tuned[0], "cell_lanes": tuned[1]} if tuned else None,
@@ -426,6 +469,7 @@ def main(argv=None):
         "wall_s_timed": wall,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0

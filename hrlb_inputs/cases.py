@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["SINGLE_CASES", "case", "batch_draws", "poisson_arrivals", "perturb"]
+__all__ = ["SINGLE_CASES", "case", "batch_draws", "poisson_arrivals", "perturb", "steady_calibration_draws"]
 
 # The single-instance workloads (plain and mixed-precision).  A = 0 means a uniform grid.
 SINGLE_CASES = {
@@ -54,3 +54,22 @@ def perturb(arr: np.ndarray, amp: float, seed: int) -> np.ndarray:
     """Multiply an array elementwise by (1 + amp * U(-1, 1)), seeded."""
     rng = np.random.default_rng(seed)
     return arr * (1.0 + amp * rng.uniform(-1.0, 1.0, size=arr.shape))
+
+
+def steady_calibration_draws(n: int = 8, seed: int = 5) -> list[dict]:
+    """Small solves drawn from the serving workload's parameter ranges, at sizes whose steady states the
+    FP64 oracle reaches in minutes: delta = 10^U(-1, 2) (the serving range starts at 10^-2, whose
+    strongly rarefied solves take the oracle hours), u_w ~ U(0.01, 0.5), omega ~ U(0.5, 1.0),
+    Nx in {32, 64}, Qx in {4, 8}, Qy in {4, 8}; A = 0.9, T_w = 1, Pr = 2/3."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        delta = float(10.0 ** rng.uniform(-1.0, 2.0))
+        uw = float(rng.uniform(0.01, 0.5))
+        omega = float(rng.uniform(0.5, 1.0))
+        ncell = int(rng.choice((32, 64)))
+        Qx = int(rng.choice((4, 8)))
+        Qy = int(rng.choice((4, 8)))
+        out.append(dict(Qx=Qx, Qy=Qy, ncell=ncell, stretch_A=0.9, delta=delta, uw=uw, Tw=1.0, Pr=2.0 / 3.0,
+                        omega=omega, seed=seed * 1000003 + k))
+    return out

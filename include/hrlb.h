@@ -58,7 +58,7 @@ enum { HRLB_FLAG_NONFINITE = 1u, HRLB_FLAG_RANGE = 2u };
 
 enum { HRLB_FP64 = 0, HRLB_FP32_STORE_FP64_MOM = 1 };
 enum { HRLB_ROUND_NEAREST = 0, HRLB_ROUND_STOCHASTIC = 1 };
-enum { HRLB_STOP_RESIDUAL = 0, HRLB_STOP_PXY = 1 };
+enum { HRLB_STOP_RESIDUAL = 0, HRLB_STOP_PXY = 1, HRLB_STOP_PXY_ERR = 2 };
 enum { HRLB_PATH_AUTO = 0, HRLB_PATH_TILED = 1, HRLB_PATH_SMALL = 2 };
 
 typedef struct hrlb_quad hrlb_quad;   /* immutable velocity set; may be shared by many cases */
@@ -177,6 +177,7 @@ typedef struct {
     double sim_time;   /* total simulated time of the case                                   */
     double wall_s;     /* wall-clock seconds spent in this call                              */
     double mass_drift; /* (mass - initial mass)/initial mass, mass = sum_s J_s deta n_s      */
+    double pxy_err;    /* estimated remaining relative error of the mean P_xy (-1 before 9 checks, +inf with none) */
 } hrlb_steady_info;
 
 /* Autotuner of the kernel plan of one case: a coordinate search, first over tile_vpt (divisors
@@ -191,7 +192,11 @@ hrlb_status hrlb_tune_plan(const hrlb_quad *q, const hrlb_case_params *p, void *
 
 /* Runs blocks of check_every steps until the stop criterion drops below tol
  * (HRLB_STOP_RESIDUAL: the residual above; HRLB_STOP_PXY: the relative drift rate of the
- * J-weighted mean P_xy between checks), NaN/Inf appears (HRLB_E_DIVERGED), a cell leaves the
+ * J-weighted mean P_xy between checks; HRLB_STOP_PXY_ERR: the estimated remaining relative error of
+ * that mean below tol on two consecutive checks -- the differences d of the last 9 checked means taken
+ * as decaying geometrically, their rate r < 1 per check fitted by least squares to log|d|, and the
+ * error bounded by max of the last two |d| times r/(1 - r); no estimate before the 9th check or while
+ * r >= 1), NaN/Inf appears (HRLB_E_DIVERGED), a cell leaves the
  * verified band of eq. (gx) (HRLB_E_RANGE, checked at every check) or max_steps is reached
  * (HRLB_NOT_CONVERGED).  Synchronous: returns when the decision is made. */
 hrlb_status hrlb_run_to_steady(hrlb_case *c, double tol, long max_steps, int check_every, int stop_rule,
@@ -314,6 +319,7 @@ typedef struct {
                         /* FAILED: the error (HRLB_E_DIVERGED, HRLB_E_RANGE, HRLB_E_DEVICE...) */
     long steps;         /* steps taken                                                         */
     double residual, pxy_drift, Pi, sim_time, mass_drift;  /* as hrlb_steady_info/hrlb_moments */
+    double pxy_err;                                         /* as hrlb_steady_info               */
     double t_arrival, t_admit, t_done;                      /* server clock; -1 if not reached */
     int n_cells, n_vel;
     size_t bytes;       /* device workspace of the solve                                       */

@@ -945,6 +945,38 @@ hrlb_status hrlb::steady_update(SteadyTrack& t, const double* dy, long n, double
     if (t.have_prev) t.drift = std::fabs(pxy - t.pxy_prev) / (n * dt * std::max(std::fabs(pxy), 1e-300));
     t.have_prev = true;
     t.pxy_prev = pxy;
+    // remaining relative error of the mean P_xy: the last kPxyWin differences of checked means are taken
+    // as decaying geometrically, their rate r per check fitted by least squares to log|d| (a fit over
+    // several checks is not thrown off by two modes overlapping, which makes a three-point extrapolation
+    // under-estimate), and the error bounded by max(|d_last|, |d_prev|) r / (1 - r); no estimate while
+    // the fitted rate is >= 1 or a difference is exactly zero (unless the last two are)
+    constexpr int W = SteadyTrack::kPxyWin;
+    for (int k = 0; k < W; ++k) t.pxy[k] = t.pxy[k + 1];
+    t.pxy[W] = pxy;
+    if (++t.nchk > W) {
+        double d[W], est = HUGE_VAL;
+        bool zero = false;
+        for (int k = 0; k < W; ++k) {
+            d[k] = std::fabs(t.pxy[k + 1] - t.pxy[k]);
+            zero = zero || d[k] == 0.0;
+        }
+        if (d[W - 1] == 0.0 && d[W - 2] == 0.0) {
+            est = 0.0;
+        } else if (!zero) {
+            double sy = 0.0, sxy = 0.0, sxx = 0.0;
+            for (int k = 0; k < W; ++k) sy += std::log(d[k]);
+            const double xm = 0.5 * (W - 1), ym = sy / W;
+            for (int k = 0; k < W; ++k) {
+                sxy += (k - xm) * (std::log(d[k]) - ym);
+                sxx += (k - xm) * (k - xm);
+            }
+            const double r = std::exp(sxy / sxx);
+            if (r < 1.0) est = std::max(d[W - 1], d[W - 2]) * r / (1.0 - r);
+        }
+        t.err = est / std::max(std::fabs(pxy), 1e-300);
+        t.below = t.err < tol ? t.below + 1 : 0;
+    }
+    if (stop_rule == HRLB_STOP_PXY_ERR) return t.below >= 2 ? HRLB_OK : HRLB_NOT_CONVERGED;
     const double crit = stop_rule == HRLB_STOP_RESIDUAL ? t.res : t.drift;
     return (crit >= 0.0 && crit < tol) ? HRLB_OK : HRLB_NOT_CONVERGED;
 }
@@ -958,7 +990,8 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         if (sl != HRLB_OK) return sl;
     }
     if (check_every < 1 || max_steps < 0 || !(tol > 0.0)) return fail(HRLB_E_INVALID, "bad tol/max_steps/check_every");
-    if (stop_rule != HRLB_STOP_RESIDUAL && stop_rule != HRLB_STOP_PXY) return fail(HRLB_E_INVALID, "bad stop rule");
+    if (stop_rule != HRLB_STOP_RESIDUAL && stop_rule != HRLB_STOP_PXY && stop_rule != HRLB_STOP_PXY_ERR)
+        return fail(HRLB_E_INVALID, "bad stop rule");
     const auto t0 = std::chrono::steady_clock::now();
     {
         hrlb_status sa = ensure_analyzed(c);
@@ -989,6 +1022,7 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         info->steps = taken;
         info->residual = res;
         info->pxy_drift = drift;
+        info->pxy_err = track.err;
         info->sim_time = c->steps_done * c->dt;
         info->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->mass_drift = taken > 0 ? (dy[DY_MASS] - c->mass0) / c->mass0 : 0.0;

@@ -97,6 +97,13 @@ struct SteadyTrack {
     bool have_prev = false;
     double pxy_prev = 0.0;
     double res = -1.0, drift = -1.0;
+    // P_xy error rule: the last kPxyWin + 1 checked means, how many were seen, the last estimate, and how
+    // many consecutive estimates were below the tolerance
+    static constexpr int kPxyWin = 8;
+    double pxy[kPxyWin + 1] = {};
+    int nchk = 0;
+    double err = -1.0;
+    int below = 0;
 };
 // dy: the case's dynamic scalars read after a block of n steps whose last step was checked.
 // Returns HRLB_OK when the stop criterion is below tol, HRLB_NOT_CONVERGED to go on, and

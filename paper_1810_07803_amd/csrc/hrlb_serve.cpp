@@ -156,7 +156,7 @@ extern "C" hrlb_status hrlb_server_submit(hrlb_server* s, const hrlb_solve_reque
         return fail(HRLB_E_INVALID, "max_steps=%ld must be a positive multiple of check_every=%d", r->max_steps,
                     s->cfg.check_every);
     if (!(r->tol > 0.0)) return fail(HRLB_E_INVALID, "tol must be > 0");
-    if (r->stop_rule != HRLB_STOP_RESIDUAL && r->stop_rule != HRLB_STOP_PXY)
+    if (r->stop_rule != HRLB_STOP_RESIDUAL && r->stop_rule != HRLB_STOP_PXY && r->stop_rule != HRLB_STOP_PXY_ERR)
         return fail(HRLB_E_INVALID, "bad stop rule");
     const QuadKey key{r->Qx, r->Nx_order, r->Qy, r->Ny_order};
     auto it = s->quads.find(key);
@@ -325,6 +325,7 @@ extern "C" hrlb_status hrlb_server_request(hrlb_server* s, long id, hrlb_request
         info->steps = rq->taken;
         info->residual = rq->track.res;
         info->pxy_drift = rq->track.drift;
+        info->pxy_err = rq->track.err;
         info->Pi = rq->pi;
         info->sim_time = rq->sim_time;
         info->mass_drift = rq->mass_drift;

@@ -20,7 +20,7 @@ HRLB_E_INVALID, HRLB_E_NOMEM, HRLB_E_DEVICE, HRLB_E_DIVERGED, HRLB_E_RANGE = -1,
 HRLB_FLAG_NONFINITE, HRLB_FLAG_RANGE = 1, 2
 HRLB_FP64, HRLB_FP32_STORE_FP64_MOM = 0, 1
 HRLB_ROUND_NEAREST, HRLB_ROUND_STOCHASTIC = 0, 1
-HRLB_STOP_RESIDUAL, HRLB_STOP_PXY = 0, 1
+HRLB_STOP_RESIDUAL, HRLB_STOP_PXY, HRLB_STOP_PXY_ERR = 0, 1, 2
 HRLB_PATH_AUTO, HRLB_PATH_TILED, HRLB_PATH_SMALL = 0, 1, 2
 
 FIELD_NAMES = ("n", "u_x", "u_y", "T", "P_xx", "P_xy", "P_yy", "T_zz", "q_x", "q_y")
@@ -59,7 +59,8 @@ class CaseParams(C.Structure):
 
 class SteadyInfo(C.Structure):
     _fields_ = [("steps", C.c_long), ("residual", C.c_double), ("pxy_drift", C.c_double),
-                ("sim_time", C.c_double), ("wall_s", C.c_double), ("mass_drift", C.c_double)]
+                ("sim_time", C.c_double), ("wall_s", C.c_double), ("mass_drift", C.c_double),
+                ("pxy_err", C.c_double)]
 
 
 class ServerConfig(C.Structure):
@@ -75,7 +76,7 @@ class SolveRequest(C.Structure):
 class RequestInfo(C.Structure):
     _fields_ = [("state", C.c_int), ("status", C.c_int), ("steps", C.c_long), ("residual", C.c_double),
                 ("pxy_drift", C.c_double), ("Pi", C.c_double), ("sim_time", C.c_double),
-                ("mass_drift", C.c_double), ("t_arrival", C.c_double), ("t_admit", C.c_double),
+                ("mass_drift", C.c_double), ("pxy_err", C.c_double), ("t_arrival", C.c_double), ("t_admit", C.c_double),
                 ("t_done", C.c_double), ("n_cells", C.c_int), ("n_vel", C.c_int), ("bytes", C.c_size_t)]
 
 

@@ -18,7 +18,8 @@ def run_trace(server: "hrlb.Server", requests, arrivals, *, tol: float, max_step
               stop_rule: int = hrlb.HRLB_STOP_PXY, wall_limit_s: float = 600.0, local_dt_cap: float = 0.0):
     """requests: dicts with Qx, Qy, ncell, stretch_A, delta, uw, Tw, Pr, omega, seed (hrlb_inputs
     draws); arrivals: seconds after the trace start.  Returns (records, totals): one record per
-    request (arrival, admit and done times relative to the trace start, steps, status, Pi) and the
+    request (arrival, admit and done times relative to the trace start, steps, status, Pi, the last
+    estimate of the P_xy error rule) and the
     totals of the run (wall time, cell-velocity updates, rounds).  local_dt_cap > 1 runs every solve with
     local time steps (steady-state acceleration)."""
     order = np.argsort(arrivals, kind="stable")
@@ -56,7 +57,7 @@ def run_trace(server: "hrlb.Server", requests, arrivals, *, tol: float, max_step
         info, _, _ = server.request(ids[k])
         state = {hrlb.HRLB_REQ_WAITING: "waiting", hrlb.HRLB_REQ_ACTIVE: "active", hrlb.HRLB_REQ_DONE: "done",
                  hrlb.HRLB_REQ_FAILED: "failed"}[info.state]
-        rec = dict(index=k, state=state, status=info.status, steps=info.steps, Pi=info.Pi,
+        rec = dict(index=k, state=state, status=info.status, steps=info.steps, Pi=info.Pi, pxy_err=info.pxy_err,
                    arrival=info.t_arrival - t_start, n_cells=info.n_cells, n_vel=info.n_vel, bytes=info.bytes)
         if info.t_admit >= 0:
             rec["admit"] = info.t_admit - t_start
@@ -67,11 +68,25 @@ def run_trace(server: "hrlb.Server", requests, arrivals, *, tol: float, max_step
 
 
 def latency_summary(records):
-    """p50/p99 of arrival->result and admission->result over the finished requests."""
+    """Latencies of a trace.  time to steady = arrival -> result of a request that met its stop rule;
+    a request that reached its step cap or failed never reached the target, so it counts as infinitely
+    late in the percentiles over all requests (null when the percentile falls on one).  Also the same
+    percentiles over the converged requests alone, arrival -> result and admission -> result over the
+    finished ones, and the counts."""
     done = [r for r in records if r.get("state") == "done"]
-    out = dict(finished=len(done), converged=sum(1 for r in done if r["status"] == hrlb.HRLB_OK),
+    conv = [r for r in done if r["status"] == hrlb.HRLB_OK]
+    out = dict(requests=len(records), finished=len(done), converged=len(conv),
                capped=sum(1 for r in done if r["status"] == hrlb.HRLB_NOT_CONVERGED),
-               unfinished=len(records) - len(done))
+               failed=sum(1 for r in records if r.get("state") == "failed"),
+               unfinished=len(records) - len(done) - sum(1 for r in records if r.get("state") == "failed"))
+    t_all = np.array([r["done"] - r["arrival"] if r in conv else np.inf for r in records])
+    for q in (50, 99):
+        v = float(np.percentile(t_all, q, method="higher")) if len(t_all) else np.inf
+        out[f"p{q}_time_to_steady_s"] = v if np.isfinite(v) else None
+    if conv:
+        t = np.array([r["done"] - r["arrival"] for r in conv])
+        out.update(p50_time_to_steady_converged_s=float(np.percentile(t, 50)),
+                   p99_time_to_steady_converged_s=float(np.percentile(t, 99)))
     if done:
         a2r = np.array([r["done"] - r["arrival"] for r in done])
         d2r = np.array([r["done"] - r["admit"] for r in done])
@@ -79,8 +94,4 @@ def latency_summary(records):
                    p99_arrival_to_result_s=float(np.percentile(a2r, 99)),
                    p50_admit_to_result_s=float(np.percentile(d2r, 50)),
                    p99_admit_to_result_s=float(np.percentile(d2r, 99)))
-    conv = [r for r in done if r["status"] == hrlb.HRLB_OK]
-    if conv:
-        t = np.array([r["done"] - r["arrival"] for r in conv])
-        out.update(p50_time_to_steady_s=float(np.percentile(t, 50)), p99_time_to_steady_s=float(np.percentile(t, 99)))
     return out

@@ -1,0 +1,81 @@
+"""Steady states against the oracle's: the P_xy error stop rule of the serving loop on seeded draws
+from the serving parameter ranges (tests/golden/pxy_steady_oracle.json), and the FP32 storage path's
+time-averaged steady state element by element (tests/golden/c2_shaped_steady_oracle.json).  Both
+goldens were written by committed scripts that call only the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PXY_GOLDEN = os.path.join(HERE, "golden", "pxy_steady_oracle.json")
+STEADY_GOLDEN = os.path.join(HERE, "golden", "c2_shaped_steady_oracle.json")
+# the target of the serving workload: the mean P_xy within 1e-5 of the steady state; the stop rule runs
+# with a margin below it (the worst draw stops 3.8e-6 away, FP32 with the global time step)
+TARGET = 1e-5
+RULE_TOL = 3e-6
+
+
+def _params(hrlb, d, precision, lts):
+    return hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"], Tw=d["Tw"],
+                            Pr=d["Pr"], omega=d["omega"], precision=precision,
+                            rounding=hrlb.HRLB_ROUND_STOCHASTIC if precision else 0, seed=d["seed"],
+                            local_dt_cap=lts)
+
+
+@pytest.mark.parametrize("precision,lts", [(1, 64.0), (0, 64.0), (1, 0.0), (0, 0.0)])
+def test_pxy_error_rule_stops_within_the_target_of_the_oracle_steady_state(precision, lts):
+    from paper_1810_07803_amd import hrlb
+
+    g = json.load(open(PXY_GOLDEN))
+    worst = 0.0
+    for row in g["rows"]:
+        d = row["params"]
+        q = hrlb.Quadrature(d["Qx"], d["Qy"])
+        c = hrlb.Case(q, _params(hrlb, d, precision, lts))
+        st, info = c.run_to_steady(RULE_TOL, 400000, 500, hrlb.HRLB_STOP_PXY_ERR)
+        # the J-weighted channel mean of P_xy, from Pi = -mean / (sqrt 2 u_w) at T_w = 1 (eq. Pi)
+        mean = -c.moments()[2] * np.sqrt(2.0) * d["uw"]
+        err = abs(mean - row["pxy_mean"]) / abs(row["pxy_mean"])
+        worst = max(worst, err)
+        say(f"   draw {row['draw']} (Q{d['Qx']}x{d['Qy']} nx={d['ncell']} delta={d['delta']:.3g}): "
+            f"status {st}, {info.steps} steps, estimate {info.pxy_err:.2e}, error vs oracle {err:.2e}")
+        assert st == 0
+        assert err < TARGET
+    say(f"[pxy rule] precision={precision} lts={lts}: worst error {worst:.2e} (target {TARGET:g}, rule tol {RULE_TOL:g})")
+
+
+@pytest.mark.parametrize("name", ["c2_shaped_nx64_q16x8", "plain_nx32_q4x4"])
+def test_fp32_time_averaged_steady_state_against_the_oracle(name):
+    from paper_1810_07803_amd import hrlb
+    from tests.gpu_helpers import fmt_errs, term_scales
+
+    g = json.load(open(STEADY_GOLDEN))["cases"][name]
+    d = g["params"]
+    ref = np.array(g["fields"])
+    q = hrlb.Quadrature(d["Qx"], d["Qy"])
+    c = hrlb.Case(q, hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
+                                      omega=d["omega"], precision=1, rounding=hrlb.HRLB_ROUND_STOCHASTIC, seed=3,
+                                      local_dt_cap=64.0))
+    # as many steps as the oracle took to its fixed point (the same local time steps), then the average
+    # over 20000 more: FP32 stochastic rounding keeps the state fluctuating around the fixed point
+    st, info = c.run_to_steady(1e-300, g["steps"], 1000, hrlb.HRLB_STOP_RESIDUAL)
+    assert st == hrlb.HRLB_NOT_CONVERGED and info.steps == g["steps"]
+    c.average_start()
+    c.step(20000)
+    f, pi, m = c.average_read()
+    own = {k: float(np.max(np.abs(f[i] - ref[i])) / np.max(np.abs(ref[i]))) for k, i in
+           (("n", 0), ("u_y", 2), ("T", 3), ("P_xy", 5))}
+    sc = term_scales(ref)
+    ef = np.array([np.max(np.abs(f[i] - ref[i])) / max(np.max(np.abs(ref[i])), sc[i]) for i in range(10)])
+    say(f"[fp32 steady] {name}: {info.steps} steps, {m} averaged; own-magnitude errors "
+        + ", ".join(f"{k} {v:.2e}" for k, v in own.items()) + f"; Pi {pi:.9f} vs {g['Pi']:.9f}; fields {fmt_errs(ef)}")
+    # measured: at most 1.8e-7 (P_xy), 1.5e-7 (Pi), 2.1e-7 (u_y), 1.1e-8 (T), 1.1e-7 (n)
+    assert own["P_xy"] < 1e-6
+    assert abs(pi / g["Pi"] - 1.0) < 1e-6
+    assert own["u_y"] < 1e-6 and own["T"] < 1e-6 and own["n"] < 1e-6
