@@ -48,8 +48,9 @@ constexpr int kMaxViscTable = 256;  // rows of a tabulated transport law
 constexpr int kNMom = 11;  // raw moment accumulators per cell
 
 // per-cell scalars of the collision, FP64 for both storage precisions (the Shakhov factor's
-// temperature and heat-flux terms are evaluated in FP64), slot-major [slot][nx]
-enum : int { SC_UX = 0, SC_UY, SC_T, SC_INVTAU, SC_AS, SC_AS5T, SC_QX, SC_QY, kNSc };
+// temperature and heat-flux terms are evaluated in FP64), slot-major [slot][nx]: u_x, u_y, T, 1/tau,
+// 0.8 A, 0.4 A and A/(5T) with A = (1 - Pr)/(n T^2), q_x, q_y
+enum : int { SC_UX = 0, SC_UY, SC_T, SC_INVTAU, SC_S8, SC_S4, SC_AS5T, SC_QX, SC_QY, kNSc };
 // per-cell table in the storage precision, slot-major [slot][nx]: 1/(J_s deta), then g_x at the
 // 2 Q_x nodes, then g_y at the Q_y nodes
 constexpr int kGIjd = 0, kGx0 = 1;

@@ -157,14 +157,10 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x)
     return x;
 }
 
-// xorshift32 (G. Marsaglia, 2003): cheap successors of a hashed word for the neighbouring cells
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x)
-{
-    x ^= x << 13;
-    x ^= x >> 17;
-    x ^= x << 5;
-    return x;
-}
+// successor of a hashed word for the neighbouring cell of a strip: a Weyl step by the 32-bit golden
+// ratio constant (one addition).  Each word stays uniform, so each rounding stays unbiased; the words
+// of the 4 cells of a strip are evenly spread rather than independent.
+__device__ __forceinline__ uint32_t weyl32(uint32_t x) { return x + 0x9e3779b9u; }
 
 // Stochastic rounding of an FP64 value to FP32 with 16 random bits: the 29 bits a conversion
 // drops are incremented by r << 13 before truncation, so the value rounds away from zero with
@@ -355,8 +351,9 @@ __host__ __device__ constexpr size_t cell_lds_bytes(int qy, size_t es)
 }
 
 // MODE: kModeAnalyze (no update; partials of the current state f[0], used after set-up or a state
-// upload), kModeStep, kModeResid (a step whose stage 3 also forms the residual partials)
-enum : int { kModeAnalyze = 0, kModeStep = 1, kModeResid = 2 };
+// upload), kModeStep0 (the first stage of a step, which reads no f^n), kModeStep (stage 2 or 3),
+// kModeResid (a stage 3 that also forms the residual partials)
+enum : int { kModeAnalyze = 0, kModeStep0 = 1, kModeStep = 2, kModeResid = 3 };
 // Work distribution: one queue per XCD.  Block b runs on XCD b % 8 (blocks are dispatched round
 // robin and the grid is a multiple of 8, sized to the blocks that fit on the chip at once); it takes
 // the next position x + 8 k of its XCD's part of the tile list from the counter ctr[x] until the
@@ -367,11 +364,13 @@ enum : int { kModeAnalyze = 0, kModeStep = 1, kModeResid = 2 };
 // the FP64 collision would otherwise cost a third of its occupancy).  The residual variant, which
 // runs on checked steps only, keeps 2 rather than spill.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && MODE == 1 ? 3 : 2))) void stage_kernel(const InstDesc* __restrict__ descs,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
+    sizeof(T) == 4 && (MODE == kModeStep0 || MODE == kModeStep) ? 3 : 2))) void stage_kernel(const InstDesc* __restrict__ descs,
                                                          const TileRef* __restrict__ tiles, int ntiles,
                                                          int stage, unsigned* __restrict__ ctr)
 {
     constexpr bool ANALYZE = MODE == kModeAnalyze;
+    constexpr bool HAS_FN = MODE == kModeStep || MODE == kModeResid;  // stages 2 and 3 combine with f^n
     constexpr bool kDma = std::is_same<T, float>::value && !ANALYZE;  // windows prefetched through LDS
     // dynamic LDS: [union of (cell tables of the tile) and (moment reduction)] + boundary faces
     extern __shared__ __align__(16) unsigned char smem[];
@@ -452,7 +451,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
             dma16(rin, pf + 3 * kPfLoad, chi_off + rowoff + oL, ks);
             dma16(rin, pf + 4 * kPfLoad, chi_off + rowoff + oC, ks);
             dma16(rin, pf + 5 * kPfLoad, chi_off + rowoff + oR, ks);
-            if (stage > 0) {
+            if constexpr (HAS_FN) {
                 dma16(rfn, pf + 6 * kPfLoad, rowoff + oC, ks);
                 dma16(rfn, pf + 7 * kPfLoad, chi_off + rowoff + oC, ks);
             }
@@ -565,11 +564,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                     // velocity k is in the buffer once every operation but the last two (the previous
                     // velocity's output stores) has retired
                     f4v t[kPfSlots];
-                    if (k == 0) {
-                        if (stage > 0) read_slots<0, 8>(pf_la, t); else read_slots<0, 6>(pf_la, t);
-                    } else {
-                        if (stage > 0) read_slots<2, 8>(pf_la, t); else read_slots<2, 6>(pf_la, t);
-                    }
+                    constexpr int nslot = HAS_FN ? 8 : 6;
+                    if (k == 0)
+                        read_slots<0, nslot>(pf_la, t);
+                    else
+                        read_slots<2, nslot>(pf_la, t);
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         P.w[c] = t[0][c];
@@ -578,7 +577,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                         P.w[8 + c] = t[2][c];
                         X.w[4 + c] = t[4][c];
                         X.w[8 + c] = t[5][c];
-                        if (stage > 0) {
+                        if constexpr (HAS_FN) {
                             fnp[c] = t[6][c];
                             fnc[c] = t[7][c];
                         }
@@ -628,7 +627,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
 #pragma unroll
                         for (int c = 0; c < 4; ++c) X.w[3 - c] = tmp[c];
                     }
-                    if (!ANALYZE && stage > 0) {
+                    if constexpr (HAS_FN) {
                         bld4(rfn, rowoff + oC, fnp, kstep);
                         bld4(rfn, chi_off + rowoff + oC, fnc, kstep);
                     }
@@ -694,7 +693,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                             Fc[4] = chiwr;
                         }
                     }
-                    if constexpr (kDma) {
+                    if constexpr (kDma && HAS_FN) {
                         // the previous stage's values are first needed by the combine: their loads
                         // overlap the face computation
 #pragma unroll
@@ -705,7 +704,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                     if (rounding) {
                         const uint32_t base = rkey ^ ((uint32_t)v * 0x85ebca6bu) ^ ((uint32_t)s0 * 0xc2b2ae35u);
 #pragma unroll
-                        for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : xorshift32(rbits[c - 1]);
+                        for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : weyl32(rbits[c - 1]);
                     }
                     int lcol = strip;
                     // an opaque column index keeps the compiler from hoisting the per-cell terms out of
@@ -718,31 +717,43 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                         const T p = P.w[4 + c], x = X.w[4 + c];
                         const double ux = Ls[SC_UX * kScSlot + c * kTPR], uy = Ls[SC_UY * kScSlot + c * kTPR];
                         const double Tt = Ls[SC_T * kScSlot + c * kTPR], itau = Ls[SC_INVTAU * kScSlot + c * kTPR];
-                        const double AS = Ls[SC_AS * kScSlot + c * kTPR], A5 = Ls[SC_AS5T * kScSlot + c * kTPR];
+                        const double S8 = Ls[SC_S8 * kScSlot + c * kTPR], S4 = Ls[SC_S4 * kScSlot + c * kTPR];
+                        const double A5 = Ls[SC_AS5T * kScSlot + c * kTPR];
                         const double qxv = Ls[SC_QX * kScSlot + c * kTPR], qyv = Ls[SC_QY * kScSlot + c * kTPR];
                         const T ijd = Lg[kGIjd * kLdsSlot + c * kTPR];
                         const T gy = Lg[(1 + j) * kLdsSlot + c * kTPR];
                         const T gx = Lg[(1 + qy + row) * kLdsSlot + c * kTPR];
-                        // reduced Shakhov collision, Sec. II, in FP64: the Shakhov factors S_phi, S_chi
-                        // (temperature and heat-flux terms), the targets phi_eq (1 + S_phi), chi_eq (1 + S_chi)
-                        // (the product of the truncated equilibria is exact in FP64) and their relaxation
+                        // reduced Shakhov collision, Sec. II, in FP64: with xi = p - u, the targets
+                        // phi_eq (1 + S_phi) and chi_eq (1 + S_chi) = T phi_eq (1 + S_chi), where
+                        // S_phi = (q.xi) (A xi^2/(5T) - 0.8 A), S_chi = (q.xi) (A xi^2/(5T) - 0.4 A); with
+                        // W = phi_eq (q.xi) and V = phi_eq + W A xi^2/(5T) they are V - 0.8 A W and
+                        // T (V - 0.4 A W) (the product of the truncated equilibria is exact in FP64)
                         const double xx = pxd - ux, xy = pyd - uy;
                         const double x2 = xx * xx + xy * xy;
                         const double qxi = qxv * xx + qyv * xy;
-                        const double sp = qxi * (A5 * x2 - 0.8 * AS);
-                        const double sch = qxi * (A5 * x2 - 0.4 * AS);
                         const double feq = (double)gx * (double)gy;
-                        const double tp = feq + feq * sp;
-                        const double tc = Tt * (feq + feq * sch);
+                        const double W = feq * qxi;
+                        const double V = fma(W, A5 * x2, feq);
+                        const double tp = fma(-W, S8, V);
+                        const double tc = Tt * fma(-W, S4, V);
                         // x-advection in the storage precision: -p_x (F_{s+1/2} - F_{s-1/2}) / (J_s deta)
-                        const T ap = -px * (Fp[c + 1] - Fp[c]) * ijd;
-                        const T ax = -px * (Fc[c + 1] - Fc[c]) * ijd;
+                        const T mpi = -px * ijd;
+                        const T ap = (Fp[c + 1] - Fp[c]) * mpi;
+                        const T ax = (Fc[c + 1] - Fc[c]) * mpi;
                         const double Lp = (double)ap + (tp - (double)p) * itau;
                         const double Lx = (double)ax + (tc - (double)x) * itau;
-                        // SSP-RK3 stage: out = a f^n + b (f_in + dt L(f_in)), combined in FP64
-                        const double fnpd = (double)fnp[c], fncd = (double)fnc[c];
-                        const double ope = ca * fnpd + cb * ((double)p + dtc[c] * Lp);
-                        const double oce = ca * fncd + cb * ((double)x + dtc[c] * Lx);
+                        // SSP-RK3 stage: out = a f^n + b (f_in + dt L(f_in)), combined in FP64 (a = 0, b = 1
+                        // in the first stage, which reads no f^n)
+                        double fnpd = 0.0, fncd = 0.0, ope, oce;
+                        if constexpr (HAS_FN) {
+                            fnpd = (double)fnp[c];
+                            fncd = (double)fnc[c];
+                            ope = ca * fnpd + cb * ((double)p + dtc[c] * Lp);
+                            oce = ca * fncd + cb * ((double)x + dtc[c] * Lx);
+                        } else {
+                            ope = (double)p + dtc[c] * Lp;
+                            oce = (double)x + dtc[c] * Lx;
+                        }
                         op[c] = store_round<T>(ope, rounding, rbits[c]);
                         oc[c] = store_round<T>(oce, rounding, rbits[c] >> 16);
                         if (want_res) {
@@ -1171,7 +1182,8 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
         sc[SC_UY * nx + s] = uy;
         sc[SC_T * nx + s] = Tm;
         sc[SC_INVTAU * nx + s] = invtau;
-        sc[SC_AS * nx + s] = As;
+        sc[SC_S8 * nx + s] = 0.8 * As;
+        sc[SC_S4 * nx + s] = 0.4 * As;
         sc[SC_AS5T * nx + s] = As5T;
         sc[SC_QX * nx + s] = qx;
         sc[SC_QY * nx + s] = qy;
@@ -1514,7 +1526,7 @@ __device__ __forceinline__ void small_update(const InstDesc& D, const SmallPtrs<
         if (D.rounding) {
             const uint32_t base = rkey ^ ((uint32_t)v * 0x85ebca6bu) ^ ((uint32_t)s0 * 0xc2b2ae35u);
 #pragma unroll
-            for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : xorshift32(rbits[c - 1]);
+            for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : weyl32(rbits[c - 1]);
         }
 #pragma unroll
         for (int c = 0; c < kStrip; ++c) {
@@ -1522,19 +1534,20 @@ __device__ __forceinline__ void small_update(const InstDesc& D, const SmallPtrs<
             const T fv = P.w[4 + c];
             const double* sc = S.sc + s;
             const double ux = sc[SC_UX * nx], uy = sc[SC_UY * nx], itau = sc[SC_INVTAU * nx];
-            const double AS = sc[SC_AS * nx], A5 = sc[SC_AS5T * nx], qxv = sc[SC_QX * nx], qyv = sc[SC_QY * nx];
+            const double A5 = sc[SC_AS5T * nx], qxv = sc[SC_QX * nx], qyv = sc[SC_QY * nx];
             const T ijd = S.g[kGIjd * nx + s];
             const T gy = S.g[(kGx0 + 2 * qx + j) * nx + s];
             const T gx = S.g[(kGx0 + hi) * nx + s];
-            // reduced Shakhov collision, Sec. II, in FP64 (as the tiled path): phi relaxes to
-            // phi_eq (1 + S_phi), chi to T phi_eq (1 + S_chi)
+            // reduced Shakhov collision, Sec. II, in FP64 (the same operations as the tiled path): phi
+            // relaxes to V - 0.8 A W = phi_eq (1 + S_phi), chi to T (V - 0.4 A W) = T phi_eq (1 + S_chi)
             const double xx = pxd - ux, xy = pyd - uy;
             const double x2 = xx * xx + xy * xy;
             const double qxi = qxv * xx + qyv * xy;
             const double feq = (double)gx * (double)gy;
-            const double tg = d ? sc[SC_T * nx] * (feq + feq * (qxi * (A5 * x2 - 0.4 * AS)))
-                                : feq + feq * (qxi * (A5 * x2 - 0.8 * AS));
-            const T a = -pxt * (F[c + 1] - F[c]) * ijd;
+            const double W = feq * qxi;
+            const double V = fma(W, A5 * x2, feq);
+            const double tg = d ? sc[SC_T * nx] * fma(-W, sc[SC_S4 * nx], V) : fma(-W, sc[SC_S8 * nx], V);
+            const T a = (F[c + 1] - F[c]) * (-pxt * ijd);
             const double L = (double)a + (tg - (double)fv) * itau;
             const double fnd = stage > 0 ? (double)fn[row + s] : 0.0;
             const double oe = ca * fnd + cb * ((double)fv + S.dts[s] * L);
@@ -1819,6 +1832,9 @@ extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_stage(int fp32
     if ((flags & FLAG_RESID) && stage == 2)
         return fp32 ? launch_stage<float, kModeResid>(descs, tiles, ntiles, stage, ctr, lds, st)
                     : launch_stage<double, kModeResid>(descs, tiles, ntiles, stage, ctr, lds, st);
+    if (stage == 0)
+        return fp32 ? launch_stage<float, kModeStep0>(descs, tiles, ntiles, stage, ctr, lds, st)
+                    : launch_stage<double, kModeStep0>(descs, tiles, ntiles, stage, ctr, lds, st);
     return fp32 ? launch_stage<float, kModeStep>(descs, tiles, ntiles, stage, ctr, lds, st)
                 : launch_stage<double, kModeStep>(descs, tiles, ntiles, stage, ctr, lds, st);
 }
