@@ -419,13 +419,18 @@ def main(argv=None):
     from paper_1810_07803_amd import profiling
 
     traffic = profiling.load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_stage_kernel_traffic.txt"))
+    # the method floor: a whole step reads and writes phi and chi once in the storage precision
+    # (2 x 2 x es bytes per unit) at the HBM peak
+    floor_frac = value * 4 * es / (HBM_PEAK_GBS * 1e9)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "stage_kernel<%s, 1>" % ("float" if es == 4 else "double"),
+                "kernel": "stage_kernel<%s, 1..3> (the three stages of a step)" % ("float" if es == 4 else "double"),
                 "kernel_ms": round(stage_ms, 4), "cell_kernel_ms": round(cell_ms, 4),
                 "bytes_per_unit_per_launch": bytes_per_unit, "units_per_launch": tiled_units,
                 "small_path_instances": n_small,
-                "launches": "whole batch on one stream"}
+                "launches": "whole batch on one stream",
+                "method_floor_frac": round(floor_frac, 4),
+                "method_floor_bytes_per_unit_per_step": 4 * es}
 
     cpu = None
     if not args.no_cpu_baseline:

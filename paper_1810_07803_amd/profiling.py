@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 output for the solver's kernels (tracing/profiling support).
 
 * ``stats``: the kernel table of a ``rocprofv3 --kernel-trace --stats --output-format csv`` run.
+* ``sq``: instructions per cell-velocity unit and the VALU issue share per kernel (SQ counters).
 * ``traffic``: HBM bytes per dispatch of one kernel from two counter runs (``--pmc FETCH_SIZE`` and
   ``--pmc WRITE_SIZE``, values in KiB per dispatch), each scaled by what the same counter reads for
   the largest plain device copy in the same run (``bench.py --copy-probe-mib N`` issues one of a
@@ -11,6 +12,7 @@
 Command line:
     python -m paper_1810_07803_amd.profiling stats <kernel_stats.csv> [command...]
     python -m paper_1810_07803_amd.profiling traffic <fetch.csv> <write.csv> <kernel-substring> <probe-MiB> [command...]
+    python -m paper_1810_07803_amd.profiling sq <counter_collection.csv> <units-per-launch> [command...]
 """
 from __future__ import annotations
 
@@ -64,6 +66,8 @@ def _per_dispatch(path: str, counter: str):
 
 
 def traffic(fetch_csv: str, write_csv: str, kernel: str, probe_mib: float, command: str = "") -> str:
+    """kernel: a substring of the kernel names, or several separated by ';' (the dispatches of all of
+    them are averaged: the three stage variants of a step give the mean per stage launch)."""
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
     write = _per_dispatch(write_csv, "WRITE_SIZE")
     known_kib = probe_mib * 1024.0
@@ -71,8 +75,9 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, probe_mib: float, comma
     cal_w = max(v for n, v in write if "copy" in n.lower() or "elementwise" in n.lower())
     cal_f = max(v for n, v in fetch if "copy" in n.lower() or "elementwise" in n.lower())
     f_scale, w_scale = known_kib / cal_f, known_kib / cal_w
-    kf = [v for n, v in fetch if kernel in n]
-    kw = [v for n, v in write if kernel in n]
+    names = [k for k in kernel.split(";") if k]
+    kf = [v for n, v in fetch if any(k in n for k in names)]
+    kw = [v for n, v in write if any(k in n for k in names)]
     f_kib = sum(kf) / len(kf)
     w_kib = sum(kw) / len(kw)
     tb = (f_kib * f_scale + w_kib * w_scale) * 1024.0
@@ -94,6 +99,41 @@ def traffic(fetch_csv: str, write_csv: str, kernel: str, probe_mib: float, comma
         f"traffic_bytes_per_dispatch: {tb:.0f}",
     ]
     return "\n".join(lines) + "\n"
+
+
+def sq(path: str, units_per_launch: float, command: str = "") -> str:
+    """Per-kernel table of a ``--pmc SQ_WAVES SQ_INSTS_VALU ...`` run: dispatches, mean duration, VALU,
+    LDS and SALU instructions per cell-velocity unit of the launch (wave instructions x 64 lanes /
+    units), and the VALU issue share: SQ_INSTS_VALU x 4 cycles (a wave64 VALU instruction on a 16-lane
+    SIMD) over the 1024 SIMDs x the duration x 2.4 GHz."""
+    rows = list(csv.DictReader(open(path)))
+    agg, disp, dur = {}, {}, {}
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        if "hrlb::" not in name:
+            continue
+        a = agg.setdefault(name, {})
+        a[r["Counter_Name"]] = a.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        disp.setdefault(name, set()).add(r["Dispatch_Id"])
+        dur.setdefault(name, {})[r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    out = []
+    if command:
+        out.append(f"command: {command}")
+    out.append(f"kernel source digest: {source_digest()}")
+    out.append(f"units per launch: {units_per_launch:.0f}")
+    out.append("")
+    out.append("| kernel | dispatches | mean us | VALU/unit | LDS/unit | SALU/unit | VALU issue share |")
+    out.append("|---|---:|---:|---:|---:|---:|---:|")
+    for name in sorted(agg):
+        n = len(disp[name])
+        a = agg[name]
+        d_ns = sum(dur[name].values()) / n
+        per = lambda c: a.get(c, 0.0) / n * 64.0 / units_per_launch
+        share = a.get("SQ_INSTS_VALU", 0.0) / n * 4.0 / (1024.0 * d_ns * 2.4)
+        out.append("| %s | %d | %.1f | %.1f | %.1f | %.1f | %.3f |" % (
+            name.replace("hrlb::", ""), n, d_ns / 1e3, per("SQ_INSTS_VALU"), per("SQ_INSTS_LDS"),
+            per("SQ_INSTS_SALU"), share))
+    return "\n".join(out) + "\n"
 
 
 def load_traffic(path: str):
@@ -119,5 +159,7 @@ if __name__ == "__main__":
         sys.stdout.write(stats(sys.argv[2], " ".join(sys.argv[3:])))
     elif mode == "traffic":
         sys.stdout.write(traffic(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]), " ".join(sys.argv[6:])))
+    elif mode == "sq":
+        sys.stdout.write(sq(sys.argv[2], float(sys.argv[3]), " ".join(sys.argv[4:])))
     else:
         raise SystemExit(__doc__)
