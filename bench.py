@@ -56,11 +56,12 @@ WORKLOADS = {
                                          tol=2e-6, max_steps=100000, check_every=1000, local_dt_cap=64.0),
     # the serving metric: each solve stops once the estimated remaining error of its mean P_xy is below
     # 3e-6 on two checks (the rule that keeps every oracle-checked calibration draw within 1e-5 of the
-    # oracle's steady state), local time steps, at most 1M steps; the default run serves the first 32
-    # requests of this trace next to the batch
+    # oracle's steady state), local time steps, Courant number 1 (the steady state does not depend on
+    # the time step; the oracle reaches the same one at CFL 1), at most 1M steps; the default run serves
+    # the first 32 requests of this trace next to the batch
     "couette_serve_poisson200_pxyerr": dict(kind="serve", precision=1, rounding=1, requests=64, rate=200.0,
                                             tol=3e-6, stop_rule=2, max_steps=1000000, check_every=500,
-                                            local_dt_cap=64.0),
+                                            local_dt_cap=64.0, cfl=1.0),
     # the quadrature-convergence claim of Sec. IV in its own setting: half channel, A = 0.98,
     # u_w = sqrt(2 K_B T_w/m), delta in {10, 1, 0.1}; the production models HHLB(6;7) x HLB(6;7)
     # (delta = 10, 1) and HHLB(10;16) x HLB(6;7) (delta = 0.1) on S = 16 cells against the reference
@@ -170,7 +171,7 @@ def _serve_trace(args, spec, n_requests, wall_limit_s):
     print(f"# serving {len(reqs)} requests", file=sys.stderr, flush=True)
     records, tot = serve.run_trace(srv, reqs, arrivals, tol=spec["tol"], max_steps=spec["max_steps"],
                                    stop_rule=spec.get("stop_rule", hrlb.HRLB_STOP_PXY), wall_limit_s=wall_limit_s,
-                                   local_dt_cap=spec.get("local_dt_cap", 0.0))
+                                   local_dt_cap=spec.get("local_dt_cap", 0.0), cfl=spec.get("cfl", 0.5))
     summ = serve.latency_summary(records)
     summ["solves_per_s"] = summ["finished"] / tot["wall_s"]
     summ["updates_per_s"] = tot["units"] / tot["wall_s"]
@@ -201,7 +202,7 @@ def _serve_main(args, spec):
         "config": {"workload": args.workload, "requests": len(reqs), "arrival_rate_per_s": spec["rate"],
                    "stop": _stop_desc(spec),
                    "arena_mib": args.arena_mib, "local_dt_cap": spec.get("local_dt_cap", 0.0),
-                   "parallelism": "single GPU, continuous batching"},
+                   "cfl": spec.get("cfl", 0.5), "parallelism": "single GPU, continuous batching"},
         "serving": summ,
         "roofline": None,
         "cpu_baseline": None,
@@ -449,7 +450,7 @@ def main(argv=None):
         summ, _, reqs = _serve_trace(args, sspec, args.serve_requests, args.serve_leg_wall_s)
         serving = dict(summ, workload="couette_serve_poisson200_pxyerr", requests=len(reqs),
                        arrival_rate_per_s=sspec["rate"], stop=_stop_desc(sspec),
-                       local_dt_cap=sspec["local_dt_cap"], dtype="f32", moments_dtype="f64",
+                       local_dt_cap=sspec["local_dt_cap"], cfl=sspec["cfl"], dtype="f32", moments_dtype="f64",
                        target="mean P_xy within 1e-5 of the steady state")
 
     out = {

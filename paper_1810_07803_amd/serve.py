@@ -15,13 +15,14 @@ from . import hrlb
 
 
 def run_trace(server: "hrlb.Server", requests, arrivals, *, tol: float, max_steps: int,
-              stop_rule: int = hrlb.HRLB_STOP_PXY, wall_limit_s: float = 600.0, local_dt_cap: float = 0.0):
+              stop_rule: int = hrlb.HRLB_STOP_PXY, wall_limit_s: float = 600.0, local_dt_cap: float = 0.0,
+              cfl: float = 0.5):
     """requests: dicts with Qx, Qy, ncell, stretch_A, delta, uw, Tw, Pr, omega, seed (hrlb_inputs
     draws); arrivals: seconds after the trace start.  Returns (records, totals): one record per
     request (arrival, admit and done times relative to the trace start, steps, status, Pi, the last
     estimate of the P_xy error rule) and the
     totals of the run (wall time, cell-velocity updates, rounds).  local_dt_cap > 1 runs every solve with
-    local time steps (steady-state acceleration)."""
+    local time steps (steady-state acceleration); cfl is the Courant number of the time step rule."""
     order = np.argsort(arrivals, kind="stable")
     t_start = server.clock()
     ids = {}
@@ -35,7 +36,7 @@ def run_trace(server: "hrlb.Server", requests, arrivals, *, tol: float, max_step
             p = hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"],
                                  Tw=d.get("Tw", 1.0), Pr=d.get("Pr", 2.0 / 3.0), omega=d["omega"],
                                  precision=server.precision, rounding=hrlb.HRLB_ROUND_STOCHASTIC,
-                                 seed=d.get("seed", k), local_dt_cap=local_dt_cap)
+                                 seed=d.get("seed", k), local_dt_cap=local_dt_cap, cfl=cfl)
             ids[k] = server.submit(d["Qx"], d["Qy"], p, tol=tol, max_steps=max_steps, stop_rule=stop_rule,
                                    arrival_s=t_start + float(arrivals[k]))
             nxt += 1
@@ -72,26 +73,28 @@ def latency_summary(records):
     a request that reached its step cap or failed never reached the target, so it counts as infinitely
     late in the percentiles over all requests (null when the percentile falls on one).  Also the same
     percentiles over the converged requests alone, arrival -> result and admission -> result over the
-    finished ones, and the counts."""
+    finished ones, and the counts.  Percentiles are sample values (the smallest with at least q% of
+    the samples at or below it), not interpolations."""
     done = [r for r in records if r.get("state") == "done"]
     conv = [r for r in done if r["status"] == hrlb.HRLB_OK]
     out = dict(requests=len(records), finished=len(done), converged=len(conv),
                capped=sum(1 for r in done if r["status"] == hrlb.HRLB_NOT_CONVERGED),
                failed=sum(1 for r in records if r.get("state") == "failed"),
                unfinished=len(records) - len(done) - sum(1 for r in records if r.get("state") == "failed"))
+    def pct(x, q):
+        # the smallest sample with at least q% of the samples at or below it (no interpolation)
+        return float(np.percentile(x, q, method="inverted_cdf"))
+
     t_all = np.array([r["done"] - r["arrival"] if r in conv else np.inf for r in records])
     for q in (50, 99):
-        v = float(np.percentile(t_all, q, method="higher")) if len(t_all) else np.inf
+        v = pct(t_all, q) if len(t_all) else np.inf
         out[f"p{q}_time_to_steady_s"] = v if np.isfinite(v) else None
     if conv:
         t = np.array([r["done"] - r["arrival"] for r in conv])
-        out.update(p50_time_to_steady_converged_s=float(np.percentile(t, 50)),
-                   p99_time_to_steady_converged_s=float(np.percentile(t, 99)))
+        out.update(p50_time_to_steady_converged_s=pct(t, 50), p99_time_to_steady_converged_s=pct(t, 99))
     if done:
         a2r = np.array([r["done"] - r["arrival"] for r in done])
         d2r = np.array([r["done"] - r["admit"] for r in done])
-        out.update(p50_arrival_to_result_s=float(np.percentile(a2r, 50)),
-                   p99_arrival_to_result_s=float(np.percentile(a2r, 99)),
-                   p50_admit_to_result_s=float(np.percentile(d2r, 50)),
-                   p99_admit_to_result_s=float(np.percentile(d2r, 99)))
+        out.update(p50_arrival_to_result_s=pct(a2r, 50), p99_arrival_to_result_s=pct(a2r, 99),
+                   p50_admit_to_result_s=pct(d2r, 50), p99_admit_to_result_s=pct(d2r, 99))
     return out

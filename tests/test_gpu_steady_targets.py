@@ -21,15 +21,18 @@ TARGET = 1e-5
 RULE_TOL = 3e-6
 
 
-def _params(hrlb, d, precision, lts):
+def _params(hrlb, d, precision, lts, cfl):
     return hrlb.make_params(delta=d["delta"], uw=d["uw"], ncell=d["ncell"], stretch_A=d["stretch_A"], Tw=d["Tw"],
                             Pr=d["Pr"], omega=d["omega"], precision=precision,
                             rounding=hrlb.HRLB_ROUND_STOCHASTIC if precision else 0, seed=d["seed"],
-                            local_dt_cap=lts)
+                            local_dt_cap=lts, cfl=cfl)
 
 
-@pytest.mark.parametrize("precision,lts", [(1, 64.0), (0, 64.0), (1, 0.0), (0, 0.0)])
-def test_pxy_error_rule_stops_within_the_target_of_the_oracle_steady_state(precision, lts):
+# (precision, local-step cap, Courant number): the serving configuration is FP32, cap 64, CFL 1 (the
+# steady state does not depend on the time step; the oracle reaches the same one at CFL 1)
+@pytest.mark.parametrize("precision,lts,cfl", [(1, 64.0, 0.5), (0, 64.0, 0.5), (1, 0.0, 0.5), (0, 0.0, 0.5),
+                                               (1, 64.0, 1.0), (0, 64.0, 1.0)])
+def test_pxy_error_rule_stops_within_the_target_of_the_oracle_steady_state(precision, lts, cfl):
     from paper_1810_07803_amd import hrlb
 
     g = json.load(open(PXY_GOLDEN))
@@ -37,7 +40,7 @@ def test_pxy_error_rule_stops_within_the_target_of_the_oracle_steady_state(preci
     for row in g["rows"]:
         d = row["params"]
         q = hrlb.Quadrature(d["Qx"], d["Qy"])
-        c = hrlb.Case(q, _params(hrlb, d, precision, lts))
+        c = hrlb.Case(q, _params(hrlb, d, precision, lts, cfl))
         st, info = c.run_to_steady(RULE_TOL, 400000, 500, hrlb.HRLB_STOP_PXY_ERR)
         # the J-weighted channel mean of P_xy, from Pi = -mean / (sqrt 2 u_w) at T_w = 1 (eq. Pi)
         mean = -c.moments()[2] * np.sqrt(2.0) * d["uw"]
@@ -47,7 +50,8 @@ def test_pxy_error_rule_stops_within_the_target_of_the_oracle_steady_state(preci
             f"status {st}, {info.steps} steps, estimate {info.pxy_err:.2e}, error vs oracle {err:.2e}")
         assert st == 0
         assert err < TARGET
-    say(f"[pxy rule] precision={precision} lts={lts}: worst error {worst:.2e} (target {TARGET:g}, rule tol {RULE_TOL:g})")
+    say(f"[pxy rule] precision={precision} lts={lts} cfl={cfl}: worst error {worst:.2e} (target {TARGET:g}, "
+        f"rule tol {RULE_TOL:g})")
 
 
 @pytest.mark.parametrize("name", ["c2_shaped_nx64_q16x8", "plain_nx32_q4x4"])
