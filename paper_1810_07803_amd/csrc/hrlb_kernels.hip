@@ -974,9 +974,28 @@ __device__ __forceinline__ void wall_right(const InstDesc& D, const T* fcur)
     }
 }
 
+// the value of x in the partner lane of a DPP pattern within a 16-lane row (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// sum over the lanes of a cell (lanes = 1, 2, 4, 8 or 16 consecutive lanes, aligned): a butterfly
+// whose step s adds the partner's value, identical in every lane afterwards.  The partners come from
+// DPP patterns inside a 16-lane row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror): after the steps before it, every lane of a group of 2^s holds the same value, so
+// these pair each group with the neighbouring one exactly as lane ^ 2^s would, and the sums (and
+// their bits) are those of the xor butterfly, without a trip through LDS.
 __device__ __forceinline__ double lane_sum(double x, int lanes)
 {
-    for (int o = 1; o < lanes; o <<= 1) x += __shfl_xor(x, o, kMaxCellLanes);
+    if (lanes > 1) x += dpp_partner<0xB1>(x);
+    if (lanes > 2) x += dpp_partner<0x4E>(x);
+    if (lanes > 4) x += dpp_partner<0x141>(x);
+    if (lanes > 8) x += dpp_partner<0x140>(x);
     return x;
 }
 
