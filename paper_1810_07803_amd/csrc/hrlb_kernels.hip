@@ -183,6 +183,31 @@ __device__ __forceinline__ float store_round<float>(double x, int stochastic, ui
     return stochastic ? round_stochastic(x, r16) : (float)x;
 }
 
+// the value of x in the partner lane of a DPP pattern within a 16-lane row (both 32-bit halves)
+template <int CTRL>
+__device__ __forceinline__ double dpp_partner(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// sum over the 64 lanes of a wave, the same bits in every lane: a butterfly whose in-row steps take
+// their partners from DPP patterns (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror; every lane of a group holds the same value after the steps before it), then the two
+// steps across 16-lane rows through LDS permutes
+__device__ __forceinline__ double wave_sum(double x)
+{
+    x += dpp_partner<0xB1>(x);
+    x += dpp_partner<0x4E>(x);
+    x += dpp_partner<0x141>(x);
+    x += dpp_partner<0x140>(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
+    return x;
+}
+
 // ---- buffer resources: 32-bit byte offsets from a base held in scalar registers ---------------
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef int i4v __attribute__((ext_vector_type(4)));
@@ -847,8 +872,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
             const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                double s = vals[q];
-                for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+                const double s = wave_sum(vals[q]);
                 if (lane == 0) lds_red[wave][q] = s;
             }
             __syncthreads();
@@ -892,10 +916,8 @@ __device__ void wall_sums(const InstDesc& D, const T* f, bool right, double& flu
         a += pxv * (double)F;
         b += pxv * pyv * (double)F;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o, 64);
-        b += __shfl_xor(b, o, 64);
-    }
+    a = wave_sum(a);
+    b = wave_sum(b);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
         red[wave][0] = a;
@@ -972,16 +994,6 @@ __device__ __forceinline__ void wall_right(const InstDesc& D, const T* fcur)
         D.dyn[DY_NWR] = nwr;
         D.dyn[DY_SHEAR_R] = mr + nwr * D.mom_r;
     }
-}
-
-// the value of x in the partner lane of a DPP pattern within a 16-lane row (both 32-bit halves)
-template <int CTRL>
-__device__ __forceinline__ double dpp_partner(double x)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // sum over the lanes of a cell (lanes = 1, 2, 4, 8 or 16 consecutive lanes, aligned): a butterfly
@@ -1377,7 +1389,7 @@ __device__ inline void small_block_sum(double (&x)[N], double (*red)[N])
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        for (int o = 32; o > 0; o >>= 1) x[i] += __shfl_xor(x[i], o, 64);
+        x[i] = wave_sum(x[i]);
         if (lane == 0) red[wave][i] = x[i];
     }
     __syncthreads();
