@@ -123,10 +123,24 @@ def _build(spec, insts, tune: bool, tile_vpt: int = 0, cell_lanes: int = 0, rows
 
 
 def _cpu_baseline(insts, budget_s: float, half: bool = False):
-    """The oracle as it stands, on a bounded sample of the same workload (host cores, OpenMP)."""
+    """The oracle as it stands, on a bounded sample of the same workload (host cores, OpenMP).  The
+    sample is the instances at the work-weighted sixths of the workload (instances ordered by cell x
+    velocity count, the one holding the midpoint of each sixth of the total), so that its mix of sizes
+    is the mix the batch's updates come from; every sampled instance runs the same number of steps."""
     from oracle.oracle import OracleProblem, num_threads
 
-    sample = insts[: min(len(insts), 6)]
+    if len(insts) <= 6:
+        sample = list(insts)
+    else:
+        size = [d["ncell"] * 2 * d["Qx"] * d["Qy"] for d in insts]
+        order = sorted(range(len(insts)), key=lambda k: size[k])
+        total = float(sum(size))
+        sample, acc, want = [], 0.0, [(2 * i + 1) / 12.0 * total for i in range(6)]
+        for k in order:
+            acc += size[k]
+            while want and acc >= want[0]:
+                sample.append(insts[k])
+                want.pop(0)
     probs = []
     for d in sample:
         probs.append(OracleProblem(d["Qx"], d["Qy"], d["ncell"] // 2 if half else d["ncell"],
@@ -148,7 +162,8 @@ def _cpu_baseline(insts, budget_s: float, half: bool = False):
         units += p.nv * p.ncell * steps
     dt = time.perf_counter() - t0
     return {"value": units / dt, "unit": "cell·velocity updates/s", "cores": num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle, first {len(sample)} instances of the workload, {steps} steps each "
+            "sample": f"FP64 oracle, {len(sample)} instances at the work-weighted sixths of the workload "
+                      f"(cells x velocities {sorted(p.nv * p.ncell for p in probs)}), {steps} steps each "
                       f"({units} cell·velocity updates in {dt:.1f} s)"}
 
 
