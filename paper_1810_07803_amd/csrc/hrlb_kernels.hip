@@ -618,8 +618,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(
                     pyd = lds_py[j];
                     gl = lds_gw[row * vpt + k];
                     gr = lds_gw[(kRows + row) * vpt + k];
-                    // the next velocity (the last one loads its own again, which nothing reads)
-                    prefetch(k + 1 < vpt ? k + 1 : k);
+                    // the next velocity's loads (none after the last: the epilogue drains the counter)
+                    if (k + 1 < vpt) prefetch(k + 1);
                 } else {
                     T tmp[4];
                     bld4(rin, rowoff + oL, tmp, kstep);
