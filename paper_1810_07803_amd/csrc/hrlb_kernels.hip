@@ -1145,10 +1145,12 @@ __device__ __forceinline__ void gy_nodes_long(int q, int LN, int nyo, double uy,
 // averages and the range flag.  Shared by the per-cell kernel (global tables) and the small-case kernel
 // (tables in LDS, same layout).
 // SMALLB: only the unrolled buckets of expansion orders up to N_x = 10, N_y = 11 (the small-case path
-// admits no others), which keeps its register use down
+// admits no others), which keeps its register use down.  avg: whether the running averages are on
+// (-1: read it from the dynamic scalars)
 template <typename T, bool SMALLB = false>
 __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom], int q, int LN, int s, bool on,
-                                            int flags, double* sc, T* cell, const double* ktab, const CellLds& lay)
+                                            int flags, double* sc, T* cell, const double* ktab, const CellLds& lay,
+                                            int avg = -1)
 {
     const int nx = D.nx;
     const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
@@ -1223,7 +1225,7 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
         // flagged; non-finite values are caught by the residual check)
         const double Tr = Tm / D.Tw;
         if (Tr < kAuxTlo || Tr > kAuxThi || fabs(ux) > kAuxUmax * sqrt(D.Tw)) D.dyn[DY_RANGE] = 1.0;
-        if ((flags & FLAG_STEP_DONE) && D.dyn[DY_AVG_ON] != 0.0) {
+        if ((flags & FLAG_STEP_DONE) && (avg < 0 ? D.dyn[DY_AVG_ON] != 0.0 : avg != 0)) {
             // running sums of the fields at the end of every step (time averages, hrlb_average_*)
             double* A = D.avg;
             A[F_N * nx + s] += n;
@@ -1419,7 +1421,7 @@ struct SmallPtrs {
 // (FLAG_STEP_DONE also counts the step and its average); returns the wall densities
 template <typename T>
 __device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs<T>& S, const T* f, const CellLds& lay, int LN,
-                              int flags, double (*red)[4], double& nwl, double& nwr)
+                              int flags, double (*red)[4], double& nwl, double& nwr, int avg)
 {
     const int nx = D.nx, nv = D.nv, qy = D.qy, half = D.qx * qy;
     const int tid = threadIdx.x;
@@ -1471,7 +1473,7 @@ __device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs
             R[9] += pxv * x;
             R[10] += pyv * x;
         }
-        cell_tables<T, true>(D, R, q, LN, s, on, flags, S.sc, S.g, S.ktab, lay);
+        cell_tables<T, true>(D, R, q, LN, s, on, flags, S.sc, S.g, S.ktab, lay, avg);
         if (on && q == 0) {
             // the same arithmetic as the fields of cell_tables: n and P_xy of the cell
             const double n = R[0], ux = R[1] / n, uy = R[2] / n;
@@ -1480,14 +1482,11 @@ __device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs
         }
     }
     if (tid == 0) {
+        // stores only: the step counters are written once at the end of the launch
         D.dyn[DY_NWL] = nwl;
         D.dyn[DY_NWR] = nwr;
         D.dyn[DY_SHEAR_L] = D.half ? 0.0 : w[1] + nwl * D.mom_l;
         D.dyn[DY_SHEAR_R] = w[3] + nwr * D.mom_r;
-        if (flags & FLAG_STEP_DONE) {
-            D.dyn[DY_STEP] += 1.0;
-            if (D.dyn[DY_AVG_ON] != 0.0) D.dyn[DY_AVG_STEPS] += 1.0;
-        }
     }
     __syncthreads();
 }
@@ -1641,9 +1640,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
         S.g[kGIjd * nx + k] = (T)D.inv_jdeta[k];
     }
     __syncthreads();
-    uint32_t stepc = (uint32_t)D.dyn[DY_STEP];
+    // the step counter and the averaging switch, read once: nothing else changes them during the launch
+    const double step0 = D.dyn[DY_STEP];
+    const int avg = D.dyn[DY_AVG_ON] != 0.0;
+    uint32_t stepc = (uint32_t)step0;
     double nwl = 0.0, nwr = 0.0;
-    small_analyze<T>(D, S, S.b0, lay, LN, 0, red, nwl, nwr);
+    small_analyze<T>(D, S, S.b0, lay, LN, 0, red, nwl, nwr, avg);
     double rnum = 0.0, rden = 0.0;
 #pragma unroll 1
     for (int k = 0; k < 3 * n_steps; ++k) {
@@ -1654,7 +1656,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
         T* fout = S.buf(stage == 2 ? 0 : stage + 1);
         small_update<T>(D, S, fin, fout, stage, stepc, res, nwl, nwr, rnum, rden);
         if (stage == 2) ++stepc;
-        small_analyze<T>(D, S, fout, lay, LN, stage == 2 ? FLAG_STEP_DONE : 0, red, nwl, nwr);
+        small_analyze<T>(D, S, fout, lay, LN, stage == 2 ? FLAG_STEP_DONE : 0, red, nwl, nwr, avg);
     }
     if (check) {
         // residual, J-weighted mean P_xy and mass of the final state, as the tiled path's check
@@ -1677,8 +1679,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
             const double scale = D.jsum / r[3];
             for (size_t k = tid; k < nst; k += kSmallThreads) S.b0[k] = (T)((double)S.b0[k] * scale);
             __syncthreads();
-            small_analyze<T>(D, S, S.b0, lay, LN, FLAG_FIELDS, red, nwl, nwr);
+            small_analyze<T>(D, S, S.b0, lay, LN, FLAG_FIELDS, red, nwl, nwr, avg);
         }
+    }
+    if (tid == 0) {
+        D.dyn[DY_STEP] = step0 + (double)n_steps;
+        if (avg) D.dyn[DY_AVG_STEPS] += (double)n_steps;
     }
     T* fo = (T*)D.f[0];
     for (size_t k = tid; k < nst; k += kSmallThreads) fo[k] = S.b0[k];
