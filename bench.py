@@ -60,7 +60,7 @@ WORKLOADS = {
     # the time step; the oracle reaches the same one at CFL 1), at most 1M steps; the default run serves
     # the first 32 requests of this trace next to the batch
     "couette_serve_poisson200_pxyerr": dict(kind="serve", precision=1, rounding=1, requests=64, rate=200.0,
-                                            tol=3e-6, stop_rule=2, max_steps=1000000, check_every=500,
+                                            tol=3e-6, stop_rule=2, max_steps=1000000, check_every=250,
                                             local_dt_cap=64.0, cfl=1.0),
     # the quadrature-convergence claim of Sec. IV in its own setting: half channel, A = 0.98,
     # u_w = sqrt(2 K_B T_w/m), delta in {10, 1, 0.1}; the production models HHLB(6;7) x HLB(6;7)
