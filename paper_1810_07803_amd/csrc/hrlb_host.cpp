@@ -998,7 +998,7 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         if (sa != HRLB_OK) return sa;
     }
     long taken = 0;
-    hrlb_status verdict = HRLB_NOT_CONVERGED;
+    hrlb_status decision = HRLB_NOT_CONVERGED;
     double dy[kNDyn];
     SteadyTrack track;
     while (taken < max_steps) {
@@ -1011,7 +1011,7 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         c->steps_done += n;
         const hrlb_status v = steady_update(track, dy, n, c->dt, tol, stop_rule);
         if (v != HRLB_NOT_CONVERGED) {
-            verdict = v;
+            decision = v;
             if (v == HRLB_E_DIVERGED) fail(HRLB_E_DIVERGED, "non-finite residual after %ld steps", c->steps_done);
             if (v == HRLB_E_RANGE) range_message(c->steps_done);
             break;
@@ -1027,7 +1027,7 @@ extern "C" hrlb_status hrlb_run_to_steady(hrlb_case* c, double tol, long max_ste
         info->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->mass_drift = taken > 0 ? (dy[DY_MASS] - c->mass0) / c->mass0 : 0.0;
     }
-    return verdict;
+    return decision;
 }
 
 extern "C" hrlb_status hrlb_moments(hrlb_case* c, double* fields, double* x, double* Pi, double* wall_shear)

@@ -89,11 +89,11 @@ struct hrlb_server {
     }
 
     // ends a resident solve: results to the host (DONE) or the error (FAILED); frees its memory
-    void retire(Request* rq, hrlb_status verdict, const double* dy)
+    void retire(Request* rq, hrlb_status decision, const double* dy)
     {
         rq->t_done = now();
-        rq->status = verdict;
-        if (verdict == HRLB_OK || verdict == HRLB_NOT_CONVERGED) {
+        rq->status = decision;
+        if (decision == HRLB_OK || decision == HRLB_NOT_CONVERGED) {
             const int nx = rq->r.params.n_cells;
             rq->fields.assign((size_t)kNFields * nx, 0.0);
             rq->x.assign(nx, 0.0);
