@@ -46,7 +46,7 @@ CASES = [  # name, Qx, Qy, nx, steps, kw
 ]
 
 
-@pytest.mark.parametrize("precision,rounding,tol", [(0, 0, FP64_TOL), (1, 1, FP32_TOL)])
+@pytest.mark.parametrize("precision,rounding,tol", [(0, 0, FP64_TOL), (1, 1, FP32_TOL), (1, 0, FP32_TOL)])
 @pytest.mark.parametrize("name,Qx,Qy,nx,steps,kw", CASES)
 def test_small_path_fixed_step_parity(name, Qx, Qy, nx, steps, kw, precision, rounding, tol):
     say(f"[small] {name} precision={precision}: {steps} steps in launches of 1, 7 and the rest")
