@@ -435,6 +435,9 @@ def main(argv=None):
     from paper_1810_07803_amd import profiling
 
     traffic = profiling.load_traffic(os.path.join(ROOT, "profiles", f"{args.workload}_stage_kernel_traffic.txt"))
+    tname = "float" if es == 4 else "double"
+    valu = profiling.load_sq(os.path.join(ROOT, "profiles", f"{args.workload}_sq_counters.md"),
+                             [f"stage_kernel<{tname}, {m}>" for m in (1, 2, 3)])
     # the method floor: a whole step reads and writes phi and chi once in the storage precision
     # (2 x 2 x es bytes per unit) at the HBM peak
     floor_frac = value * 4 * es / (HBM_PEAK_GBS * 1e9)
@@ -446,7 +449,11 @@ def main(argv=None):
                 "small_path_instances": n_small,
                 "launches": "whole batch on one stream",
                 "method_floor_frac": round(floor_frac, 4),
-                "method_floor_bytes_per_unit_per_step": 4 * es}
+                "method_floor_bytes_per_unit_per_step": 4 * es,
+                # VALU instructions per unit and issue share of the step kernels from the SQ-counter
+                # profile of the same kernels (null once the kernels have changed): the kernel is bound
+                # by VALU issue, not by HBM
+                "valu": valu}
 
     cpu = None
     if not args.no_cpu_baseline:

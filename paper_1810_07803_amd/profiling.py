@@ -153,6 +153,27 @@ def load_traffic(path: str):
         return None
 
 
+def load_sq(path: str, kernels):
+    """From an SQ-counter summary: the VALU instructions per unit and the VALU issue share averaged over
+    the given kernels weighted by their dispatch counts, or None if absent or the kernels have changed."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel source digest: (\w+)", text)
+    if not m or m.group(1) != source_digest():
+        return None
+    rows = {}
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 7 and cells[0] in kernels:
+            rows[cells[0]] = (int(cells[1]), float(cells[3]), float(cells[6]))
+    if not rows:
+        return None
+    n = sum(r[0] for r in rows.values())
+    return {"valu_per_unit": round(sum(r[0] * r[1] for r in rows.values()) / n, 1),
+            "valu_issue_share": round(sum(r[0] * r[2] for r in rows.values()) / n, 3)}
+
+
 if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "stats":

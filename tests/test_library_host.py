@@ -119,3 +119,35 @@ def test_new_case_parameters_and_empty_batches_are_validated():
             hrlb.Quadrature(Qx, Qy)
     n = C.c_size_t()
     assert hrlb.load().hrlb_batch_workspace_bytes(None, 0, C.byref(n)) == hrlb.HRLB_E_INVALID
+
+
+def test_sq_summary_round_trip_and_digest_guard(tmp_path):
+    # the SQ-counter summary the profiling helper writes is read back by the benchmark only while the
+    # kernel sources keep the digest it records
+    import csv
+
+    from paper_1810_07803_amd import profiling
+
+    path = tmp_path / "run_counter_collection.csv"
+    cols = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    rows = []
+    for disp, kern, valu in ((1, "void hrlb::stage_kernel<float, 1>(args)", 1000.0),
+                             (2, "void hrlb::stage_kernel<float, 2>(args)", 3000.0),
+                             (3, "void hrlb::stage_kernel<float, 2>(args)", 3000.0)):
+        for name, val in (("SQ_INSTS_VALU", valu), ("SQ_INSTS_LDS", 10.0), ("SQ_INSTS_SALU", 5.0)):
+            rows.append(dict(Dispatch_Id=disp, Kernel_Name=kern, Counter_Name=name, Counter_Value=val,
+                             Start_Timestamp=0, End_Timestamp=1000))
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=cols)
+        w.writeheader()
+        w.writerows(rows)
+    summary = tmp_path / "sq.md"
+    summary.write_text(profiling.sq(str(path), 64.0, "cmd"))
+    got = profiling.load_sq(str(summary), ["stage_kernel<float, 1>", "stage_kernel<float, 2>"])
+    # VALU per unit: wave instructions x 64 lanes / 64 units; weighted by dispatches (1 and 2)
+    assert got["valu_per_unit"] == round((1000.0 + 2 * 3000.0) / 3, 1)
+    # issue share: instructions x 4 cycles / (1024 SIMDs x 1000 ns x 2.4 GHz)
+    assert got["valu_issue_share"] == round((1000.0 * 4 / 2457600 + 2 * 3000.0 * 4 / 2457600) / 3, 3)
+    stale = summary.read_text().replace(profiling.source_digest(), "0000000000000000")
+    summary.write_text(stale)
+    assert profiling.load_sq(str(summary), ["stage_kernel<float, 1>"]) is None
