@@ -243,6 +243,15 @@ void hrlb_free_case(hrlb_case *c);
 void hrlb_free_quadrature(hrlb_quad *q);
 const char *hrlb_last_error(void);
 
+/* The estimate behind HRLB_STOP_PXY_ERR (not a step of the paper's method; the stop rule of the
+ * serving metric, a fixed error of the channel-mean P_xy): means[count] are successive checked values
+ * of the mean P_xy (count >= 3; hrlb_run_to_steady and the server use the last 9).  The count - 1
+ * differences d are taken as decaying geometrically with a rate r per check fitted by least squares
+ * to log|d|; *estimate = max(|d_last|, |d_prev|) r/(1 - r) / |means[count - 1]|, 0 when the last two
+ * differences are exactly zero, +inf while r >= 1 or another difference is exactly zero.  Host
+ * only.  HRLB_E_INVALID for count < 3 or a NULL pointer. */
+hrlb_status hrlb_pxy_error_estimate(const double *means, int count, double *estimate);
+
 /* ---- batching: several cases, possibly of different sizes and velocity sets, advanced by shared
  * kernel launches.  The cases of the tiled path are split into parts of about equal work (velocities x
  * cells); each part is advanced by one persistent launch per stage and kernel on a stream of its own,

@@ -936,6 +936,39 @@ extern "C" hrlb_status hrlb_tune_plan(const hrlb_quad* q, const hrlb_case_params
     return HRLB_OK;
 }
 
+// Remaining absolute error of the last of m checked means of P_xy (m >= 3): the m - 1 differences d are
+// taken as decaying geometrically, their rate r per check fitted by least squares to log|d| (a fit over
+// several checks is not thrown off by two modes overlapping, which makes a three-point extrapolation
+// under-estimate), and the error bounded by max(|d_last|, |d_prev|) r / (1 - r).  0 when the last two
+// differences are exactly zero; HUGE_VAL while the fitted rate is >= 1 or another difference is zero.
+double hrlb::pxy_error_bound(const double* m, int count)
+{
+    const int W = count - 1;
+    double est = HUGE_VAL;
+    bool zero = false;
+    for (int k = 0; k < W; ++k) zero = zero || m[k + 1] == m[k];
+    if (m[W] == m[W - 1] && m[W - 1] == m[W - 2]) return 0.0;
+    if (zero) return est;
+    double sy = 0.0, sxy = 0.0, sxx = 0.0;
+    for (int k = 0; k < W; ++k) sy += std::log(std::fabs(m[k + 1] - m[k]));
+    const double xm = 0.5 * (W - 1), ym = sy / W;
+    for (int k = 0; k < W; ++k) {
+        sxy += (k - xm) * (std::log(std::fabs(m[k + 1] - m[k])) - ym);
+        sxx += (k - xm) * (k - xm);
+    }
+    const double r = std::exp(sxy / sxx);
+    if (r < 1.0) est = std::max(std::fabs(m[W] - m[W - 1]), std::fabs(m[W - 1] - m[W - 2])) * r / (1.0 - r);
+    return est;
+}
+
+extern "C" hrlb_status hrlb_pxy_error_estimate(const double* means, int count, double* estimate)
+{
+    if (!means || !estimate || count < 3) return fail(HRLB_E_INVALID, "need at least 3 means and an output pointer");
+    const double last = std::fabs(means[count - 1]);
+    *estimate = pxy_error_bound(means, count) / std::max(last, 1e-300);
+    return HRLB_OK;
+}
+
 hrlb_status hrlb::steady_update(SteadyTrack& t, const double* dy, long n, double dt, double tol, int stop_rule)
 {
     t.res = std::sqrt(dy[DY_RES_NUM]) / (dt * std::sqrt(dy[DY_RES_DEN]));
@@ -945,34 +978,11 @@ hrlb_status hrlb::steady_update(SteadyTrack& t, const double* dy, long n, double
     if (t.have_prev) t.drift = std::fabs(pxy - t.pxy_prev) / (n * dt * std::max(std::fabs(pxy), 1e-300));
     t.have_prev = true;
     t.pxy_prev = pxy;
-    // remaining relative error of the mean P_xy: the last kPxyWin differences of checked means are taken
-    // as decaying geometrically, their rate r per check fitted by least squares to log|d| (a fit over
-    // several checks is not thrown off by two modes overlapping, which makes a three-point extrapolation
-    // under-estimate), and the error bounded by max(|d_last|, |d_prev|) r / (1 - r); no estimate while
-    // the fitted rate is >= 1 or a difference is exactly zero (unless the last two are)
     constexpr int W = SteadyTrack::kPxyWin;
     for (int k = 0; k < W; ++k) t.pxy[k] = t.pxy[k + 1];
     t.pxy[W] = pxy;
     if (++t.nchk > W) {
-        double d[W], est = HUGE_VAL;
-        bool zero = false;
-        for (int k = 0; k < W; ++k) {
-            d[k] = std::fabs(t.pxy[k + 1] - t.pxy[k]);
-            zero = zero || d[k] == 0.0;
-        }
-        if (d[W - 1] == 0.0 && d[W - 2] == 0.0) {
-            est = 0.0;
-        } else if (!zero) {
-            double sy = 0.0, sxy = 0.0, sxx = 0.0;
-            for (int k = 0; k < W; ++k) sy += std::log(d[k]);
-            const double xm = 0.5 * (W - 1), ym = sy / W;
-            for (int k = 0; k < W; ++k) {
-                sxy += (k - xm) * (std::log(d[k]) - ym);
-                sxx += (k - xm) * (k - xm);
-            }
-            const double r = std::exp(sxy / sxx);
-            if (r < 1.0) est = std::max(d[W - 1], d[W - 2]) * r / (1.0 - r);
-        }
+        const double est = pxy_error_bound(t.pxy, W + 1);
         t.err = est / std::max(std::fabs(pxy), 1e-300);
         t.below = t.err < tol ? t.below + 1 : 0;
     }

@@ -109,6 +109,8 @@ struct SteadyTrack {
 // Returns HRLB_OK when the stop criterion is below tol, HRLB_NOT_CONVERGED to go on, and
 // HRLB_E_DIVERGED (with the message set) on a non-finite value.
 hrlb_status steady_update(SteadyTrack& t, const double* dy, long n, double dt, double tol, int stop_rule);
+// remaining absolute error of the last of count checked means of P_xy (the P_xy error rule)
+double pxy_error_bound(const double* means, int count);
 // sets the thread's error message of HRLB_E_RANGE
 void range_message(long steps);
 // HRLB_OK unless the case lives in the static scratch and a later static case on its device replaced it

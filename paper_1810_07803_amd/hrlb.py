@@ -36,6 +36,7 @@ EXPORTED = (
     "hrlb_tune_workspace_bytes", "hrlb_tune_plan",
     "hrlb_server_create", "hrlb_server_clock", "hrlb_server_submit", "hrlb_server_pump", "hrlb_server_request",
     "hrlb_server_free", "hrlb_average_start", "hrlb_average_stop", "hrlb_average_read",
+    "hrlb_pxy_error_estimate",
 )
 HRLB_REQ_WAITING, HRLB_REQ_ACTIVE, HRLB_REQ_DONE, HRLB_REQ_FAILED = 0, 1, 2, 3
 
@@ -135,6 +136,7 @@ def load() -> C.CDLL:
                 "hrlb_server_submit": [vp, C.POINTER(SolveRequest), C.POINTER(C.c_long)],
                 "hrlb_server_pump": [vp, C.POINTER(ServerStats)],
                 "hrlb_server_request": [vp, C.c_long, C.POINTER(RequestInfo), dp, dp, C.c_int],
+                "hrlb_pxy_error_estimate": [dp, C.c_int, dp],
             }
             for name, args in sig.items():
                 fn = getattr(lib, name)
@@ -149,6 +151,14 @@ def load() -> C.CDLL:
             lib.hrlb_last_error.restype = C.c_char_p
             _lib = lib
     return _lib
+
+
+def pxy_error_estimate(means) -> float:
+    """The estimate behind HRLB_STOP_PXY_ERR for successive checked means of P_xy (host only)."""
+    m = np.ascontiguousarray(means, dtype=np.float64)
+    est = C.c_double()
+    _check(load().hrlb_pxy_error_estimate(_dptr(m), len(m), C.byref(est)))
+    return est.value
 
 
 def _check(status: int, allow=(HRLB_OK,)) -> int:

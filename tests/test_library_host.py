@@ -151,3 +151,36 @@ def test_sq_summary_round_trip_and_digest_guard(tmp_path):
     stale = summary.read_text().replace(profiling.source_digest(), "0000000000000000")
     summary.write_text(stale)
     assert profiling.load_sq(str(summary), ["stage_kernel<float, 1>"]) is None
+
+
+def test_pxy_error_estimate_against_closed_forms():
+    # the estimate behind the P_xy error stop rule (host only), against sequences whose remaining error is
+    # known in closed form
+    import numpy as np
+
+    from paper_1810_07803_amd import hrlb
+
+    L, c = -0.25, 3e-3
+    k = np.arange(9)
+    # exact geometric decay m_k = L + c r^k (differences d_k = m_{k+1} - m_k, k = 0..7): the fitted rate
+    # is r and max(|d_7|, |d_6|) r / (1 - r) = |d_6| r / (1 - r) = c r^7, the remaining error c r^8
+    # over r (one check of margin)
+    for r in (0.3, 0.7, 0.95):
+        m = L + c * r ** k
+        assert hrlb.pxy_error_estimate(m) == pytest.approx(c * r ** 7 / abs(m[-1]), rel=1e-9)
+        assert hrlb.pxy_error_estimate(m) >= abs(m[-1] - L) / abs(m[-1])
+    # alternating decay m_k = L + c (-r)^k: |d| decays at r, |d_6| = c r^6 (1 + r), and the bound is
+    # c r^7 (1 + r)/(1 - r), above the remaining error c r^8
+    r = 0.6
+    m = L + c * (-r) ** k
+    assert hrlb.pxy_error_estimate(m) == pytest.approx(c * r ** 7 * (1 + r) / (1 - r) / abs(m[-1]), rel=1e-9)
+    # settled: the last two differences exactly zero
+    m = np.array([L + 1e-3, L + 1e-4, L + 1e-5, L, L, L])
+    assert hrlb.pxy_error_estimate(m) == 0.0
+    # not decaying (fitted rate >= 1), or a zero difference inside the window: no estimate
+    assert hrlb.pxy_error_estimate(L + 1e-6 * 1.1 ** k) == float("inf")
+    m = L + c * 0.5 ** k
+    m[3] = m[2]
+    assert hrlb.pxy_error_estimate(m) == float("inf")
+    with pytest.raises(hrlb.HrlbError):
+        hrlb.pxy_error_estimate([L, L])
