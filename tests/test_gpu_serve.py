@@ -120,3 +120,36 @@ def test_served_solve_matches_oracle_at_the_same_stop():
     say(f"   steps {info.steps}")
     assert moment_errs(f, orc.moments(phi, chi), 1e-12)
     srv.free()
+
+
+def test_served_with_the_pxy_error_rule_equals_alone():
+    # the serving configuration of the benchmark: FP32 with stochastic rounding, local time steps (cap
+    # 64), CFL 1, the P_xy error rule checked every 250 steps; every request stops at the same step, with
+    # the same estimate and the same fields, as the same solve alone
+    from paper_1810_07803_amd import hrlb
+
+    say("[serve] P_xy error rule, FP32, local steps, CFL 1: served vs alone")
+    every, tol, cap = 250, 3e-6, 20000
+
+    def params(k):
+        Qx, Qy, nx, delta, uw, omega, A = REQS[k]
+        return hrlb.make_params(delta=delta, uw=uw, ncell=nx, stretch_A=A, omega=omega, precision=1,
+                                rounding=1, seed=2000 + k, local_dt_cap=64.0, cfl=1.0)
+
+    srv = hrlb.Server(256 << 20, max_active=8, check_every=every, max_bypass=2, precision=1)
+    ids = [srv.submit(REQS[k][0], REQS[k][1], params(k), tol=tol, max_steps=cap, stop_rule=hrlb.HRLB_STOP_PXY_ERR)
+           for k in range(len(REQS))]
+    while True:
+        st = srv.pump()
+        if st.waiting == 0 and st.active == 0:
+            break
+    for k, rid in enumerate(ids):
+        info, f, _ = srv.request(rid)
+        c = hrlb.Case(hrlb.Quadrature(REQS[k][0], REQS[k][1]), params(k))
+        st_a, info_a = c.run_to_steady(tol, cap, every, hrlb.HRLB_STOP_PXY_ERR)
+        say(f"   req {k}: status {info.status} steps {info.steps} (alone {info_a.steps}), "
+            f"estimate {info.pxy_err:.2e} (alone {info_a.pxy_err:.2e})")
+        assert info.status == st_a and info.steps == info_a.steps
+        assert info.pxy_err == info_a.pxy_err
+        np.testing.assert_array_equal(f, c.moments()[0])
+    srv.free()
