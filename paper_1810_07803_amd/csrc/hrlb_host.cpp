@@ -601,6 +601,14 @@ hrlb_status init_case_in(const hrlb_quad* q, const hrlb_case_params* p, const La
     D.mom_r = mom_r;
     D.jsum = 0.0;
     for (int s = 0; s < nx; ++s) D.jsum += c->jdeta[s];
+    D.inv_Tw = 1.0 / p->T_w;
+    D.visc_y = 1.0 - p->omega;
+    D.band_tlo = kAuxTlo * p->T_w;
+    D.band_thi = kAuxThi * p->T_w;
+    D.band_u = kAuxUmax * std::sqrt(p->T_w);
+    D.aux2_tlo = kAux2Tlo * p->T_w;
+    D.aux2_thi = kAux2Thi * p->T_w;
+    D.aux2_u = kAux2Umax * std::sqrt(p->T_w);
     char* ws = aux;
     for (int k = 0; k < 3; ++k) D.f[k] = state + L.f[k];
     D.sc = (double*)(ws + L.cell);

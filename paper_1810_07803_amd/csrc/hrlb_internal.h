@@ -102,6 +102,10 @@ struct InstDesc {
     double den_l, den_r; // sum over entering directions of p_x g_x(0,T_w) g_y(-/+u_w,T_w)
     double mom_l, mom_r; // same sums weighted by p_y (incoming momentum flux per unit n_w)
     double jsum;         // sum_s J_s deta (channel width in x)
+    double inv_Tw;       // 1/T_w
+    double visc_y;       // 1 - omega: (T/T_w)^(1-omega) = exp(visc_y log(T inv_Tw))
+    double band_tlo, band_thi, band_u;  // kAuxTlo T_w, kAuxThi T_w, kAuxUmax sqrt(T_w)
+    double aux2_tlo, aux2_thi, aux2_u;  // kAux2Tlo T_w, kAux2Thi T_w, kAux2Umax sqrt(T_w)
     // device pointers (all inside the case workspace)
     void* f[3];          // state buffers, each [2][nv][nx] in the storage precision
     double* sc;          // [kNSc][nx] FP64 per-cell scalars of the collision

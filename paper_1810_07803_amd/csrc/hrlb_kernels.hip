@@ -996,25 +996,41 @@ __device__ __forceinline__ void wall_right(const InstDesc& D, const T* fcur)
     }
 }
 
-// sum over the lanes of a cell (lanes = 1, 2, 4, 8 or 16 consecutive lanes, aligned): a butterfly
-// whose step s adds the partner's value, identical in every lane afterwards.  The partners come from
-// DPP patterns inside a 16-lane row (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
-// row_mirror): after the steps before it, every lane of a group of 2^s holds the same value, so
-// these pair each group with the neighbouring one exactly as lane ^ 2^s would, and the sums (and
-// their bits) are those of the xor butterfly, without a trip through LDS.
-__device__ __forceinline__ double lane_sum(double x, int lanes)
+// sums over the lanes of a cell (lanes = 1, 2, 4, 8 or 16 consecutive lanes, aligned) of the N
+// values x and the M values y: a butterfly whose step s adds the partner's value, identical in every
+// lane afterwards.  The partners come from DPP patterns inside a 16-lane row (quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror): after the steps before it, every lane of a group
+// of 2^s holds the same value, so these pair each group with the neighbouring one exactly as
+// lane ^ 2^s would, and the sums (and their bits) are those of the xor butterfly, without a trip
+// through LDS.  One uniform branch per step covers every value.
+template <int N, int M = 0>
+__device__ __forceinline__ void lane_sums(double (&x)[N], double (&y)[M > 0 ? M : 1], int lanes)
 {
-    if (lanes > 1) x += dpp_partner<0xB1>(x);
-    if (lanes > 2) x += dpp_partner<0x4E>(x);
-    if (lanes > 4) x += dpp_partner<0x141>(x);
-    if (lanes > 8) x += dpp_partner<0x140>(x);
-    return x;
+    auto step = [&](auto ctrl) {
+        constexpr int C = decltype(ctrl)::value;
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] += dpp_partner<C>(x[i]);
+#pragma unroll
+        for (int i = 0; i < M; ++i) y[i] += dpp_partner<C>(y[i]);
+    };
+    if (lanes > 1) step(std::integral_constant<int, 0xB1>());
+    if (lanes > 2) step(std::integral_constant<int, 0x4E>());
+    if (lanes > 4) step(std::integral_constant<int, 0x141>());
+    if (lanes > 8) step(std::integral_constant<int, 0x140>());
 }
 
+// a pointer into global memory (address space 1) from a generic one: accesses through it count on
+// the vector memory counter alone, so that waits for LDS reads do not also wait for these stores
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T* p) { return (gptr<T>)p; }
+
 // eq. (gx) as the projection of g/omega on h_0..h_{NB-1} (rows beyond N_x are zero) with the
-// auxiliary rule: lane q of the cell takes nodes k = q, q + L, ...; two nodes per iteration keep two
-// independent exponential chains in flight (one node per iteration for the largest row count, whose
-// accumulators already fill the register budget).  Partial sums in k order, then an xor butterfly.
+// auxiliary rule: lane q of the cell takes nodes k = q, q + L, ...; three nodes per iteration (up to
+// 8 rows) or two (up to 11) keep that many independent exponential chains in flight (one node per
+// iteration for the largest row count, whose accumulators already fill the register budget).  Partial
+// sums in k order, then an xor butterfly.
 // The rule is scaled to T_w (nodes Z of the weight exp(-p^2/(2 T_w))), on which the integrand is
 // exp(Z^2 (T/T_w - 1)/(2T) + Z u/T - u^2/(2T))/sqrt(T) h_l(Z).
 template <int NB>
@@ -1028,6 +1044,25 @@ __device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, do
     const double rsT = 1.0 / sqrt(Tm);
     const double c0 = ((Tm - Tw) / Tw) * inv2T, c1 = ux * (2.0 * inv2T), c2 = ux * ux * inv2T;
     int k = q;
+    for (; NB <= 8 && k + 2 * LN < K; k += 3 * LN) {
+        double ep[3], em[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const double Z = s_az[k + u * LN];
+            const double a = Z * Z * c0 - c2, bb = Z * c1;
+            const double wk = s_aw[k + u * LN] * rsT;
+            ep[u] = wk * exp(a + bb);
+            em[u] = wk * exp(a - bb);
+        }
+#pragma unroll
+        for (int l = 0; l < NB; ++l)
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const double h = s_hZ[l * K + k + u * LN];
+                Ip[l] += ep[u] * h;
+                Im[l] += em[u] * h;
+            }
+    }
     for (; NB <= 11 && k + LN < K; k += 2 * LN) {
         const double Z0 = s_az[k], Z1 = s_az[k + LN];
         const double a0 = Z0 * Z0 * c0 - c2, a1 = Z1 * Z1 * c0 - c2;
@@ -1056,28 +1091,21 @@ __device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, do
             Im[l] += em * h;
         }
     }
-#pragma unroll
-    for (int l = 0; l < NB; ++l)
-        if (l <= nxo) {  // uniform over the block
-            Ip[l] = lane_sum(Ip[l], LN);
-            Im[l] = lane_sum(Im[l], LN);
-        }
+    // rows beyond N_x hold zeros in every lane: summing them leaves them zero
+    lane_sums<NB, NB>(Ip, Im, LN);
 }
 
-// g_x at the 2 Q_x nodes from the projections: n w_i sum_l I_l h_l(z_i); the 24-node auxiliary rule
-// (ktab at s_az2) where it is as accurate as the 48-node one, the latter elsewhere (the same choice in
-// every lane of a cell).  With 16 lanes per cell the 24 nodes would split unevenly over the lanes
+// g_x at the 2 Q_x nodes from the projections: n w_i sum_l I_l h_l(z_i); small: the 24-node auxiliary
+// rule (ktab at s_az2), else the 48-node one.  With 16 lanes per cell the 24 nodes would split unevenly over the lanes
 // (pairs on 8 of them, single nodes on the others: both paths in every wave, no faster than the
 // 48-node split), so such plans keep the 48-node rule.
-template <typename T, int NB>
-__device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, double Tm, double Tw, double ux, bool on,
+template <typename T, int NB, typename CP>
+__device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, double Tm, double Tw, double ux, bool small, bool on,
                                          int s, int nx, int qxn, const double* s_wx, const double* s_az,
                                          const double* s_aw, const double* s_hZ, const double* s_az2,
-                                         const double* s_hz, T* cell)
+                                         const double* s_hz, CP cell)
 {
     double Ip[NB], Im[NB];
-    const bool small = uses_aux2(LN) && Tm >= kAux2Tlo * Tw && Tm <= kAux2Thi * Tw &&
-                       fabs(ux) <= kAux2Umax * sqrt(Tw);
     if (small)
         gx_project<NB>(q, LN, nxo, Tm, Tw, ux, kAux2, s_az2, s_az2 + kAux2, s_az2 + 2 * kAux2, Ip, Im);
     else
@@ -1100,9 +1128,9 @@ __device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, doubl
 
 // eq. (gy): c_l = coefficient of t^l in exp(u t + (T-1) t^2/2), l c_l = u c_{l-1} + (T-1) c_{l-2};
 // NB rows of the He table, zero beyond N_y
-template <typename T, int NB>
+template <typename T, int NB, typename CP>
 __device__ __forceinline__ void gy_nodes(int q, int LN, int nyo, double uy, double Tm, bool on, int s, int nx,
-                                         int qxn, int nqy, const double* s_wy, const double* s_he, T* cell)
+                                         int qxn, int nqy, const double* s_wy, const double* s_he, CP cell)
 {
     const double tm1 = Tm - 1.0;
     double cl[NB];
@@ -1121,9 +1149,9 @@ __device__ __forceinline__ void gy_nodes(int q, int LN, int nyo, double uy, doub
 }
 
 // the same for orders beyond the unrolled buckets: the recurrence runs once per output node
-template <typename T>
+template <typename T, typename CP>
 __device__ __forceinline__ void gy_nodes_long(int q, int LN, int nyo, double uy, double Tm, bool on, int s, int nx,
-                                              int qxn, int nqy, const double* s_wy, const double* s_he, T* cell)
+                                              int qxn, int nqy, const double* s_wy, const double* s_he, CP cell)
 {
     const double tm1 = Tm - 1.0;
     for (int j = q; j < nqy; j += LN) {
@@ -1162,8 +1190,17 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
     const double* s_hz = ktab + lay.hz;
     const double* s_he = ktab + lay.he;
     const double* s_az2 = ktab + lay.az2;
-#pragma unroll
-    for (int m = 0; m < kNMom; ++m) R[m] = lane_sum(R[m], LN);
+    // the tiled path's tables are global memory, the small-case path's LDS
+    const auto scp = [&]() {
+        if constexpr (SMALLB) return sc; else return gmem(sc);
+    }();
+    const auto cellp = [&]() {
+        if constexpr (SMALLB) return cell; else return gmem(cell);
+    }();
+    {
+        double none[1];
+        lane_sums<kNMom>(R, none, LN);
+    }
 
     // moments of Sec. II from the raw sums (shift to the peculiar velocity xi = p - u)
     const double n = R[0];
@@ -1191,7 +1228,9 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
         visc_lookup(D.vT, D.vMu, D.vOm, D.vPr, D.ntab, Tm, &mu, &pr);
         invtau = D.tau_pref * n * (Tm / D.Tw) * (D.mu_w / mu);
     } else {
-        invtau = D.tau_pref * n * pow(Tm / D.Tw, 1.0 - D.omega);
+        // (T/T_w)^(1-omega) as an exponential of a logarithm: about half the instructions of pow, and
+        // (T/T_w near 1, |1-omega| <= 1) within a few units in the last place of it
+        invtau = D.tau_pref * n * exp(D.visc_y * log(Tm * D.inv_Tw));
     }
     if (D.collisionless) invtau = 0.0;
     const double As = (1.0 - pr) / (n * Tm * Tm);
@@ -1199,7 +1238,7 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
 
     if (on && q == 0) {
         if (flags & (FLAG_STEP_DONE | FLAG_FIELDS)) {
-            double* F = D.fields;
+            const gptr<double> F = gmem(D.fields);
             F[F_N * nx + s] = n;
             F[F_UX * nx + s] = ux;
             F[F_UY * nx + s] = uy;
@@ -1211,23 +1250,22 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
             F[F_QX * nx + s] = qx;
             F[F_QY * nx + s] = qy;
         }
-        sc[SC_UX * nx + s] = ux;
-        sc[SC_UY * nx + s] = uy;
-        sc[SC_T * nx + s] = Tm;
-        sc[SC_INVTAU * nx + s] = invtau;
-        sc[SC_S8 * nx + s] = 0.8 * As;
-        sc[SC_S4 * nx + s] = 0.4 * As;
-        sc[SC_AS5T * nx + s] = As5T;
-        sc[SC_QX * nx + s] = qx;
-        sc[SC_QY * nx + s] = qy;
-        if constexpr (!SMALLB) cell[kGIjd * nx + s] = (T)D.inv_jdeta[s];  // the small path fills it once
+        scp[SC_UX * nx + s] = ux;
+        scp[SC_UY * nx + s] = uy;
+        scp[SC_T * nx + s] = Tm;
+        scp[SC_INVTAU * nx + s] = invtau;
+        scp[SC_S8 * nx + s] = 0.8 * As;
+        scp[SC_S4 * nx + s] = 0.4 * As;
+        scp[SC_AS5T * nx + s] = As5T;
+        scp[SC_QX * nx + s] = qx;
+        scp[SC_QY * nx + s] = qy;
+        if constexpr (!SMALLB) cellp[kGIjd * nx + s] = (T)D.inv_jdeta[s];  // the small path fills it once
         // the band in which the projection of eq. (gx) is verified (a finite state outside it is
         // flagged; non-finite values are caught by the residual check)
-        const double Tr = Tm / D.Tw;
-        if (Tr < kAuxTlo || Tr > kAuxThi || fabs(ux) > kAuxUmax * sqrt(D.Tw)) D.dyn[DY_RANGE] = 1.0;
+        if (Tm < D.band_tlo || Tm > D.band_thi || fabs(ux) > D.band_u) gmem(D.dyn)[DY_RANGE] = 1.0;
         if ((flags & FLAG_STEP_DONE) && (avg < 0 ? D.dyn[DY_AVG_ON] != 0.0 : avg != 0)) {
             // running sums of the fields at the end of every step (time averages, hrlb_average_*)
-            double* A = D.avg;
+            const gptr<double> A = gmem(D.avg);
             A[F_N * nx + s] += n;
             A[F_UX * nx + s] += ux;
             A[F_UY * nx + s] += uy;
@@ -1242,32 +1280,34 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
     }
 
     // g_x (eq. gx) and g_y (eq. gy) with the loops over the expansion order unrolled for the case's
-    // padded row count (uniform over the block)
+    // padded row count (uniform over the block); the 24-node auxiliary rule (ktab at s_az2) where it is
+    // as accurate as the 48-node one (the same choice in every lane of a cell)
+    const bool use2 = uses_aux2(LN) && Tm >= D.aux2_tlo && Tm <= D.aux2_thi && fabs(ux) <= D.aux2_u;
     switch (nxb) {
-        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
-        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell); break;
+        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
+        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
+        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
         default:
             if constexpr (!SMALLB)
-                gx_nodes<T, 17>(q, LN, nxo, n, Tm, D.Tw, ux, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cell);
+                gx_nodes<T, 17>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp);
             break;
     }
     if constexpr (SMALLB) {
         switch (nyb) {
-            case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-            case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-            default: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+            case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+            case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+            default: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
         }
         return;
     }
     switch (nyb) {
-        case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 12: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 16: gy_nodes<T, 16>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 20: gy_nodes<T, 20>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        case 32: gy_nodes<T, 32>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
-        default: gy_nodes_long<T>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cell); break;
+        case 4: gy_nodes<T, 4>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+        case 8: gy_nodes<T, 8>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+        case 12: gy_nodes<T, 12>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+        case 16: gy_nodes<T, 16>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+        case 20: gy_nodes<T, 20>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+        case 32: gy_nodes<T, 32>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
+        default: gy_nodes_long<T>(q, LN, nyo, uy, Tm, on, s, nx, qxn, nqy, s_wy, s_he, cellp); break;
     }
 }
 
@@ -1358,8 +1398,8 @@ __host__ __device__ inline int small_lanes(int nx)
     while (ln > 1 && ln * nx > kSmallThreads) ln >>= 1;
     return ln;
 }
-// per-velocity constants [p_x of the 2 Q_x nodes | p_y of the Q_y nodes | g_w left (nv) | g_w right (nv)]
-// and per-cell ones [dt_s | residual weight | J deta | 1/(J deta)], FP64
+// per-velocity constants [p_x of the 2 Q_x nodes | p_y of the Q_y nodes | g_w left (nv) | g_w right (nv) |
+// (p_x, p_y) of every velocity (2 nv)] and per-cell ones [dt_s | residual weight | J deta | 1/(J deta)], FP64
 __host__ __device__ inline SmallLds small_lds(int nx, int nv, int qx, int qy, int ktab_total, size_t es)
 {
     SmallLds o;
@@ -1377,7 +1417,7 @@ __host__ __device__ inline SmallLds small_lds(int nx, int nv, int qx, int qy, in
     o.pm = off;  // per cell: n and P_xy of the last analysed state
     off = align16(off + sizeof(double) * 2 * (size_t)nx);
     o.vel = off;
-    off = align16(off + sizeof(double) * (size_t)(2 * qx + qy + 2 * nv));
+    off = align16(off + sizeof(double) * (size_t)(2 * qx + qy + 4 * nv));
     o.cel = off;
     off = align16(off + sizeof(double) * 4 * (size_t)nx);
     o.total = off;
@@ -1413,28 +1453,29 @@ struct SmallPtrs {
     double* ktab;                           // quadrature tables of eqs. (gx), (gy)
     double* pm;                             // n and P_xy per cell of the last analysed state
     const double *px, *py, *gwl, *gwr;      // per-velocity constants
+    const double* pv;                       // (p_x, p_y) of velocity v at 2v, 2v + 1
     const double *dts, *jres, *jdeta;       // per-cell constants
     __device__ __forceinline__ T* buf(int k) const { return k == 0 ? b0 : k == 1 ? b1 : b2; }
 };
 
-// walls, moments and per-cell tables of the state f (block-wide); flags as the per-cell kernel's
-// (FLAG_STEP_DONE also counts the step and its average); returns the wall densities
+// Leaving fluxes through both walls (eq. diffuse_nw) of the state f: p_x F and p_x p_y F of the leaving
+// face values, F formed exactly as the per-cell kernel's wall blocks form it; velocity v < half leaves
+// through the right wall (p_x > 0), v >= half through the left one.  Every wave forms the whole sums
+// (lane l takes v = l, l + 64, ..., then a wave sum), so each holds the same bits without a block
+// reduction.  w: left flux, left momentum, right flux, right momentum.  (Inside the step loop the
+// update forms these sums from the values it stores.)
 template <typename T>
-__device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs<T>& S, const T* f, const CellLds& lay, int LN,
-                              int flags, double (*red)[4], double& nwl, double& nwr, int avg)
+__device__ __forceinline__ void small_walls(const InstDesc& D, const SmallPtrs<T>& S, const T* f, double (&w)[4])
 {
-    const int nx = D.nx, nv = D.nv, qy = D.qy, half = D.qx * qy;
-    const int tid = threadIdx.x;
-    // leaving fluxes through both walls (eq. diffuse_nw): p_x F and p_x p_y F of the leaving face values,
-    // F formed exactly as the per-cell kernel's wall blocks form it; velocity v < half leaves through the
-    // right wall (p_x > 0), v >= half through the left one
-    double w[4] = {0.0, 0.0, 0.0, 0.0};  // left flux, left momentum, right flux, right momentum
-    for (int v = tid; v < 2 * half; v += kSmallThreads) {
+    const int nx = D.nx, half = D.qx * D.qy;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = 0.0;
+    for (int v = threadIdx.x & 63; v < 2 * half; v += 64) {
         const bool right = v < half;
         if (!right && D.half) continue;
         const T* r = f + (size_t)v * nx;
         const T F = right ? wall_face_right(r[nx - 3], r[nx - 2], r[nx - 1]) : wall_face_left(r[0], r[1], r[2]);
-        const double pxv = S.px[v / qy], pyv = S.py[v % qy];
+        const double pxv = S.pv[2 * v], pyv = S.pv[2 * v + 1];
         const double a = pxv * (double)F, b = pxv * pyv * (double)F;
         if (right) {
             w[2] += a;
@@ -1444,7 +1485,19 @@ __device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs
             w[1] += b;
         }
     }
-    small_block_sum<4>(w, red);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = wave_sum(w[i]);
+}
+
+// moments and per-cell tables of the state f (block-wide) and the wall densities from its wall sums w
+// (identical in every thread); flags as the per-cell kernel's; returns the wall densities and the
+// y-momentum fluxes through the walls (stored once per launch)
+template <typename T>
+__device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs<T>& S, const T* f, const CellLds& lay, int LN,
+                              int flags, const double (&w)[4], double& nwl, double& nwr, double& shl, double& shr, int avg)
+{
+    const int nx = D.nx, nv = D.nv;
+    const int tid = threadIdx.x;
     nwl = D.half ? 0.0 : -w[0] / D.den_l;
     nwr = -w[2] / D.den_r;
     const int q = tid % LN;
@@ -1458,7 +1511,7 @@ __device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs
 #pragma unroll
         for (int m = 0; m < kNMom; ++m) R[m] = 0.0;
         for (int v = q; v < nv; v += LN) {
-            const double pxv = S.px[v / qy], pyv = S.py[v % qy];
+            const double pxv = S.pv[2 * v], pyv = S.pv[2 * v + 1];
             const double o = (double)f[(size_t)v * nx + sc_], x = (double)f[(size_t)(nv + v) * nx + sc_];
             const double p2 = pxv * pxv + pyv * pyv;
             R[0] += o;
@@ -1481,76 +1534,112 @@ __device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs
             S.pm[nx + s] = R[4] - n * ux * uy;
         }
     }
-    if (tid == 0) {
-        // stores only: the step counters are written once at the end of the launch
-        D.dyn[DY_NWL] = nwl;
-        D.dyn[DY_NWR] = nwr;
-        D.dyn[DY_SHEAR_L] = D.half ? 0.0 : w[1] + nwl * D.mom_l;
-        D.dyn[DY_SHEAR_R] = w[3] + nwr * D.mom_r;
-    }
+    shl = D.half ? 0.0 : w[1] + nwl * D.mom_l;
+    shr = w[3] + nwr * D.mom_r;
     __syncthreads();
 }
 
-// one SSP-RK3 stage from fin (f^n in S.b0) into fout, each item one distribution of one velocity over 4
-// cells; residual partials on request
+// one SSP-RK3 stage from fin (f^n in S.b0) into fout, each item one velocity over 4 cells, both
+// distributions (phi and chi share the velocity's constants, the cells' tables and the collision's
+// common terms; their two WENO windows are independent work); residual partials on request.  The
+// items that store a wall's three cells of a leaving velocity also form its leaving face value of phi
+// (as small_walls does, from the stored values), so that w returns the wall sums of fout, identical in
+// every thread (thread partials, wave sums, then the waves in order through red).
 template <typename T>
 __device__ __forceinline__ void small_update(const InstDesc& D, const SmallPtrs<T>& S, const T* fin, T* fout, int stage,
-                             uint32_t stepc, bool want_res, double nwl, double nwr, double& rnum, double& rden)
+                             uint32_t stepc, bool want_res, double nwl, double nwr, double& rnum, double& rden,
+                             double (*red)[4], double (&w)[4])
 {
-    const int nx = D.nx, nv = D.nv, qx = D.qx, qy = D.qy;
+    const int nx = D.nx, nv = D.nv, qx = D.qx, qy = D.qy, half = qx * qy;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = 0.0;
     const double ca = stage == 1 ? 0.75 : stage == 2 ? (1.0 / 3.0) : 0.0;
     const double cb = stage == 1 ? 0.25 : stage == 2 ? (2.0 / 3.0) : 1.0;
     const uint32_t rkey = D.rounding ? hash32(D.seed ^ hash32(stepc * 3u + (uint32_t)stage + 0x9e3779b9u)) : 0u;
     const int nstrip = nx / kStrip, per_dist = nv * nstrip;
     const T* fn = S.b0;
 #pragma unroll 1
-    for (int it = threadIdx.x; it < 2 * per_dist; it += kSmallThreads) {
-        const int d = it >= per_dist, r = it - d * per_dist;
+    for (int r = threadIdx.x; r < per_dist; r += kSmallThreads) {
         const int v = r / nstrip, s0 = (r - v * nstrip) * kStrip;
         const int hi = v / qy, j = v - hi * qy;
         const double pxd = S.px[hi], pyd = S.py[j];
         const T pxt = (T)pxd;
         const bool first = s0 == 0 && !D.half, mirror = s0 == 0 && D.half, last = s0 + kStrip == nx;
-        const size_t row = (size_t)(d * nv + v) * nx;
-        const T* fr = fin + row;
-        Win<T> P;
-        // window cells s0-4 .. s0+7; the tiled path's loads: cells 0..3 for the left window of the strip
-        // at cell 0, cells s0..s0+3 for the right window of the last strip (the ghost logic below replaces
-        // whatever of them the faces read)
+        size_t row[2];
+        Win<T> P[2];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            P.w[c] = fr[s0 == 0 ? c : s0 - 4 + c];
-            P.w[4 + c] = fr[s0 + c];
-            P.w[8 + c] = fr[last ? s0 + c : s0 + 4 + c];
+        for (int d = 0; d < 2; ++d) {
+            row[d] = (size_t)(d * nv + v) * nx;
+            const T* fr = fin + row[d];
+            // window cells s0-4 .. s0+7; the tiled path's loads: cells 0..3 for the left window of the
+            // strip at cell 0, cells s0..s0+3 for the right window of the last strip (the ghost logic
+            // below replaces whatever of them the faces read)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                P[d].w[c] = fr[s0 == 0 ? c : s0 - 4 + c];
+                P[d].w[4 + c] = fr[s0 + c];
+                P[d].w[8 + c] = fr[last ? s0 + c : s0 + 4 + c];
+            }
         }
         if (mirror) {
             // point symmetry of Sec. II about x = 0: ghost cells -1..-4 of (p_x, p_y) hold the values of
             // (-p_x, -p_y) in cells 0..3
             const int hmir = hi < qx ? hi + qx : hi - qx;
-            const T* fm = fin + (size_t)(d * nv + hmir * qy + (qy - 1 - j)) * nx;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) P.w[3 - c] = fm[c];
+            for (int d = 0; d < 2; ++d) {
+                const T* fm = fin + (size_t)(d * nv + hmir * qy + (qy - 1 - j)) * nx;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) P[d].w[3 - c] = fm[c];
+            }
+        }
+        // every table value and f^n of the 4 cells read before the first store: in FP64 the tables
+        // and the state share a type, so reads after a store would wait for it
+        double ux[kStrip], uy[kStrip], itau[kStrip], A5[kStrip], qxv[kStrip], qyv[kStrip], tt[kStrip];
+        double s8[kStrip], s4[kStrip], dts[kStrip], fnd[2][kStrip];
+        T ijd[kStrip], gy[kStrip], gx[kStrip];
+#pragma unroll
+        for (int c = 0; c < kStrip; ++c) {
+            const int s = s0 + c;
+            const double* sc = S.sc + s;
+            ux[c] = sc[SC_UX * nx];
+            uy[c] = sc[SC_UY * nx];
+            itau[c] = sc[SC_INVTAU * nx];
+            A5[c] = sc[SC_AS5T * nx];
+            qxv[c] = sc[SC_QX * nx];
+            qyv[c] = sc[SC_QY * nx];
+            tt[c] = sc[SC_T * nx];
+            s8[c] = sc[SC_S8 * nx];
+            s4[c] = sc[SC_S4 * nx];
+            ijd[c] = S.g[kGIjd * nx + s];
+            gy[c] = S.g[(kGx0 + 2 * qx + j) * nx + s];
+            gx[c] = S.g[(kGx0 + hi) * nx + s];
+            dts[c] = S.dts[s];
+#pragma unroll
+            for (int d = 0; d < 2; ++d) fnd[d][c] = stage > 0 ? (double)fn[row[d] + s] : 0.0;
         }
         // wall populations (eq. diffuse): n_w g_w for phi, T_w n_w g_w for chi
-        const double sl = d ? D.Tw * nwl : nwl, sr = d ? D.Tw * nwr : nwr;
-        const T wl = first ? (T)(sl * S.gwl[v]) : T(0), wr = last ? (T)(sr * S.gwr[v]) : T(0);
-        T F[5];
-        if (pxt > T(0)) {
-            if (first) P.w[1] = P.w[2] = P.w[3] = wl;
-            if (last) {
-                P.w[8] = ext_p3(P.w[5], P.w[6], P.w[7]);
-                P.w[9] = ext_p4(P.w[5], P.w[6], P.w[7]);
+        T F[2][5];
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+            const double sl = d ? D.Tw * nwl : nwl, sr = d ? D.Tw * nwr : nwr;
+            const T wl = first ? (T)(sl * S.gwl[v]) : T(0), wr = last ? (T)(sr * S.gwr[v]) : T(0);
+            if (pxt > T(0)) {
+                if (first) P[d].w[1] = P[d].w[2] = P[d].w[3] = wl;
+                if (last) {
+                    P[d].w[8] = ext_p3(P[d].w[5], P[d].w[6], P[d].w[7]);
+                    P[d].w[9] = ext_p4(P[d].w[5], P[d].w[6], P[d].w[7]);
+                }
+                P[d].faces_pos(F[d]);
+                if (first) F[d][0] = wl;
+            } else {
+                if (first) {
+                    P[d].w[3] = ext_m1(P[d].w[4], P[d].w[5], P[d].w[6]);
+                    P[d].w[2] = ext_m2(P[d].w[4], P[d].w[5], P[d].w[6]);
+                }
+                if (last) P[d].w[8] = P[d].w[9] = P[d].w[10] = wr;
+                P[d].faces_neg(F[d]);
+                if (last) F[d][4] = wr;
             }
-            P.faces_pos(F);
-            if (first) F[0] = wl;
-        } else {
-            if (first) {
-                P.w[3] = ext_m1(P.w[4], P.w[5], P.w[6]);
-                P.w[2] = ext_m2(P.w[4], P.w[5], P.w[6]);
-            }
-            if (last) P.w[8] = P.w[9] = P.w[10] = wr;
-            P.faces_neg(F);
-            if (last) F[4] = wr;
         }
         uint32_t rbits[kStrip] = {0, 0, 0, 0};
         if (D.rounding) {
@@ -1558,39 +1647,60 @@ __device__ __forceinline__ void small_update(const InstDesc& D, const SmallPtrs<
 #pragma unroll
             for (int c = 0; c < kStrip; ++c) rbits[c] = c == 0 ? hash32(base) : weyl32(rbits[c - 1]);
         }
+        T st[kStrip];  // the stored phi values
 #pragma unroll
         for (int c = 0; c < kStrip; ++c) {
             const int s = s0 + c;
-            const T fv = P.w[4 + c];
-            const double* sc = S.sc + s;
-            const double ux = sc[SC_UX * nx], uy = sc[SC_UY * nx], itau = sc[SC_INVTAU * nx];
-            const double A5 = sc[SC_AS5T * nx], qxv = sc[SC_QX * nx], qyv = sc[SC_QY * nx];
-            const T ijd = S.g[kGIjd * nx + s];
-            const T gy = S.g[(kGx0 + 2 * qx + j) * nx + s];
-            const T gx = S.g[(kGx0 + hi) * nx + s];
             // reduced Shakhov collision, Sec. II, in FP64 (the same operations as the tiled path): phi
             // relaxes to V - 0.8 A W = phi_eq (1 + S_phi), chi to T (V - 0.4 A W) = T phi_eq (1 + S_chi)
-            const double xx = pxd - ux, xy = pyd - uy;
+            const double xx = pxd - ux[c], xy = pyd - uy[c];
             const double x2 = xx * xx + xy * xy;
-            const double qxi = qxv * xx + qyv * xy;
-            const double feq = (double)gx * (double)gy;
+            const double qxi = qxv[c] * xx + qyv[c] * xy;
+            const double feq = (double)gx[c] * (double)gy[c];
             const double W = feq * qxi;
-            const double V = fma(W, A5 * x2, feq);
-            const double tg = d ? sc[SC_T * nx] * fma(-W, sc[SC_S4 * nx], V) : fma(-W, sc[SC_S8 * nx], V);
-            const T a = (F[c + 1] - F[c]) * (-pxt * ijd);
-            const double L = (double)a + (tg - (double)fv) * itau;
-            const double fnd = stage > 0 ? (double)fn[row + s] : 0.0;
-            const double oe = ca * fnd + cb * ((double)fv + S.dts[s] * L);
-            // stage 3 writes f^n in place: f^n is read only at an item's own cells, by that item
-            fout[row + s] = store_round<T>(oe, D.rounding, d ? rbits[c] >> 16 : rbits[c]);
-            if (want_res) {
-                const double dd = oe - fnd;
-                rnum += S.jres[s] * (dd * dd);
-                rden += S.jdeta[s] * (fnd * fnd);
+            const double V = fma(W, A5[c] * x2, feq);
+            const double tg[2] = {fma(-W, s8[c], V), tt[c] * fma(-W, s4[c], V)};
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const T fv = P[d].w[4 + c];
+                const T a = (F[d][c + 1] - F[d][c]) * (-pxt * ijd[c]);
+                const double L = (double)a + (tg[d] - (double)fv) * itau[c];
+                const double oe = ca * fnd[d][c] + cb * ((double)fv + dts[c] * L);
+                // stage 3 writes f^n in place: f^n is read only at an item's own cells, by that item
+                const T o = store_round<T>(oe, D.rounding, d ? rbits[c] >> 16 : rbits[c]);
+                if (d == 0) st[c] = o;
+                fout[row[d] + s] = o;
+                if (want_res) {
+                    const double dd = oe - fnd[d][c];
+                    rnum += S.jres[s] * (dd * dd);
+                    rden += S.jdeta[s] * (fnd[d][c] * fnd[d][c]);
+                }
             }
         }
+        // cells nx-3..nx-1 are cells 1..3 of the last strip, cells 0..2 those of the first
+        if (last && v < half) {
+            const T Fw = wall_face_right(st[1], st[2], st[3]);
+            w[2] += pxd * (double)Fw;
+            w[3] += pxd * pyd * (double)Fw;
+        }
+        if (first && v >= half) {
+            const T Fw = wall_face_left(st[0], st[1], st[2]);
+            w[0] += pxd * (double)Fw;
+            w[1] += pxd * pyd * (double)Fw;
+        }
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i] = wave_sum(w[i]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[threadIdx.x >> 6][i] = w[i];
     __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double t = 0.0;
+        for (int k = 0; k < kSmallThreads / 64; ++k) t += red[k][i];
+        w[i] = t;
+    }
 }
 
 template <typename T>
@@ -1618,6 +1728,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
     S.py = vel + 2 * qx;
     S.gwl = vel + 2 * qx + qy;
     S.gwr = vel + 2 * qx + qy + nv;
+    S.pv = vel + 2 * qx + qy + 2 * nv;
     S.dts = cel;
     S.jres = cel + nx;
     S.jdeta = cel + 2 * nx;
@@ -1632,6 +1743,8 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
     for (int k = tid; k < nv; k += kSmallThreads) {
         vel[2 * qx + qy + k] = D.gw_l[k];
         vel[2 * qx + qy + nv + k] = D.gw_r[k];
+        vel[2 * qx + qy + 2 * nv + 2 * k] = D.px[k / qy];
+        vel[2 * qx + qy + 2 * nv + 2 * k + 1] = D.py[k % qy];
     }
     for (int k = tid; k < nx; k += kSmallThreads) {
         cel[k] = D.dts[k];
@@ -1644,8 +1757,10 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
     const double step0 = D.dyn[DY_STEP];
     const int avg = D.dyn[DY_AVG_ON] != 0.0;
     uint32_t stepc = (uint32_t)step0;
-    double nwl = 0.0, nwr = 0.0;
-    small_analyze<T>(D, S, S.b0, lay, LN, 0, red, nwl, nwr, avg);
+    double nwl = 0.0, nwr = 0.0, shl = 0.0, shr = 0.0;
+    double w[4];
+    small_walls<T>(D, S, S.b0, w);
+    small_analyze<T>(D, S, S.b0, lay, LN, 0, w, nwl, nwr, shl, shr, avg);
     double rnum = 0.0, rden = 0.0;
 #pragma unroll 1
     for (int k = 0; k < 3 * n_steps; ++k) {
@@ -1654,9 +1769,12 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
         const bool res = check && k + 1 == 3 * n_steps;
         T* fin = S.buf(stage);
         T* fout = S.buf(stage == 2 ? 0 : stage + 1);
-        small_update<T>(D, S, fin, fout, stage, stepc, res, nwl, nwr, rnum, rden);
+        small_update<T>(D, S, fin, fout, stage, stepc, res, nwl, nwr, rnum, rden, red, w);
         if (stage == 2) ++stepc;
-        small_analyze<T>(D, S, fout, lay, LN, stage == 2 ? FLAG_STEP_DONE : 0, red, nwl, nwr, avg);
+        // the fields of the state at the end of every step are needed only with the running averages
+        // on; otherwise those of the launch's last step
+        const int fl = stage != 2 ? 0 : (avg ? FLAG_STEP_DONE : 0) | (k + 1 == 3 * n_steps ? FLAG_FIELDS : 0);
+        small_analyze<T>(D, S, fout, lay, LN, fl, w, nwl, nwr, shl, shr, avg);
     }
     if (check) {
         // residual, J-weighted mean P_xy and mass of the final state, as the tiled path's check
@@ -1679,10 +1797,15 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
             const double scale = D.jsum / r[3];
             for (size_t k = tid; k < nst; k += kSmallThreads) S.b0[k] = (T)((double)S.b0[k] * scale);
             __syncthreads();
-            small_analyze<T>(D, S, S.b0, lay, LN, FLAG_FIELDS, red, nwl, nwr, avg);
+            small_walls<T>(D, S, S.b0, w);
+            small_analyze<T>(D, S, S.b0, lay, LN, FLAG_FIELDS, w, nwl, nwr, shl, shr, avg);
         }
     }
     if (tid == 0) {
+        D.dyn[DY_NWL] = nwl;
+        D.dyn[DY_NWR] = nwr;
+        D.dyn[DY_SHEAR_L] = shl;
+        D.dyn[DY_SHEAR_R] = shr;
         D.dyn[DY_STEP] = step0 + (double)n_steps;
         if (avg) D.dyn[DY_AVG_STEPS] += (double)n_steps;
     }
