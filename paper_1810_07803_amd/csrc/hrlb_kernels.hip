@@ -183,13 +183,15 @@ __device__ __forceinline__ float store_round<float>(double x, int stochastic, ui
     return stochastic ? round_stochastic(x, r16) : (float)x;
 }
 
-// the value of x in the partner lane of a DPP pattern within a 16-lane row (both 32-bit halves)
+// the value of x in the partner lane of a DPP pattern within a 16-lane row (both 32-bit halves).  Every
+// pattern used here reads a valid lane of the same row for every lane, so no lane keeps its old value
+// and the moves need none (no register to initialise first).
 template <int CTRL>
 __device__ __forceinline__ double dpp_partner(double x)
 {
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
@@ -1387,7 +1389,12 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
 // path's own (another summation order).
 constexpr int kSmallThreads = 256;
 
-// LDS layout of a small case (bytes from the start of the dynamic LDS)
+// LDS layout of a small case (bytes from the start of the dynamic LDS).  The rows of the state buffers
+// (one distribution of one velocity) are small_row(nx) = nx + 1 elements apart: with an odd stride the
+// rows of neighbouring velocities start on different banks, so that the update's window reads (lanes
+// spread over velocities and strips) and the moment sums (lanes spread over velocities and cells) do
+// not pile onto a few banks.
+__host__ __device__ constexpr int small_row(int nx) { return nx + 1; }
 struct SmallLds {
     size_t buf[3], sc, g, ktab, pm, vel, cel, total;
 };
@@ -1406,7 +1413,7 @@ __host__ __device__ inline SmallLds small_lds(int nx, int nv, int qx, int qy, in
     size_t off = 0;
     for (int k = 0; k < 3; ++k) {
         o.buf[k] = off;
-        off = align16(off + es * 2 * (size_t)nv * nx);
+        off = align16(off + es * 2 * (size_t)nv * small_row(nx));
     }
     o.sc = off;
     off = align16(off + sizeof(double) * kNSc * nx);
@@ -1448,6 +1455,7 @@ __device__ inline void small_block_sum(double (&x)[N], double (*red)[N])
 template <typename T>
 struct SmallPtrs {
     T *b0, *b1, *b2;                        // state buffers: f^n, stage 1 and stage 2 outputs
+    int rs;                                 // their row stride, small_row(nx)
     double* sc;                             // FP64 per-cell scalars [kNSc][nx]
     T* g;                                   // per-cell table [g_slots][nx]
     double* ktab;                           // quadrature tables of eqs. (gx), (gy)
@@ -1473,7 +1481,7 @@ __device__ __forceinline__ void small_walls(const InstDesc& D, const SmallPtrs<T
     for (int v = threadIdx.x & 63; v < 2 * half; v += 64) {
         const bool right = v < half;
         if (!right && D.half) continue;
-        const T* r = f + (size_t)v * nx;
+        const T* r = f + (size_t)v * S.rs;
         const T F = right ? wall_face_right(r[nx - 3], r[nx - 2], r[nx - 1]) : wall_face_left(r[0], r[1], r[2]);
         const double pxv = S.pv[2 * v], pyv = S.pv[2 * v + 1];
         const double a = pxv * (double)F, b = pxv * pyv * (double)F;
@@ -1506,13 +1514,15 @@ __device__ __forceinline__ void small_analyze(const InstDesc& D, const SmallPtrs
         const int s = c0 + tid / LN;
         const bool on = s < nx;
         const int sc_ = on ? s : 0;
-        // raw sums of Sec. II's moments over the velocities v = q, q + LN, ... of the cell
+        // raw sums of Sec. II's moments over the velocities of the cell, lane q taking the block
+        // v = q vb ... q vb + vb - 1 (the rows of a block are consecutive, one bank apart)
         double R[kNMom];
 #pragma unroll
         for (int m = 0; m < kNMom; ++m) R[m] = 0.0;
-        for (int v = q; v < nv; v += LN) {
+        const int vb = (nv + LN - 1) / LN, vend = min(nv, (q + 1) * vb);
+        for (int v = q * vb; v < vend; ++v) {
             const double pxv = S.pv[2 * v], pyv = S.pv[2 * v + 1];
-            const double o = (double)f[(size_t)v * nx + sc_], x = (double)f[(size_t)(nv + v) * nx + sc_];
+            const double o = (double)f[(size_t)v * S.rs + sc_], x = (double)f[(size_t)(nv + v) * S.rs + sc_];
             const double p2 = pxv * pxv + pyv * pyv;
             R[0] += o;
             R[1] += pxv * o;
@@ -1569,7 +1579,7 @@ __device__ __forceinline__ void small_update(const InstDesc& D, const SmallPtrs<
         Win<T> P[2];
 #pragma unroll
         for (int d = 0; d < 2; ++d) {
-            row[d] = (size_t)(d * nv + v) * nx;
+            row[d] = (size_t)(d * nv + v) * S.rs;
             const T* fr = fin + row[d];
             // window cells s0-4 .. s0+7; the tiled path's loads: cells 0..3 for the left window of the
             // strip at cell 0, cells s0..s0+3 for the right window of the last strip (the ghost logic
@@ -1587,7 +1597,7 @@ __device__ __forceinline__ void small_update(const InstDesc& D, const SmallPtrs<
             const int hmir = hi < qx ? hi + qx : hi - qx;
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
-                const T* fm = fin + (size_t)(d * nv + hmir * qy + (qy - 1 - j)) * nx;
+                const T* fm = fin + (size_t)(d * nv + hmir * qy + (qy - 1 - j)) * S.rs;
 #pragma unroll
                 for (int c = 0; c < 4; ++c) P[d].w[3 - c] = fm[c];
             }
@@ -1720,6 +1730,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
     S.b0 = (T*)(lds + L.buf[0]);
     S.b1 = (T*)(lds + L.buf[1]);
     S.b2 = (T*)(lds + L.buf[2]);
+    S.rs = small_row(nx);
     S.sc = (double*)(lds + L.sc);
     S.g = (T*)(lds + L.g);
     S.ktab = (double*)(lds + L.ktab);
@@ -1735,8 +1746,8 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
     const int tid = threadIdx.x;
     // the state, the quadrature tables and the constants into LDS
     const T* f0 = (const T*)D.f[0];
-    const size_t nst = 2 * (size_t)nv * nx;
-    for (size_t k = tid; k < nst; k += kSmallThreads) S.b0[k] = f0[k];
+    const int nst = 2 * nv * nx;  // the state's elements, rows of nx in global memory
+    for (int k = tid; k < nst; k += kSmallThreads) S.b0[(k / nx) * S.rs + k % nx] = f0[k];
     for (int k = tid; k < lay.total; k += kSmallThreads) S.ktab[k] = ktab_source(D, lay, k);
     for (int k = tid; k < 2 * qx; k += kSmallThreads) vel[k] = D.px[k];
     for (int k = tid; k < qy; k += kSmallThreads) vel[2 * qx + k] = D.py[k];
@@ -1795,7 +1806,10 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
         if (D.lts) {
             // local time steps: back to the rest-state mass, then the moments of the rescaled state
             const double scale = D.jsum / r[3];
-            for (size_t k = tid; k < nst; k += kSmallThreads) S.b0[k] = (T)((double)S.b0[k] * scale);
+            for (int k = tid; k < nst; k += kSmallThreads) {
+                T& e = S.b0[(k / nx) * S.rs + k % nx];
+                e = (T)((double)e * scale);
+            }
             __syncthreads();
             small_walls<T>(D, S, S.b0, w);
             small_analyze<T>(D, S, S.b0, lay, LN, FLAG_FIELDS, w, nwl, nwr, shl, shr, avg);
@@ -1810,7 +1824,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
         if (avg) D.dyn[DY_AVG_STEPS] += (double)n_steps;
     }
     T* fo = (T*)D.f[0];
-    for (size_t k = tid; k < nst; k += kSmallThreads) fo[k] = S.b0[k];
+    for (int k = tid; k < nst; k += kSmallThreads) fo[k] = S.b0[(k / nx) * S.rs + k % nx];
 }
 
 // ---- per-instance reductions at a check point: residual, mean P_xy, mass ----------------------
