@@ -266,6 +266,9 @@ Layout make_layout(const hrlb_quad* q, const hrlb_case_params* p)
     L.t_az2 = t; t += kAux2;
     L.t_aw2 = t; t += kAux2;
     L.t_hZ2 = t; t += (size_t)(q->nxo + 1) * kAux2;
+    // the per-cell kernels' LDS image of the quadrature tables (layout of cell_lds with the 24-node rule;
+    // the layout without it is a prefix)
+    L.t_img = t; t += cell_lds(qx, qy, gx_rows(q->nxo), gy_rows(q->nyo), q->nyo, true).total;
     L.t_n = t;
     off = align256(off + sizeof(double) * t);
     L.cell = off;  // FP64 scalars [kNSc][nx], then the storage-precision table [g_slots][nx]
@@ -489,6 +492,24 @@ hrlb_status init_case_in(const hrlb_quad* q, const hrlb_case_params* p, const La
         scaled(q->auxZ2l, q->auxW2l, L.t_az2, L.t_aw2, L.t_hZ2);
     }
     std::copy(q->he.begin(), q->he.end(), tab.begin() + L.t_he);
+    {
+        // the LDS image: every table at its offset of cell_lds, its rows beyond N_x (N_y) zero up to the
+        // padded row counts (the vector starts zeroed)
+        const int nxr = q->nxo + 1, nyr = q->nyo + 1;
+        const CellLds lay = cell_lds(qx, qy, gx_rows(q->nxo), gy_rows(q->nyo), q->nyo, true);
+        double* im = tab.data() + L.t_img;
+        auto put = [&](int at, size_t from, int n) { std::copy(tab.begin() + from, tab.begin() + from + n, im + at); };
+        put(lay.wx, L.t_wx, qx);
+        put(lay.wy, L.t_wy, qy);
+        put(lay.az, L.t_az, kAux);
+        put(lay.aw, L.t_aw, kAux);
+        put(lay.hZ, L.t_hZ, nxr * kAux);
+        put(lay.hz, L.t_hz, nxr * qx);
+        put(lay.he, L.t_he, nyr * qy);
+        put(lay.az2, L.t_az2, kAux2);
+        put(lay.aw2, L.t_aw2, kAux2);
+        put(lay.hZ2, L.t_hZ2, nxr * kAux2);
+    }
     for (int s = 0; s < nx; ++s) {
         tab[L.t_ijd + s] = 1.0 / c->jdeta[s];
         tab[L.t_jd + s] = c->jdeta[s];
@@ -630,6 +651,7 @@ hrlb_status init_case_in(const hrlb_quad* q, const hrlb_case_params* p, const La
     D.auxZ2 = tb + L.t_az2;
     D.auxW2 = tb + L.t_aw2;
     D.hZ2 = tb + L.t_hZ2;
+    D.ktab = tb + L.t_img;
     D.he = tb + L.t_he;
     D.inv_jdeta = tb + L.t_ijd;
     D.jdeta = tb + L.t_jd;

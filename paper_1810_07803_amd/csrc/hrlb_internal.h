@@ -126,6 +126,7 @@ struct InstDesc {
     const double* auxZ2; // [kAux2] the smaller auxiliary rule
     const double* auxW2; // [kAux2]
     const double* hZ2;   // [(nxo+1)][kAux2]
+    const double* ktab;  // [cell_lds(qx, qy, nxb, nyb, nyo, true).total] the per-cell kernels' LDS table image
     const double* he;    // [(nyo+1)][qy]   probabilists' Hermite polynomials at the y nodes
     const double* inv_jdeta; // [nx]
     const double* jdeta;     // [nx]

@@ -935,36 +935,6 @@ __device__ void wall_sums(const InstDesc& D, const T* f, bool right, double& flu
     __syncthreads();  // red may be reused by a second call in the same block
 }
 
-// entry k of the per-cell kernel's LDS table copy (layout of cell_lds): the value from the tables of
-// the instance, 0 in the padding rows and beyond the end
-__device__ __forceinline__ double ktab_source(const InstDesc& D, const CellLds& lay, int k)
-{
-    const double* src;
-    int r, lim;
-    if (k < lay.wy) {
-        src = D.wx; r = k - lay.wx; lim = D.qx;
-    } else if (k < lay.az) {
-        src = D.wy; r = k - lay.wy; lim = D.qy;
-    } else if (k < lay.aw) {
-        src = D.auxZ; r = k - lay.az; lim = kAux;
-    } else if (k < lay.hZ) {
-        src = D.auxW; r = k - lay.aw; lim = kAux;
-    } else if (k < lay.hz) {
-        src = D.hZ; r = k - lay.hZ; lim = (D.nxo + 1) * kAux;
-    } else if (k < lay.he) {
-        src = D.hz; r = k - lay.hz; lim = (D.nxo + 1) * D.qx;
-    } else if (k < lay.az2) {
-        src = D.he; r = k - lay.he; lim = (D.nyo + 1) * D.qy;
-    } else if (k < lay.aw2) {
-        src = D.auxZ2; r = k - lay.az2; lim = kAux2;
-    } else if (k < lay.hZ2) {
-        src = D.auxW2; r = k - lay.aw2; lim = kAux2;
-    } else {
-        src = D.hZ2; r = k - lay.hZ2; lim = k < lay.total ? (D.nxo + 1) * kAux2 : 0;
-    }
-    return r < lim ? src[r] : 0.0;
-}
-
 // the left wall of the current state (eq. diffuse_nw: n_w and the momentum flux; none in the half
 // channel), and the count of a completed step; block-wide
 template <typename T>
@@ -1176,11 +1146,11 @@ __device__ __forceinline__ void gy_nodes_long(int q, int LN, int nyo, double uy,
 // (tables in LDS, same layout).
 // SMALLB: only the unrolled buckets of expansion orders up to N_x = 10, N_y = 11 (the small-case path
 // admits no others), which keeps its register use down.  avg: whether the running averages are on
-// (-1: read it from the dynamic scalars)
+// (read by the caller)
 template <typename T, bool SMALLB = false>
 __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom], int q, int LN, int s, bool on,
                                             int flags, double* sc, T* cell, const double* ktab, const CellLds& lay,
-                                            int avg = -1)
+                                            int avg)
 {
     const int nx = D.nx;
     const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
@@ -1265,7 +1235,7 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
         // the band in which the projection of eq. (gx) is verified (a finite state outside it is
         // flagged; non-finite values are caught by the residual check)
         if (Tm < D.band_tlo || Tm > D.band_thi || fabs(ux) > D.band_u) gmem(D.dyn)[DY_RANGE] = 1.0;
-        if ((flags & FLAG_STEP_DONE) && (avg < 0 ? D.dyn[DY_AVG_ON] != 0.0 : avg != 0)) {
+        if ((flags & FLAG_STEP_DONE) && avg) {
             // running sums of the fields at the end of every step (time averages, hrlb_average_*)
             const gptr<double> A = gmem(D.avg);
             A[F_N * nx + s] += n;
@@ -1335,6 +1305,8 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
     const int s = cr.cell0 + threadIdx.x / LN;
     const bool on = s < nx;
     const int sc = on ? s : 0;
+    // whether the running averages are on (read only at the end of a step), issued with the loads below
+    const int avg = (flags & FLAG_STEP_DONE) ? (D.dyn[DY_AVG_ON] != 0.0) : 0;
 
     // moment partials of this cell: lane q sums the velocity groups g = q, q + L, ... (issued before
     // the table staging so that their latency overlaps it)
@@ -1345,16 +1317,20 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
 #pragma unroll
         for (int m = 0; m < kNMom; ++m) R[m] += D.mom_part[((size_t)g * kNMom + m) * nx + sc];
 
-    // quadrature tables in LDS, rows of h and He padded with zeros to the unrolled counts: every
-    // thread issues up to 8 loads before its first LDS write, so the copy takes one memory round
-    // trip (up to 2048 doubles: every velocity set up to Qx = 80, Nx = 10) instead of one per table
-    // row block
+    // quadrature tables in LDS, rows of h and He padded with zeros to the unrolled counts: a contiguous
+    // copy of the case's image of them (the plan's layout is a prefix of it); every thread issues up
+    // to 8 loads before its first LDS write, so the copy takes one memory round trip (up to 2048
+    // doubles: every velocity set up to Qx = 80, Nx = 10)
     const CellLds lay = cell_lds(D.qx, D.qy, D.nxb, D.nyb, D.nyo, uses_aux2(D.cell_lanes));
+    const gptr<const double> img = gmem(D.ktab);
     constexpr int kStageBatch = 8;
     for (int base = 0; base < lay.total; base += kStageBatch * kCellThreads) {
         double v[kStageBatch];
 #pragma unroll
-        for (int u = 0; u < kStageBatch; ++u) v[u] = ktab_source(D, lay, base + u * kCellThreads + (int)threadIdx.x);
+        for (int u = 0; u < kStageBatch; ++u) {
+            const int k = base + u * kCellThreads + (int)threadIdx.x;
+            v[u] = k < lay.total ? img[k] : 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < kStageBatch; ++u) {
             const int k = base + u * kCellThreads + (int)threadIdx.x;
@@ -1370,7 +1346,7 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
         if (cr.cell0 + kCellThreads / LN >= nx) wall_right<T>(D, fcur);
     }
 
-    cell_tables<T>(D, R, q, LN, s, on, flags, D.sc, (T*)D.cell, ktab, lay);
+    cell_tables<T>(D, R, q, LN, s, on, flags, D.sc, (T*)D.cell, ktab, lay, avg);
 }
 
 // ---- small-case kernel ---------------------------------------------------------------------------
@@ -1748,7 +1724,7 @@ __global__ __launch_bounds__(kSmallThreads) void small_kernel(const InstDesc* __
     const T* f0 = (const T*)D.f[0];
     const int nst = 2 * nv * nx;  // the state's elements, rows of nx in global memory
     for (int k = tid; k < nst; k += kSmallThreads) S.b0[(k / nx) * S.rs + k % nx] = f0[k];
-    for (int k = tid; k < lay.total; k += kSmallThreads) S.ktab[k] = ktab_source(D, lay, k);
+    for (int k = tid; k < lay.total; k += kSmallThreads) S.ktab[k] = D.ktab[k];
     for (int k = tid; k < 2 * qx; k += kSmallThreads) vel[k] = D.px[k];
     for (int k = tid; k < qy; k += kSmallThreads) vel[2 * qx + k] = D.py[k];
     for (int k = tid; k < nv; k += kSmallThreads) {

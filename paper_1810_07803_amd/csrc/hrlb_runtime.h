@@ -126,7 +126,7 @@ struct Layout {
     size_t total;  // aux_total + state_total: one workspace holding both regions
     // table offsets in doubles relative to `tables`
     size_t t_px, t_py, t_wx, t_wy, t_hz, t_az, t_aw, t_hZ, t_he, t_ijd, t_jd, t_gwl, t_gwr, t_g0, t_vT, t_vMu, t_vOm,
-        t_vPr, t_dts, t_jres, t_az2, t_aw2, t_hZ2, t_n;
+        t_vPr, t_dts, t_jres, t_az2, t_aw2, t_hZ2, t_img, t_n;
     int ngroups, nctiles, vpt, ncellblocks, cell_lanes;
     int ntile_list;  // records in the case's tile list (XCD-aware order, padded)
 };
