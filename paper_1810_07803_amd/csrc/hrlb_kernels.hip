@@ -1391,17 +1391,17 @@ __global__ __launch_bounds__(kCellThreads) __attribute__((amdgpu_waves_per_eu(4)
 // ---- small-case kernel ---------------------------------------------------------------------------
 // One workgroup holds one small case in LDS -- its three state buffers, the per-cell tables of the
 // collision, the quadrature tables of eqs. (gx), (gy) and every per-velocity and per-cell constant --
-// and runs n_steps full SSP-RK3 steps in one launch.  Per stage: the wall densities of eq.
-// (diffuse_nw) (both walls in one reduction) and the moments of the stage input (FP64 sums over every
-// velocity of a cell, split over the cell's lanes), the per-cell tables (cell_tables, as in the
-// per-cell kernel), then the update of every (distribution, velocity, 4-cell strip): WENO-5 faces
-// with the wall and mirror ghosts of the tiled path, the FP64 Shakhov collision and the FP64 stage
-// combine.  For cases of a few thousand cell-velocity units, whose tiled steps (six launches) are
-// bound by launch latency; with one block per case, its latency is what remains, so nothing it reads
-// inside the step loop comes from global memory.  The step counter, the fields of the final state, the
-// running averages, the wall densities and, at a checked last step, the residual, the mean P_xy, the
-// mass and the local-time-step rescaling are kept as the tiled path keeps them; the numbers are this
-// path's own (another summation order).
+// and runs n_steps full SSP-RK3 steps in one launch.  Per stage: the update of every (velocity, 4-cell
+// strip) for both distributions (WENO-5 faces with the wall and mirror ghosts of the tiled path, the
+// FP64 Shakhov collision and the FP64 stage combine), which also forms the leaving wall fluxes of
+// eq. (diffuse_nw) from the values it stores; then the wall densities, the moments of the new state
+// (FP64 sums over every velocity of a cell, split over the cell's lanes) and the per-cell tables
+// (cell_tables, as in the per-cell kernel).  For cases of a few thousand cell-velocity units, whose
+// tiled steps (six launches) are bound by launch latency; with one block per case, its latency is
+// what remains, so nothing it reads inside the step loop comes from global memory.  The step counter,
+// the fields of the final state, the running averages, the wall densities and, at a checked last
+// step, the residual, the mean P_xy, the mass and the local-time-step rescaling are kept as the tiled
+// path keeps them; the numbers are this path's own (another summation order).
 constexpr int kSmallThreads = 256;
 
 // LDS layout of a small case (bytes from the start of the dynamic LDS).  The rows of the state buffers
