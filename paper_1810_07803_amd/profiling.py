@@ -23,7 +23,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/hrlb_kernels.hip", "csrc/hrlb_internal.h", "csrc/hrlb_plan.h", "csrc/hrlb_host.cpp")
+KERNEL_SOURCES = ("csrc/hrlb_kernels.hip", "csrc/hrlb_internal.h", "csrc/hrlb_math.h", "csrc/hrlb_plan.h", "csrc/hrlb_host.cpp")
 
 
 _TOKENS = re.compile(r'"(?:\\.|[^"\\])*"|(?:\s|//[^\n]*|/\*.*?\*/)+', re.S)
