@@ -1371,7 +1371,23 @@ hrlb_status batch_build_parts(hrlb_batch* b, int nparts, bool all_tiled = false)
             cpb[q] = kCellThreads / c->L.cell_lanes;
             own[q] = wall_blocks_of_their_own(c->q->qx, c->q->qy);
         }
-        const std::vector<CellRef> cells = plan_cell_blocks(ncell, cpb, own);
+        std::vector<CellRef> cells = plan_cell_blocks(ncell, cpb, own);
+        {
+            // per-cell work of an instance: the projection of eq. (gx) and its 2 Q_x output nodes
+            // scale with (N_x + 1) (Q_x + 8), plus the moment shift and tau
+            std::vector<double> w(nt);
+            for (int q = 0; q < nt; ++q) {
+                const hrlb_case* c = cases[P.idx[q]];
+                w[q] = (double)(c->q->nxo + 1) * (c->q->qx + 8) + 40.0;
+            }
+            size_t first = 0;
+            while (first < cells.size() && cells[first].cell0 < 0) ++first;
+            int ncu = 0, dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+                ncu = 0;  // keep the plain order
+            balance_cell_blocks(cells, first, w, ncu);
+        }
         const std::vector<TileRef> tiles = part_tiles(cases, std::vector<int>(P.idx.begin(), P.idx.begin() + nt));
         if ((int)tiles.size() != P.ntiles || (int)cells.size() != P.ncellblocks ||
             !tiles_valid(tiles, (size_t)P.ntiles, nt, nct.data(), ngr.data()))

