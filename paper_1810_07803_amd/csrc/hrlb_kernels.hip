@@ -1016,7 +1016,7 @@ __device__ __forceinline__ void lane_sums(double (&x)[N], double (&y)[M > 0 ? M 
 // The rule is scaled to T_w (nodes Z of the weight exp(-p^2/(2 T_w))), on which the integrand is
 // exp(Z^2 (T/T_w - 1)/(2T) + Z u/T - u^2/(2T))/sqrt(T) h_l(Z).
 template <int NB>
-__device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, double Tw, double ux, int K,
+__device__ __forceinline__ void gx_project(int q, int LN, double Tm, double Tw, double ux, int K,
                                            const double* s_az, const double* s_aw, const double* s_hZ,
                                            double (&Ip)[NB], double (&Im)[NB])
 {
@@ -1082,16 +1082,16 @@ __device__ __forceinline__ void gx_project(int q, int LN, int nxo, double Tm, do
 // (pairs on 8 of them, single nodes on the others: both paths in every wave, no faster than the
 // 48-node split), so such plans keep the 48-node rule.
 template <typename T, int NB, typename CP>
-__device__ __forceinline__ void gx_nodes(int q, int LN, int nxo, double n, double Tm, double Tw, double ux, bool small, bool on,
+__device__ __forceinline__ void gx_nodes(int q, int LN, double n, double Tm, double Tw, double ux, bool small, bool on,
                                          int s, int nx, int qxn, const double* s_wx, const double* s_az,
                                          const double* s_aw, const double* s_hZ, const double* s_az2,
                                          const double* s_hz, CP cell)
 {
     double Ip[NB], Im[NB];
     if (small)
-        gx_project<NB>(q, LN, nxo, Tm, Tw, ux, kAux2, s_az2, s_az2 + kAux2, s_az2 + 2 * kAux2, Ip, Im);
+        gx_project<NB>(q, LN, Tm, Tw, ux, kAux2, s_az2, s_az2 + kAux2, s_az2 + 2 * kAux2, Ip, Im);
     else
-        gx_project<NB>(q, LN, nxo, Tm, Tw, ux, kAux, s_az, s_aw, s_hZ, Ip, Im);
+        gx_project<NB>(q, LN, Tm, Tw, ux, kAux, s_az, s_aw, s_hZ, Ip, Im);
     for (int i = q; i < qxn; i += LN) {
         double ap = 0.0, am = 0.0;
 #pragma unroll
@@ -1163,7 +1163,7 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
                                             int avg)
 {
     const int nx = D.nx;
-    const int qxn = D.qx, nqy = D.qy, nxo = D.nxo, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
+    const int qxn = D.qx, nqy = D.qy, nyo = D.nyo, nxb = D.nxb, nyb = D.nyb;
     const double* s_wx = ktab + lay.wx;
     const double* s_wy = ktab + lay.wy;
     const double* s_az = ktab + lay.az;
@@ -1266,12 +1266,12 @@ __device__ __forceinline__ void cell_tables(const InstDesc& D, double (&R)[kNMom
     // as accurate as the 48-node one (the same choice in every lane of a cell)
     const bool use2 = uses_aux2(LN) && Tm >= D.aux2_tlo && Tm <= D.aux2_thi && fabs(ux) <= D.aux2_u;
     switch (nxb) {
-        case 4: gx_nodes<T, 4>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
-        case 8: gx_nodes<T, 8>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
-        case 11: gx_nodes<T, 11>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
+        case 4: gx_nodes<T, 4>(q, LN, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
+        case 8: gx_nodes<T, 8>(q, LN, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
+        case 11: gx_nodes<T, 11>(q, LN, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp); break;
         default:
             if constexpr (!SMALLB)
-                gx_nodes<T, 17>(q, LN, nxo, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp);
+                gx_nodes<T, 17>(q, LN, n, Tm, D.Tw, ux, use2, on, s, nx, qxn, s_wx, s_az, s_aw, s_hZ, s_az2, s_hz, cellp);
             break;
     }
     if constexpr (SMALLB) {
@@ -1851,7 +1851,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restric
     red[threadIdx.x][3] = d;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             for (int q = 0; q < 4; ++q) red[threadIdx.x][q] += red[threadIdx.x + w][q];
         __syncthreads();
     }
