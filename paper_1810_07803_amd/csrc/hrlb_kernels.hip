@@ -1077,10 +1077,10 @@ __device__ __forceinline__ void gx_project(int q, int LN, double Tm, double Tw, 
     lane_sums<NB, NB>(Ip, Im, LN);
 }
 
-// g_x at the 2 Q_x nodes from the projections: n w_i sum_l I_l h_l(z_i); small: the 24-node auxiliary
-// rule (ktab at s_az2), else the 48-node one.  With 16 lanes per cell the 24 nodes would split unevenly over the lanes
-// (pairs on 8 of them, single nodes on the others: both paths in every wave, no faster than the
-// 48-node split), so such plans keep the 48-node rule.
+// g_x at the 2 Q_x nodes from the projections: n w_i sum_l I_l h_l(z_i); small: the 24-node
+// auxiliary rule (ktab at s_az2), else the 48-node one.  With 16 lanes per cell the 24 nodes would
+// split unevenly over the lanes (pairs on 8 of them, single nodes on the others: both paths in every
+// wave, no faster than the 48-node split), so such plans keep the 48-node rule.
 template <typename T, int NB, typename CP>
 __device__ __forceinline__ void gx_nodes(int q, int LN, double n, double Tm, double Tw, double ux, bool small, bool on,
                                          int s, int nx, int qxn, const double* s_wx, const double* s_az,
