@@ -131,8 +131,9 @@ typedef struct {
     double local_dt_cap;
     /* Kernels that advance the case.  HRLB_PATH_TILED: two launches per Runge-Kutta stage over tiles of
      * 64 cells x 16 velocity rows (every case, any size).  HRLB_PATH_SMALL: one launch per block of steps
-     * in which one workgroup holds the whole case (populations, stage buffers, tables) in 64 KB of LDS,
-     * for cases of a few thousand cell-velocity units whose tiled steps are bound by launch latency;
+     * in which one workgroup holds the whole case (populations, stage buffers, tables) in its LDS (as
+     * much as the device gives a workgroup: 160 KB on MI355X), for cases of a few thousand cell-velocity
+     * units whose tiled steps are bound by launch latency;
      * HRLB_E_INVALID if the case does not fit.  HRLB_PATH_AUTO (0): the small path when the case fits.
      * The two paths sum the moments in different orders; a case takes its path alone and in any batch,
      * so it keeps its bits there. */

@@ -196,8 +196,6 @@ hrlb_status validate(const hrlb_quad* q, const hrlb_case_params* p)
     return HRLB_OK;
 }
 
-// LDS of one small-case block at most: two such blocks fit a CU beside other launches' blocks
-constexpr size_t kSmallLdsMax = size_t(64) << 10;
 
 // velocities per row: the requested divisor, or the largest divisor of qy not above 8 that still
 // fills the 16 rows of a group
@@ -676,14 +674,17 @@ hrlb_status init_case_in(const hrlb_quad* q, const hrlb_case_params* p, const La
     }
     c->ntiles = (int)tiles.size();
     // the small-case kernel when the case fits its LDS (kernel_path)
+    // the small path holds a case in one workgroup's LDS: up to what the device gives a workgroup (160 KB
+    // on MI355X; the kernel's registers keep it at one block per compute unit whatever its LDS)
     c->small_lds = hrlbk_small_lds(&D);
-    const bool fits = c->small_lds <= kSmallLdsMax && D.nxb <= 11 && D.nyb != 0 && D.nyb <= 12;
+    const size_t small_max = hrlbk_small_lds_max();
+    const bool fits = c->small_lds <= small_max && D.nxb <= 11 && D.nyb != 0 && D.nyb <= 12;
     if (p->kernel_path == HRLB_PATH_SMALL && !fits) {
         const size_t need = c->small_lds;
         delete c;
         return fail(HRLB_E_INVALID,
                     "the small path takes cases of at most %zu bytes of LDS (this one: %zu) and expansion orders "
-                    "N_x <= 10, N_y <= 11", kSmallLdsMax, need);
+                    "N_x <= 10, N_y <= 11", small_max, need);
     }
     c->small = p->kernel_path == HRLB_PATH_SMALL || (p->kernel_path == HRLB_PATH_AUTO && fits);
     c->run.fp32 = p->precision == HRLB_FP32_STORE_FP64_MOM;

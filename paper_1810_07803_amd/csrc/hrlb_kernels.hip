@@ -2019,6 +2019,35 @@ extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_small_lds(const In
 }
 
 // n_steps steps of every small instance of descs (one block each); check: the last step is checked
+// dynamic LDS a small-case block may take on the current device: the device's LDS per workgroup less
+// the kernel's static LDS (160 KB less a few hundred bytes on MI355X); both kernel variants are
+// allowed that much once per device.  0 if the device cannot be queried.
+extern "C" __attribute__((visibility("hidden"))) size_t hrlbk_small_lds_max()
+{
+    static std::mutex mu;
+    static std::map<int, size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int per_block = 0;
+    hipFuncAttributes fa32{}, fa64{};
+    if (hipDeviceGetAttribute(&per_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipFuncGetAttributes(&fa32, (const void*)small_kernel<float>) != hipSuccess ||
+        hipFuncGetAttributes(&fa64, (const void*)small_kernel<double>) != hipSuccess)
+        return 0;
+    const size_t stat = std::max(fa32.sharedSizeBytes, fa64.sharedSizeBytes);
+    size_t lim = per_block > 0 && (size_t)per_block > stat ? (size_t)per_block - stat : 0;
+    if (hipFuncSetAttribute((const void*)small_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+            hipSuccess ||
+        hipFuncSetAttribute((const void*)small_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+            hipSuccess)
+        lim = std::min(lim, size_t(64) << 10);  // keep to the default limit if the opt-in is refused
+    cache.emplace(dev, lim);
+    return lim;
+}
+
 extern "C" __attribute__((visibility("hidden"))) hipError_t hrlbk_small(int fp32, const InstDesc* descs, int ninst,
                                                                           int n_steps, int check, size_t lds,
                                                                           hipStream_t st)

@@ -23,6 +23,7 @@ extern "C" hipError_t hrlbk_init(int fp32, const hrlb::InstDesc* descs, int inst
 extern "C" hipError_t hrlbk_average(const hrlb::InstDesc* desc, int start, int nx, hipStream_t st);
 extern "C" hipError_t hrlbk_scratch(void** ptr, size_t* bytes);
 extern "C" size_t hrlbk_small_lds(const hrlb::InstDesc* D);
+extern "C" size_t hrlbk_small_lds_max();
 extern "C" hipError_t hrlbk_small(int fp32, const hrlb::InstDesc* descs, int ninst, int n_steps, int check, size_t lds,
                                   hipStream_t st);
 

@@ -127,6 +127,39 @@ def test_small_path_several_items_per_thread(rounding, half):
     assert info.residual == pytest.approx(res, rel=FP32_TOL)
 
 
+@pytest.mark.parametrize("precision,rounding,nx,tol", [(0, 0, 64, FP64_TOL), (1, 1, 128, FP32_TOL)])
+def test_small_path_beyond_64_kib_of_lds(precision, rounding, nx, tol):
+    # Q4x4 with 64 cells in FP64 or 128 in FP32 needs about 125 KB of LDS: the automatic choice takes
+    # the small path as long as the device gives a workgroup that much (160 KB on MI355X)
+    import time
+
+    import torch
+
+    from paper_1810_07803_amd import hrlb
+
+    say(f"[small] Q4x4 nx{nx} precision={precision}: more than 64 KB of LDS")
+    c, orc = _oracle_pair(4, 4, nx, precision=precision, rounding=rounding, path=hrlb.HRLB_PATH_AUTO, delta=0.5,
+                          uw=0.3, omega=0.7, stretch_A=0.9)
+    assert c.kernel_path() == hrlb.HRLB_PATH_SMALL
+    phi, chi = orc.init_state()
+    phi, chi = perturb(phi, 0.05, 99), perturb(chi, 0.05, 100)
+    c.set_state(np.stack([phi, chi]))
+    c.step(20)
+    orc.step(phi, chi, 20)
+    assert parity(c.get_state(), phi, chi, c.moments()[0], orc.moments(phi, chi), tol)
+    # time per step against the tiled path (reported, not asserted)
+    t = {}
+    for path in (hrlb.HRLB_PATH_SMALL, hrlb.HRLB_PATH_TILED):
+        k = _case(hrlb, 4, 4, nx, path, precision=precision, rounding=rounding, delta=0.5, uw=0.3, stretch_A=0.9)
+        k.step(100)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k.step(1000)
+        torch.cuda.synchronize()
+        t[path] = (time.perf_counter() - t0) / 1000 * 1e6
+    say(f"   us per step: small {t[hrlb.HRLB_PATH_SMALL]:.1f}, tiled {t[hrlb.HRLB_PATH_TILED]:.1f}")
+
+
 def test_small_and_tiled_paths_agree():
     from paper_1810_07803_amd import hrlb
 
